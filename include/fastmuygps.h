@@ -1,0 +1,172 @@
+/*
+ * fastmuygps.h -- C ABI of the MI355X (gfx950) FastMuyGPs posterior-mean library.
+ *
+ * Method: Dunton, Priest, Muyskens, "Fast Gaussian Process Posterior Mean
+ * Prediction via Local Cross Validation and Precomputation", arXiv 2205.10879.
+ *   offline (Algorithm 2, training loop; Section 3, coefficient equation):
+ *       N(i) = k nearest training points of x_i other than i (leave-one-out),
+ *       C[i] = (K(X_N(i), X_N(i)) + sigma^2 I)^{-1} Y(X_N(i));
+ *   online (Algorithm 2, prediction loop; Section 3, prediction equation):
+ *       j = nearest training point of z,
+ *       mu(z) = K(z, X_N(j)) . C[j].
+ * Kernels: Matern (Section 2, Matern equation) at nu in {1/2, 3/2, 5/2}, and
+ * the RBF limit nu -> infinity.
+ *
+ * Conventions for every call:
+ *   - all arrays are row-major; all sizes are element counts;
+ *   - "device pointer" means memory of the current HIP device; "host pointer"
+ *     means ordinary process memory;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the legacy default
+ *     stream); work is enqueued on it;
+ *   - no call throws; every call returns an fmg_status and, on failure,
+ *     leaves a message for fastmuygps_last_error() (thread-local);
+ *   - indices are int32, so n <= 2^31 - 1.
+ */
+#ifndef FASTMUYGPS_H
+#define FASTMUYGPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FMG_OK = 0,
+    FMG_E_INVALID_ARG = 1, /* bad size, null pointer, unsupported kernel, non-finite input */
+    FMG_E_OOM = 2,         /* device allocation failed */
+    FMG_E_NOT_PD = 3,      /* build finished but some neighbourhood matrices were not
+                              positive definite; their C rows are NaN (count in fmg_info) */
+    FMG_E_DEVICE = 4,      /* a HIP runtime call failed */
+    FMG_E_BUSY = 5,        /* server admission: request queued, not yet admitted */
+    FMG_E_UNSUPPORTED = 6  /* valid request outside what this build implements (e.g. d too
+                              large for the chosen precision) */
+} fmg_status;
+
+/* Arithmetic of the path.
+ *   FP64 : X, Y, Z, C and means in double; exact FP64 neighbour search;
+ *          FP64 assembly and Cholesky.
+ *   FP32 : X, Y, Z, C and means in float; FP32 MFMA distance screen over
+ *          k + 8 candidates, FP64 re-rank with an exactness certificate
+ *          (rows that fail are rescanned in FP64); FP32 assembly and Cholesky.
+ *   MIXED: as FP32, but the screen is BF16 MFMA with FP32 accumulation over
+ *          2k candidates, and each coefficient row gets one step of iterative
+ *          refinement with an FP64 residual.
+ * In every mode the neighbour lists equal those of an exact FP64 search
+ * (ties to the smaller index). */
+typedef enum { FMG_PREC_FP64 = 0, FMG_PREC_FP32 = 1, FMG_PREC_MIXED = 2 } fmg_precision;
+
+typedef enum { FMG_KERNEL_RBF = 0, FMG_KERNEL_MATERN = 1 } fmg_kernel;
+
+/* Hyperparameters (Section 2, Matern equation, with the nugget added by
+ * index on the training diagonal only):
+ *   K(x, x') = amplitude * phi(||x - x'|| / length_scale),   x != x' by index,
+ *   K(x_a, x_a) = amplitude + noise_var.
+ * nu is read only for FMG_KERNEL_MATERN and must be 0.5, 1.5 or 2.5.
+ * amplitude <= 0 is read as 1. */
+typedef struct {
+    int32_t kernel;       /* fmg_kernel */
+    double nu;
+    double length_scale;  /* > 0 */
+    double noise_var;     /* >= 0 */
+    double amplitude;
+} fmg_hyper;
+
+/* Build flags. */
+#define FMG_FLAG_SELF_INCLUSIVE 0x1u /* paper-literal S_i = [i ; k-1 nearest others]
+                                        (Algorithm 2) instead of leave-one-out */
+#define FMG_FLAG_NO_CENTER 0x2u      /* screening uses X as given instead of X - mean(X) */
+#define FMG_FLAG_NO_REFINE 0x4u      /* MIXED: skip the FP64-residual refinement */
+#define FMG_FLAG_TIMING 0x8u         /* record per-phase HIP-event timings (build and the
+                                        most recent predict); makes predict on this
+                                        model unsafe to call from several threads */
+
+typedef struct fmg_model fmg_model;
+
+typedef struct {
+    int64_t n;
+    int32_t d, ell, k;
+    int32_t precision;        /* fmg_precision */
+    int32_t screen_cands;     /* candidates kept per training row by the screen (c) */
+    int32_t query_cands;      /* candidates kept per query by the screen (c') */
+    int64_t nonpd_rows;       /* rows whose neighbourhood matrix was not PD */
+    int64_t build_fallback_rows; /* training rows rescanned exactly after the certificate */
+    int64_t predict_fallback_rows; /* queries rescanned exactly, summed over all predicts
+                                      (reading it synchronises the device) */
+    uint64_t device_bytes;    /* device memory held by the model */
+} fmg_info;
+
+/* Per-phase times in milliseconds from HIP events (FMG_FLAG_TIMING). */
+typedef struct {
+    double build_prep_ms, build_screen_ms, build_rerank_ms, build_fallback_ms,
+        build_precompute_ms, build_total_ms;
+    double predict_prep_ms, predict_screen_ms, predict_rerank_ms, predict_fallback_ms,
+        predict_gather_ms, predict_total_ms;
+} fmg_timings;
+
+/* Offline training: neighbour lists and coefficient rows (Algorithm 2,
+ * training loop; Section 3, coefficient equation).
+ *   X   : device pointer, [n, d], double for FP64, float otherwise.
+ *   Y   : device pointer, [n, ell], same dtype as X.
+ *   n   : training points, 2 <= n < 2^31 (LOO needs 1 <= k <= n-1,
+ *         SELF needs 1 <= k <= n).
+ *   d   : 1 <= d <= 64 (FP32), 61 (MIXED), any (FP64).
+ *   ell : responses per point, 1 <= ell <= 16.
+ *   k   : neighbours, 1 <= k <= 64.
+ * X and Y are only read during the call; the model keeps its own copies of
+ * what prediction needs (X, the neighbour lists N [n,k] and C [n,k,ell]).
+ * The call returns when the model is complete (it synchronises `stream`).
+ * Errors: FMG_E_INVALID_ARG (sizes, null pointers, length_scale <= 0,
+ * noise_var < 0, nu not supported, non-finite X or Y), FMG_E_UNSUPPORTED,
+ * FMG_E_OOM, FMG_E_DEVICE.  FMG_E_NOT_PD still returns a usable model in
+ * *out (the affected C rows are NaN). */
+fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, int32_t ell,
+                            int32_t k, const fmg_hyper *hyper, fmg_precision prec,
+                            uint32_t flags, void *stream, fmg_model **out);
+
+/* Online prediction (Algorithm 2, prediction loop; Section 3, prediction
+ * equation): nearest training point j of every query, then
+ * mu(z) = K(z, X_N(j)) . C[j].
+ *   Z      : device pointer, [m, d], dtype of the model's X.
+ *   out    : device pointer, [m, ell], dtype of the model's X.
+ *   nn_out : optional device pointer, [m] int32, receives j (NULL to skip).
+ *   m = 0 is a no-op.  Asynchronous on `stream`; scratch memory is
+ *   allocated stream-ordered and released on the same stream.  The model is
+ *   not modified (unless built with FMG_FLAG_TIMING), so predictions on
+ *   several streams may run concurrently.
+ * Errors: FMG_E_INVALID_ARG (null model or pointer, m < 0), FMG_E_OOM,
+ * FMG_E_DEVICE. */
+fmg_status fastmuygps_predict(const fmg_model *model, const void *Z, int64_t m, void *out,
+                              int32_t *nn_out, void *stream);
+
+/* Model metadata (host struct).  Synchronises the device. */
+fmg_status fastmuygps_info(const fmg_model *model, fmg_info *info);
+
+/* Copy the neighbour lists N [n, k] int32 (ascending distance) into the
+ * caller's device buffer. */
+fmg_status fastmuygps_neighbors(const fmg_model *model, int32_t *dev_out, void *stream);
+
+/* Copy the coefficients C [n, k, ell] (model dtype) into the caller's
+ * device buffer. */
+fmg_status fastmuygps_coeffs(const fmg_model *model, void *dev_out, void *stream);
+
+/* HIP-event phase timings of the build and of the latest predict
+ * (FMG_FLAG_TIMING models only; FMG_E_INVALID_ARG otherwise). */
+fmg_status fastmuygps_timings(const fmg_model *model, fmg_timings *t);
+
+/* Release the model and all its device memory.  NULL is a no-op. */
+void fastmuygps_free(fmg_model *model);
+
+/* Message of the last failed call on this thread ("" if none).  The string
+ * is owned by the library and valid until the next call on this thread. */
+const char *fastmuygps_last_error(void);
+
+/* Library version string, e.g. "fastmuygps-gfx950 0.1". */
+const char *fastmuygps_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTMUYGPS_H */

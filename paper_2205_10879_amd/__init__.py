@@ -1,0 +1,245 @@
+"""FastMuyGPs posterior-mean path for MI355X (gfx950): Python binding.
+
+Thin ctypes marshalling over the C ABI in include/fastmuygps.h (same names:
+``fastmuygps_build``, ``fastmuygps_predict``, ...).  Every step of the path
+runs in the HIP library ``libfastmuygps.so``; torch is used only for device
+memory and streams.  The first call raises when the library has not been
+built (``python -m paper_2205_10879_amd.build``); there is no fallback.
+
+Method: Dunton, Priest, Muyskens, arXiv 2205.10879, Algorithm 2.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfastmuygps.so")
+
+FMG_OK = 0
+FMG_E_INVALID_ARG = 1
+FMG_E_OOM = 2
+FMG_E_NOT_PD = 3
+FMG_E_DEVICE = 4
+FMG_E_BUSY = 5
+FMG_E_UNSUPPORTED = 6
+
+PREC_FP64 = 0
+PREC_FP32 = 1
+PREC_MIXED = 2
+PRECISIONS = {"fp64": PREC_FP64, "fp32": PREC_FP32, "mixed": PREC_MIXED}
+
+KERNEL_RBF = 0
+KERNEL_MATERN = 1
+
+FLAG_SELF_INCLUSIVE = 0x1
+FLAG_NO_CENTER = 0x2
+FLAG_NO_REFINE = 0x4
+FLAG_TIMING = 0x8
+
+# Public C entry points (checked by the CPU tests against include/fastmuygps.h).
+EXPORTS = ("fastmuygps_build", "fastmuygps_predict", "fastmuygps_info", "fastmuygps_neighbors",
+           "fastmuygps_coeffs", "fastmuygps_timings", "fastmuygps_free", "fastmuygps_last_error",
+           "fastmuygps_version")
+
+
+class FmgHyper(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("nu", ctypes.c_double),
+                ("length_scale", ctypes.c_double), ("noise_var", ctypes.c_double),
+                ("amplitude", ctypes.c_double)]
+
+
+class FmgInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("ell", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("screen_cands", ctypes.c_int32), ("query_cands", ctypes.c_int32),
+                ("nonpd_rows", ctypes.c_int64), ("build_fallback_rows", ctypes.c_int64),
+                ("predict_fallback_rows", ctypes.c_int64), ("device_bytes", ctypes.c_uint64)]
+
+
+class FmgTimings(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_double) for name in (
+        "build_prep_ms", "build_screen_ms", "build_rerank_ms", "build_fallback_ms",
+        "build_precompute_ms", "build_total_ms", "predict_prep_ms", "predict_screen_ms",
+        "predict_rerank_ms", "predict_fallback_ms", "predict_gather_ms", "predict_total_ms")]
+
+
+class FmgError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("fastmuygps status %d: %s" % (status, message))
+        self.status = status
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    if not os.path.exists(path):
+        raise ImportError("FastMuyGPs HIP library not built: %s is missing "
+                          "(run `python -m paper_2205_10879_amd.build`)" % path)
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.fastmuygps_build.argtypes = [P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.POINTER(FmgHyper), ctypes.c_int,
+                                     ctypes.c_uint32, P, ctypes.POINTER(P)]
+    lib.fastmuygps_build.restype = ctypes.c_int
+    lib.fastmuygps_predict.argtypes = [P, P, ctypes.c_int64, P, P, P]
+    lib.fastmuygps_predict.restype = ctypes.c_int
+    lib.fastmuygps_info.argtypes = [P, ctypes.POINTER(FmgInfo)]
+    lib.fastmuygps_info.restype = ctypes.c_int
+    lib.fastmuygps_neighbors.argtypes = [P, P, P]
+    lib.fastmuygps_neighbors.restype = ctypes.c_int
+    lib.fastmuygps_coeffs.argtypes = [P, P, P]
+    lib.fastmuygps_coeffs.restype = ctypes.c_int
+    lib.fastmuygps_timings.argtypes = [P, ctypes.POINTER(FmgTimings)]
+    lib.fastmuygps_timings.restype = ctypes.c_int
+    lib.fastmuygps_free.argtypes = [P]
+    lib.fastmuygps_free.restype = None
+    lib.fastmuygps_last_error.argtypes = []
+    lib.fastmuygps_last_error.restype = ctypes.c_char_p
+    lib.fastmuygps_version.argtypes = []
+    lib.fastmuygps_version.restype = ctypes.c_char_p
+    return lib
+
+
+_lib_handle = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded HIP library (loaded on first use)."""
+    global _lib_handle
+    if _lib_handle is None:
+        _lib_handle = load_library()
+    return _lib_handle
+
+
+def _check(status: int, allow=()):
+    if status != FMG_OK and status not in allow:
+        raise FmgError(status, lib().fastmuygps_last_error().decode())
+    return status
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t: torch.Tensor, dtype, name: str) -> ctypes.c_void_p:
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if t.dtype != dtype:
+        raise ValueError("%s must be %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def version() -> str:
+    return lib().fastmuygps_version().decode()
+
+
+class Model:
+    """A built FastMuyGPs model (owns its device memory in the HIP library)."""
+
+    def __init__(self, handle: ctypes.c_void_p, dtype, d: int, ell: int, k: int, n: int,
+                 status: int):
+        self._h = handle
+        self.dtype = dtype
+        self.d, self.ell, self.k, self.n = d, ell, k, n
+        self.build_status = status
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if not self._h:
+            raise ValueError("model has been freed")
+        return self._h
+
+    def predict(self, Z: torch.Tensor, out: torch.Tensor | None = None,
+                nn_out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """fastmuygps_predict: means [m, ell] for the queries Z [m, d]."""
+        if Z.dim() != 2 or Z.shape[1] != self.d:
+            raise ValueError("Z must be [m, %d]" % self.d)
+        m = Z.shape[0]
+        if out is None:
+            out = torch.empty((m, self.ell), dtype=self.dtype, device=Z.device)
+        nn_ptr = None
+        if nn_out is not None:
+            nn_ptr = _dev_ptr(nn_out, torch.int32, "nn_out")
+        _check(lib().fastmuygps_predict(self.handle, _dev_ptr(Z, self.dtype, "Z"), m,
+                                       _dev_ptr(out, self.dtype, "out"), nn_ptr,
+                                       _stream_handle(stream)))
+        return out
+
+    def info(self) -> dict:
+        inf = FmgInfo()
+        _check(lib().fastmuygps_info(self.handle, ctypes.byref(inf)))
+        return {name: getattr(inf, name) for name, _ in FmgInfo._fields_}
+
+    def neighbors(self, stream=None) -> torch.Tensor:
+        out = torch.empty((self.n, self.k), dtype=torch.int32, device="cuda")
+        _check(lib().fastmuygps_neighbors(self.handle, ctypes.c_void_p(out.data_ptr()),
+                                         _stream_handle(stream)))
+        return out
+
+    def coeffs(self, stream=None) -> torch.Tensor:
+        out = torch.empty((self.n, self.k, self.ell), dtype=self.dtype, device="cuda")
+        _check(lib().fastmuygps_coeffs(self.handle, ctypes.c_void_p(out.data_ptr()),
+                                      _stream_handle(stream)))
+        return out
+
+    def timings(self) -> dict:
+        t = FmgTimings()
+        _check(lib().fastmuygps_timings(self.handle, ctypes.byref(t)))
+        return {name: getattr(t, name) for name, _ in FmgTimings._fields_}
+
+    def free(self):
+        if self._h:
+            lib().fastmuygps_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def fastmuygps_build(X: torch.Tensor, Y: torch.Tensor, k: int, kernel: str = "matern",
+                     nu: float = 1.5, length_scale: float = 1.0, noise_var: float = 0.0,
+                     amplitude: float = 1.0, precision: str = "fp32", flags: int = 0,
+                     stream=None, allow_not_pd: bool = False) -> Model:
+    """fastmuygps_build(X, y, k, kernel, hyperparams) -> model (Algorithm 2, training)."""
+    prec = PRECISIONS[precision]
+    dtype = torch.float64 if prec == PREC_FP64 else torch.float32
+    if X.dim() != 2:
+        raise ValueError("X must be [n, d]")
+    if Y.dim() == 1:
+        Y = Y[:, None]
+    n, d = X.shape
+    if Y.shape[0] != n:
+        raise ValueError("Y must have n rows")
+    ell = Y.shape[1]
+    hyper = FmgHyper(KERNEL_RBF if kernel == "rbf" else KERNEL_MATERN, float(nu),
+                     float(length_scale), float(noise_var), float(amplitude))
+    if kernel not in ("rbf", "matern"):
+        raise ValueError("kernel must be 'rbf' or 'matern'")
+    h = ctypes.c_void_p()
+    st = lib().fastmuygps_build(_dev_ptr(X, dtype, "X"), _dev_ptr(Y.contiguous(), dtype, "Y"), n,
+                               d, ell, int(k), ctypes.byref(hyper), prec, int(flags),
+                               _stream_handle(stream), ctypes.byref(h))
+    _check(st, allow=(FMG_E_NOT_PD,) if allow_not_pd else ())
+    return Model(h, dtype, d, ell, int(k), n, st)
+
+
+def fastmuygps_predict(model: Model, Z: torch.Tensor, out=None, nn_out=None, stream=None):
+    """fastmuygps_predict(model, Z) -> means (Algorithm 2, prediction)."""
+    return model.predict(Z, out=out, nn_out=nn_out, stream=stream)
+
+
+def fastmuygps_info(model: Model) -> dict:
+    return model.info()
+
+
+def fastmuygps_free(model: Model) -> None:
+    model.free()
+

@@ -1,0 +1,631 @@
+// Host runtime behind the C ABI (include/fastmuygps.h): argument checks, the
+// model object and its device memory, and the order of kernel launches for
+// offline training and online prediction (Algorithm 2).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fastmuygps.h"
+#include "fmg_device.h"
+#include "fmg_kernels.h"
+
+using namespace fmg;
+
+namespace {
+
+thread_local std::string g_err;
+
+fmg_status fail(fmg_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+fmg_status hip_fail(hipError_t e, const char *what) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(FMG_E_OOM, "%s: out of device memory (%s)", what, hipGetErrorString(e));
+    return fail(FMG_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(expr, what)                       \
+    do {                                         \
+        hipError_t e_ = (expr);                  \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// Device scratch owned by one call: freed when the holder goes out of scope,
+// stream-ordered when a stream is given.
+struct Scratch {
+    hipStream_t stream = nullptr;
+    bool async = false;
+    std::vector<void *> ptrs;
+    ~Scratch() {
+        for (void *p : ptrs) {
+            if (async)
+                (void)hipFreeAsync(p, stream);
+            else
+                (void)hipFree(p);
+        }
+    }
+    hipError_t alloc(void **p, size_t bytes) {
+        if (bytes == 0) bytes = 16;
+        hipError_t e = async ? hipMallocAsync(p, bytes, stream) : hipMalloc(p, bytes);
+        if (e == hipSuccess) ptrs.push_back(*p);
+        return e;
+    }
+};
+
+enum { EV_START = 0, EV_PREP, EV_SCREEN, EV_RERANK, EV_FALLBACK, EV_LAST, EV_COUNT };
+
+}  // namespace
+
+struct fmg_model {
+    int64_t n = 0;
+    int d = 0, ell = 0, k = 0;
+    fmg_hyper hyper{};
+    int prec = 0;
+    uint32_t flags = 0;
+    int kc = 0;
+    double inv_rho = 1.0, amp = 1.0;
+    bool self_inc = false;
+    int device = 0;
+
+    void *X = nullptr;   // [n, d]
+    int32_t *N = nullptr;  // [n, k]
+    void *C = nullptr;   // [n, k, ell]
+
+    ScreenGeom geom{};
+    int64_t n_pad = 0;
+    void *Xp = nullptr;  // [n_pad, kp] candidate-side screening rows
+    float *mu = nullptr; // [d]
+    double e_max = 0.0, nx_max = 0.0, acc_coef = 0.0;
+    int c_build = 0, c_query = 0;
+    int64_t nonpd = 0, build_fb = 0;
+    unsigned long long *pred_fb = nullptr;
+    uint64_t bytes = 0;
+
+    bool timing = false;
+    hipEvent_t evb[EV_COUNT]{};
+    hipEvent_t evp[EV_COUNT]{};
+    bool pred_recorded = false;
+    double build_ms[EV_COUNT]{};
+};
+
+namespace {
+
+void free_model(fmg_model *M) {
+    if (!M) return;
+    void *ptrs[] = {M->X, M->N, M->C, M->Xp, M->mu, M->pred_fb};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    if (M->timing)
+        for (int e = 0; e < EV_COUNT; ++e) {
+            if (M->evb[e]) (void)hipEventDestroy(M->evb[e]);
+            if (M->evp[e]) (void)hipEventDestroy(M->evp[e]);
+        }
+    delete M;
+}
+
+int kernel_code(const fmg_hyper &h) {
+    if (h.kernel == FMG_KERNEL_RBF) return KC_RBF;
+    if (h.kernel != FMG_KERNEL_MATERN) return -1;
+    if (h.nu == 0.5) return KC_M12;
+    if (h.nu == 1.5) return KC_M32;
+    if (h.nu == 2.5) return KC_M52;
+    return -1;
+}
+
+void record(fmg_model *M, hipEvent_t *ev, int idx, hipStream_t s) {
+    if (M->timing) (void)hipEventRecord(ev[idx], s);
+}
+
+fmg_status model_alloc(fmg_model *M, void **p, size_t bytes, const char *what) {
+    hipError_t e = hipMalloc(p, bytes ? bytes : 16);
+    if (e != hipSuccess) return hip_fail(e, what);
+    M->bytes += bytes;
+    return FMG_OK;
+}
+
+// Screening geometry for a precision mode and dimension.
+bool screen_geom(int prec, int d, ScreenGeom *g) {
+    if (prec == FMG_PREC_MIXED) {
+        if (d + 3 > 64) return false;
+        *g = ScreenGeom{SCREEN_BF16, 64, 2, 128};
+        return true;
+    }
+    const int kp = (int)round_up(d + 1, 16);
+    if (kp > 64) return false;
+    *g = ScreenGeom{SCREEN_F32, kp, kp / 4, kp * 4};
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fastmuygps_last_error(void) { return g_err.c_str(); }
+
+const char *fastmuygps_version(void) { return "fastmuygps-gfx950 0.1"; }
+
+void fastmuygps_free(fmg_model *model) { free_model(model); }
+
+fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, int32_t ell,
+                            int32_t k, const fmg_hyper *hyper, fmg_precision prec,
+                            uint32_t flags, void *stream, fmg_model **out) {
+    g_err.clear();
+    if (!out) return fail(FMG_E_INVALID_ARG, "out is null");
+    *out = nullptr;
+    if (!X || !Y || !hyper) return fail(FMG_E_INVALID_ARG, "X, Y and hyper must not be null");
+    if (prec != FMG_PREC_FP64 && prec != FMG_PREC_FP32 && prec != FMG_PREC_MIXED)
+        return fail(FMG_E_INVALID_ARG, "unknown precision %d", (int)prec);
+    const bool self_inc = (flags & FMG_FLAG_SELF_INCLUSIVE) != 0;
+    if (n < 2 || n > 2147483647LL) return fail(FMG_E_INVALID_ARG, "n = %lld out of range", (long long)n);
+    if (d < 1) return fail(FMG_E_INVALID_ARG, "d = %d must be >= 1", d);
+    if (ell < 1 || ell > 16) return fail(FMG_E_INVALID_ARG, "ell = %d must be in [1, 16]", ell);
+    if (k < 1 || k > 64) return fail(FMG_E_INVALID_ARG, "k = %d must be in [1, 64]", k);
+    if (!self_inc && k > n - 1)
+        return fail(FMG_E_INVALID_ARG, "leave-one-out needs k <= n-1 (k=%d, n=%lld)", k, (long long)n);
+    if (self_inc && k > n)
+        return fail(FMG_E_INVALID_ARG, "self-inclusive needs k <= n (k=%d, n=%lld)", k, (long long)n);
+    if (!(hyper->length_scale > 0.0) || !std::isfinite(hyper->length_scale))
+        return fail(FMG_E_INVALID_ARG, "length_scale must be positive and finite");
+    if (!(hyper->noise_var >= 0.0) || !std::isfinite(hyper->noise_var))
+        return fail(FMG_E_INVALID_ARG, "noise_var must be >= 0 and finite");
+    const int kc = kernel_code(*hyper);
+    if (kc < 0) return fail(FMG_E_INVALID_ARG, "kernel must be RBF or Matern with nu in {0.5, 1.5, 2.5}");
+    ScreenGeom geom{};
+    if (prec != FMG_PREC_FP64 && !screen_geom(prec, d, &geom))
+        return fail(FMG_E_UNSUPPORTED, "d = %d too large for the %s screen", d,
+                    prec == FMG_PREC_MIXED ? "BF16" : "FP32");
+
+    hipStream_t s = (hipStream_t)stream;
+    fmg_model *M = new fmg_model();
+    M->n = n;
+    M->d = d;
+    M->ell = ell;
+    M->k = k;
+    M->hyper = *hyper;
+    M->prec = prec;
+    M->flags = flags;
+    M->kc = kc;
+    M->inv_rho = 1.0 / hyper->length_scale;
+    M->amp = hyper->amplitude > 0.0 ? hyper->amplitude : 1.0;
+    M->self_inc = self_inc;
+    M->geom = geom;
+    (void)hipGetDevice(&M->device);
+    const bool f64 = prec == FMG_PREC_FP64;
+    const size_t esz = f64 ? 8 : 4;
+    fmg_status st;
+    Scratch tmp;
+
+#define MCHK(expr)                  \
+    do {                            \
+        fmg_status s_ = (expr);     \
+        if (s_ != FMG_OK) {         \
+            free_model(M);          \
+            return s_;              \
+        }                           \
+    } while (0)
+#define HCHK(expr, what)                      \
+    do {                                      \
+        hipError_t e_ = (expr);               \
+        if (e_ != hipSuccess) {               \
+            free_model(M);                    \
+            return hip_fail(e_, what);        \
+        }                                     \
+    } while (0)
+
+    if (flags & FMG_FLAG_TIMING) {
+        M->timing = true;
+        for (int e = 0; e < EV_COUNT; ++e) {
+            HCHK(hipEventCreate(&M->evb[e]), "hipEventCreate");
+            HCHK(hipEventCreate(&M->evp[e]), "hipEventCreate");
+        }
+    }
+    MCHK(model_alloc(M, &M->X, (size_t)n * d * esz, "model X"));
+    MCHK(model_alloc(M, (void **)&M->N, (size_t)n * k * 4, "model N"));
+    MCHK(model_alloc(M, &M->C, (size_t)n * k * ell * esz, "model C"));
+    MCHK(model_alloc(M, (void **)&M->pred_fb, 8, "counters"));
+    HCHK(hipMemsetAsync(M->pred_fb, 0, 8, s), "hipMemsetAsync");
+    record(M, M->evb, EV_START, s);
+    HCHK(hipMemcpyAsync(M->X, X, (size_t)n * d * esz, hipMemcpyDeviceToDevice, s), "copy X");
+
+    // Inputs must be finite.
+    int *flag = nullptr;
+    HCHK(tmp.alloc((void **)&flag, 4), "scratch");
+    HCHK(hipMemsetAsync(flag, 0, 4, s), "hipMemsetAsync");
+    HCHK(launch_finite_check(X, f64, n * (int64_t)d, flag, s), "finite check");
+    HCHK(launch_finite_check(Y, f64, n * (int64_t)ell, flag, s), "finite check");
+    int hflag = 0;
+    HCHK(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s), "copy flag");
+    HCHK(hipStreamSynchronize(s), "sync");
+    if (hflag) {
+        free_model(M);
+        return fail(FMG_E_INVALID_ARG, "X or Y holds a non-finite value");
+    }
+
+    const int kk = self_inc ? k - 1 : k;  // neighbours found by search
+    if (kk == 0) {
+        record(M, M->evb, EV_PREP, s);
+        HCHK(launch_self_rows(M->N, n, s), "self rows");
+        for (int e = EV_SCREEN; e <= EV_FALLBACK; ++e) record(M, M->evb, e, s);
+    } else if (f64) {
+        record(M, M->evb, EV_PREP, s);
+        ExactArgs ea{};
+        ea.X = M->X;
+        ea.n = n;
+        ea.d = d;
+        ea.Qc = M->X;
+        ea.nq = n;
+        ea.loo = 1;
+        ea.k = kk;
+        ea.self_first = self_inc;
+        ea.out = M->N;
+        ea.out_stride = k;
+        HCHK(launch_exact_topk(true, ea, n, s), "exact search");
+        for (int e = EV_SCREEN; e <= EV_FALLBACK; ++e) record(M, M->evb, e, s);
+    } else {
+        const int64_t n_pad = round_up(n, SCREEN_QPB);
+        M->n_pad = n_pad;
+        MCHK(model_alloc(M, (void **)&M->mu, (size_t)d * 4, "model mu"));
+        if (flags & FMG_FLAG_NO_CENTER)
+            HCHK(hipMemsetAsync(M->mu, 0, (size_t)d * 4, s), "hipMemsetAsync");
+        else
+            HCHK(launch_col_mean(M->X, false, n, d, M->mu, s), "column mean");
+        MCHK(model_alloc(M, &M->Xp, (size_t)n_pad * geom.row_bytes, "model screen rows"));
+        void *Xq = nullptr;
+        double *ex = nullptr, *nzx = nullptr;
+        unsigned long long *mx = nullptr;
+        HCHK(tmp.alloc(&Xq, (size_t)n_pad * geom.row_bytes), "scratch");
+        HCHK(tmp.alloc((void **)&ex, (size_t)n * 8), "scratch");
+        HCHK(tmp.alloc((void **)&nzx, (size_t)n * 8), "scratch");
+        HCHK(tmp.alloc((void **)&mx, 16), "scratch");
+        HCHK(hipMemsetAsync(mx, 0, 16, s), "hipMemsetAsync");
+        HCHK(launch_prep_rows(geom, (const float *)M->X, n, n_pad, d, M->mu, Xq, M->Xp, ex, nzx,
+                              mx, mx + 1, s),
+             "screen rows");
+        unsigned long long hmx[2] = {0, 0};
+        HCHK(hipMemcpyAsync(hmx, mx, 16, hipMemcpyDeviceToHost, s), "copy maxima");
+        record(M, M->evb, EV_PREP, s);
+        HCHK(hipStreamSynchronize(s), "sync");
+        memcpy(&M->e_max, &hmx[0], 8);
+        memcpy(&M->nx_max, &hmx[1], 8);
+        const double u = std::ldexp(1.0, -23);
+        const double nt = 2.0 * geom.kp;
+        M->acc_coef = nt * u / (1.0 - nt * u);
+        M->c_build = prec == FMG_PREC_MIXED ? 2 * kk : kk + 8;
+        M->c_query = 16;
+
+        const int c = M->c_build;
+        uint64_t *pool = nullptr, *cand = nullptr;
+        float *tq = nullptr;
+        int32_t *fbl = nullptr, *fbc = nullptr;
+        HCHK(tmp.alloc((void **)&pool, (size_t)n_pad * SCREEN_CAP * 8), "screen pool");
+        HCHK(tmp.alloc((void **)&cand, (size_t)n * c * 8), "scratch");
+        HCHK(tmp.alloc((void **)&tq, (size_t)n * 4), "scratch");
+        HCHK(tmp.alloc((void **)&fbl, (size_t)n * 4), "scratch");
+        HCHK(tmp.alloc((void **)&fbc, 4), "scratch");
+        HCHK(hipMemsetAsync(fbc, 0, 4, s), "hipMemsetAsync");
+        ScreenArgs sa{};
+        sa.Q = Xq;
+        sa.P = M->Xp;
+        sa.m = n;
+        sa.m_pad = n_pad;
+        sa.n = n;
+        sa.n_pad = n_pad;
+        sa.col_chunk = n_pad;
+        sa.splits = 1;
+        sa.loo = 1;
+        sa.c = c;
+        sa.pool = pool;
+        sa.cand = cand;
+        sa.tq = tq;
+        HCHK(launch_screen(geom, sa, s), "screen");
+        record(M, M->evb, EV_SCREEN, s);
+        RerankArgs ra{};
+        ra.cand = cand;
+        ra.tq = tq;
+        ra.splits = 1;
+        ra.c = c;
+        ra.m = n;
+        ra.X = M->X;
+        ra.Zc = M->X;
+        ra.d = d;
+        ra.nzq = nzx;
+        ra.eq = ex;
+        ra.e_max = M->e_max;
+        ra.acc_coef = M->acc_coef;
+        ra.nx_max = M->nx_max;
+        ra.k = kk;
+        ra.self_first = self_inc;
+        ra.out = M->N;
+        ra.out_stride = k;
+        ra.fb_list = fbl;
+        ra.fb_count = fbc;
+        HCHK(launch_rerank(ra, s), "re-rank");
+        record(M, M->evb, EV_RERANK, s);
+        int hfb = 0;
+        HCHK(hipMemcpyAsync(&hfb, fbc, 4, hipMemcpyDeviceToHost, s), "copy count");
+        HCHK(hipStreamSynchronize(s), "sync");
+        M->build_fb = hfb;
+        if (hfb > 0) {
+            ExactArgs ea{};
+            ea.X = M->X;
+            ea.n = n;
+            ea.d = d;
+            ea.Qc = M->X;
+            ea.list = fbl;
+            ea.count = fbc;
+            ea.loo = 1;
+            ea.k = kk;
+            ea.self_first = self_inc;
+            ea.out = M->N;
+            ea.out_stride = k;
+            HCHK(launch_exact_topk(false, ea, hfb, s), "exact rescan");
+        }
+        record(M, M->evb, EV_FALLBACK, s);
+    }
+
+    int32_t *status = nullptr;
+    unsigned long long *nbad = nullptr;
+    HCHK(tmp.alloc((void **)&status, (size_t)n * 4), "scratch");
+    HCHK(tmp.alloc((void **)&nbad, 8), "scratch");
+    HCHK(hipMemsetAsync(nbad, 0, 8, s), "hipMemsetAsync");
+    PrecomputeArgs pa{};
+    pa.X = M->X;
+    pa.Y = Y;
+    pa.n = n;
+    pa.d = d;
+    pa.ell = ell;
+    pa.k = k;
+    pa.N = M->N;
+    pa.C = M->C;
+    pa.status = status;
+    pa.kc = kc;
+    pa.inv_rho = M->inv_rho;
+    pa.amp = M->amp;
+    pa.noise = hyper->noise_var;
+    const bool refine = prec == FMG_PREC_MIXED && !(flags & FMG_FLAG_NO_REFINE);
+    HCHK(launch_precompute(f64, refine, pa, s), "precompute");
+    record(M, M->evb, EV_LAST, s);
+    HCHK(launch_count_nonzero(status, n, nbad, s), "count");
+    unsigned long long hbad = 0;
+    HCHK(hipMemcpyAsync(&hbad, nbad, 8, hipMemcpyDeviceToHost, s), "copy count");
+    HCHK(hipStreamSynchronize(s), "sync");
+    M->nonpd = (int64_t)hbad;
+    if (M->timing) {
+        for (int e = 1; e < EV_COUNT; ++e) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, M->evb[e - 1], M->evb[e]);
+            M->build_ms[e] = ms;
+        }
+        float tot = 0.f;
+        (void)hipEventElapsedTime(&tot, M->evb[EV_START], M->evb[EV_LAST]);
+        M->build_ms[0] = tot;
+    }
+#undef MCHK
+#undef HCHK
+    *out = M;
+    if (M->nonpd > 0)
+        return fail(FMG_E_NOT_PD, "%lld neighbourhood matrices were not positive definite",
+                    (long long)M->nonpd);
+    return FMG_OK;
+}
+
+fmg_status fastmuygps_predict(const fmg_model *model, const void *Z, int64_t m, void *out,
+                              int32_t *nn_out, void *stream) {
+    g_err.clear();
+    if (!model) return fail(FMG_E_INVALID_ARG, "model is null");
+    if (m < 0) return fail(FMG_E_INVALID_ARG, "m = %lld < 0", (long long)m);
+    if (m == 0) return FMG_OK;
+    if (m > 2147483647LL) return fail(FMG_E_INVALID_ARG, "m too large");
+    if (!Z || !out) return fail(FMG_E_INVALID_ARG, "Z and out must not be null");
+    fmg_model *M = const_cast<fmg_model *>(model);
+    hipStream_t s = (hipStream_t)stream;
+    const bool f64 = M->prec == FMG_PREC_FP64;
+    Scratch tmp;
+    tmp.stream = s;
+    tmp.async = true;
+    record(M, M->evp, EV_START, s);
+    int32_t *nn = nn_out;
+    if (!nn) HIPCHK(tmp.alloc((void **)&nn, (size_t)m * 4), "scratch");
+    if (f64) {
+        record(M, M->evp, EV_PREP, s);
+        ExactArgs ea{};
+        ea.X = M->X;
+        ea.n = M->n;
+        ea.d = M->d;
+        ea.Qc = Z;
+        ea.nq = m;
+        ea.loo = 0;
+        ea.k = 1;
+        ea.out = nn;
+        ea.out_stride = 1;
+        HIPCHK(launch_exact_topk(true, ea, m, s), "exact search");
+        for (int e = EV_SCREEN; e <= EV_FALLBACK; ++e) record(M, M->evp, e, s);
+    } else {
+        const ScreenGeom &g = M->geom;
+        const int64_t m_pad = round_up(m, SCREEN_QPB);
+        void *Zq = nullptr;
+        double *ez = nullptr, *nzz = nullptr;
+        HIPCHK(tmp.alloc(&Zq, (size_t)m_pad * g.row_bytes), "scratch");
+        HIPCHK(tmp.alloc((void **)&ez, (size_t)m * 8), "scratch");
+        HIPCHK(tmp.alloc((void **)&nzz, (size_t)m * 8), "scratch");
+        HIPCHK(launch_prep_rows(g, (const float *)Z, m, m_pad, M->d, M->mu, Zq, nullptr, ez, nzz,
+                                nullptr, nullptr, s),
+               "query rows");
+        record(M, M->evp, EV_PREP, s);
+        // Split the training columns when there are too few query blocks to
+        // fill the device.
+        const int64_t qblocks = m_pad / SCREEN_QPB;
+        int64_t splits = (512 + qblocks - 1) / qblocks;
+        if (splits > 8) splits = 8;
+        if (splits < 1) splits = 1;
+        int64_t chunk = round_up((M->n_pad + splits - 1) / splits, SCREEN_TILE);
+        splits = (M->n_pad + chunk - 1) / chunk;
+        const int c = M->c_query;
+        uint64_t *pool = nullptr, *cand = nullptr;
+        float *tq = nullptr;
+        int32_t *fbl = nullptr, *fbc = nullptr;
+        HIPCHK(tmp.alloc((void **)&pool, (size_t)splits * m_pad * SCREEN_CAP * 8), "screen pool");
+        HIPCHK(tmp.alloc((void **)&cand, (size_t)splits * m * c * 8), "scratch");
+        HIPCHK(tmp.alloc((void **)&tq, (size_t)splits * m * 4), "scratch");
+        HIPCHK(tmp.alloc((void **)&fbl, (size_t)m * 4), "scratch");
+        HIPCHK(tmp.alloc((void **)&fbc, 4), "scratch");
+        HIPCHK(launch_zero_u32(fbc, 1, s), "zero");
+        ScreenArgs sa{};
+        sa.Q = Zq;
+        sa.P = M->Xp;
+        sa.m = m;
+        sa.m_pad = m_pad;
+        sa.n = M->n;
+        sa.n_pad = M->n_pad;
+        sa.col_chunk = chunk;
+        sa.splits = (int)splits;
+        sa.loo = 0;
+        sa.c = c;
+        sa.pool = pool;
+        sa.cand = cand;
+        sa.tq = tq;
+        HIPCHK(launch_screen(g, sa, s), "screen");
+        record(M, M->evp, EV_SCREEN, s);
+        RerankArgs ra{};
+        ra.cand = cand;
+        ra.tq = tq;
+        ra.splits = (int)splits;
+        ra.c = c;
+        ra.m = m;
+        ra.X = M->X;
+        ra.Zc = Z;
+        ra.d = M->d;
+        ra.nzq = nzz;
+        ra.eq = ez;
+        ra.e_max = M->e_max;
+        ra.acc_coef = M->acc_coef;
+        ra.nx_max = M->nx_max;
+        ra.k = 1;
+        ra.self_first = 0;
+        ra.out = nn;
+        ra.out_stride = 1;
+        ra.fb_list = fbl;
+        ra.fb_count = fbc;
+        HIPCHK(launch_rerank(ra, s), "re-rank");
+        record(M, M->evp, EV_RERANK, s);
+        ExactArgs ea{};
+        ea.X = M->X;
+        ea.n = M->n;
+        ea.d = M->d;
+        ea.Qc = Z;
+        ea.list = fbl;
+        ea.count = fbc;
+        ea.loo = 0;
+        ea.k = 1;
+        ea.out = nn;
+        ea.out_stride = 1;
+        HIPCHK(launch_exact_topk(false, ea, m, s), "exact rescan");
+        HIPCHK(launch_accum(fbc, M->pred_fb, s), "count");
+        record(M, M->evp, EV_FALLBACK, s);
+    }
+    GatherArgs ga{};
+    ga.X = M->X;
+    ga.Z = Z;
+    ga.nn = nn;
+    ga.N = M->N;
+    ga.C = M->C;
+    ga.m = m;
+    ga.d = M->d;
+    ga.ell = M->ell;
+    ga.k = M->k;
+    ga.kc = M->kc;
+    ga.inv_rho = M->inv_rho;
+    ga.amp = M->amp;
+    ga.out = out;
+    HIPCHK(launch_gather(f64, ga, s), "gather");
+    record(M, M->evp, EV_LAST, s);
+    if (M->timing) M->pred_recorded = true;
+    return FMG_OK;
+}
+
+fmg_status fastmuygps_info(const fmg_model *model, fmg_info *info) {
+    g_err.clear();
+    if (!model || !info) return fail(FMG_E_INVALID_ARG, "null argument");
+    memset(info, 0, sizeof *info);
+    info->n = model->n;
+    info->d = model->d;
+    info->ell = model->ell;
+    info->k = model->k;
+    info->precision = model->prec;
+    info->screen_cands = model->c_build;
+    info->query_cands = model->c_query;
+    info->nonpd_rows = model->nonpd;
+    info->build_fallback_rows = model->build_fb;
+    info->device_bytes = model->bytes;
+    HIPCHK(hipDeviceSynchronize(), "sync");
+    unsigned long long v = 0;
+    HIPCHK(hipMemcpy(&v, model->pred_fb, 8, hipMemcpyDeviceToHost), "copy counter");
+    info->predict_fallback_rows = (int64_t)v;
+    return FMG_OK;
+}
+
+fmg_status fastmuygps_neighbors(const fmg_model *model, int32_t *dev_out, void *stream) {
+    g_err.clear();
+    if (!model || !dev_out) return fail(FMG_E_INVALID_ARG, "null argument");
+    HIPCHK(hipMemcpyAsync(dev_out, model->N, (size_t)model->n * model->k * 4,
+                          hipMemcpyDeviceToDevice, (hipStream_t)stream),
+           "copy N");
+    return FMG_OK;
+}
+
+fmg_status fastmuygps_coeffs(const fmg_model *model, void *dev_out, void *stream) {
+    g_err.clear();
+    if (!model || !dev_out) return fail(FMG_E_INVALID_ARG, "null argument");
+    const size_t esz = model->prec == FMG_PREC_FP64 ? 8 : 4;
+    HIPCHK(hipMemcpyAsync(dev_out, model->C, (size_t)model->n * model->k * model->ell * esz,
+                          hipMemcpyDeviceToDevice, (hipStream_t)stream),
+           "copy C");
+    return FMG_OK;
+}
+
+fmg_status fastmuygps_timings(const fmg_model *model, fmg_timings *t) {
+    g_err.clear();
+    if (!model || !t) return fail(FMG_E_INVALID_ARG, "null argument");
+    if (!model->timing) return fail(FMG_E_INVALID_ARG, "model was built without FMG_FLAG_TIMING");
+    memset(t, 0, sizeof *t);
+    t->build_prep_ms = model->build_ms[EV_PREP];
+    t->build_screen_ms = model->build_ms[EV_SCREEN];
+    t->build_rerank_ms = model->build_ms[EV_RERANK];
+    t->build_fallback_ms = model->build_ms[EV_FALLBACK];
+    t->build_precompute_ms = model->build_ms[EV_LAST];
+    t->build_total_ms = model->build_ms[0];
+    if (model->pred_recorded) {
+        HIPCHK(hipEventSynchronize(model->evp[EV_LAST]), "event sync");
+        double v[EV_COUNT] = {0};
+        for (int e = 1; e < EV_COUNT; ++e) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, model->evp[e - 1], model->evp[e]), "elapsed");
+            v[e] = ms;
+        }
+        float tot = 0.f;
+        HIPCHK(hipEventElapsedTime(&tot, model->evp[EV_START], model->evp[EV_LAST]), "elapsed");
+        t->predict_prep_ms = v[EV_PREP];
+        t->predict_screen_ms = v[EV_SCREEN];
+        t->predict_rerank_ms = v[EV_RERANK];
+        t->predict_fallback_ms = v[EV_FALLBACK];
+        t->predict_gather_ms = v[EV_LAST];
+        t->predict_total_ms = tot;
+    }
+    return FMG_OK;
+}
+
+}  // extern "C"

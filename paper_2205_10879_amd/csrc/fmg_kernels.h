@@ -1,0 +1,125 @@
+// Internal launch interface between the host runtime (fmg_api.cpp) and the
+// HIP kernels.  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fmg {
+
+// Screening arithmetic.
+enum ScreenMode { SCREEN_BF16 = 0, SCREEN_F32 = 1 };
+
+// Candidates per iteration of the screen (one 64-row tile of training points).
+constexpr int SCREEN_TILE = 64;
+// Queries per screen workgroup (4 waves x 64 queries).
+constexpr int SCREEN_QPB = 256;
+// Pool entries per query in the screen (candidate keys awaiting selection).
+constexpr int SCREEN_CAP = 512;
+
+// Row layout of the screening arrays: `kp` elements per row (bf16 or f32),
+// row bytes = kp * elem.  bf16: kp = 64 (2 MFMA k-steps of 32); f32: kp a
+// multiple of 16.
+struct ScreenGeom {
+    int mode;    // ScreenMode
+    int kp;      // elements per row
+    int ksteps;  // MFMA k-steps per tile
+    int row_bytes;
+};
+
+struct ScreenArgs {
+    const void *Q;      // [m_pad, kp] query-side rows
+    const void *P;      // [n_pad, kp] candidate-side rows
+    int64_t m, m_pad;   // queries (real, padded to SCREEN_QPB)
+    int64_t n, n_pad;   // candidates (real, padded to SCREEN_TILE)
+    int64_t col_chunk;  // candidate columns per split (multiple of SCREEN_TILE)
+    int splits;
+    int loo;            // 1: query q never takes candidate q
+    int c;              // candidates kept per (query, split), <= SCREEN_CAP - SCREEN_TILE
+    uint64_t *pool;     // [splits, m_pad, SCREEN_CAP] scratch
+    uint64_t *cand;     // [splits, m, c] sorted screen keys (value, index)
+    float *tq;          // [splits, m] c-th kept value, +inf when fewer than c
+};
+
+struct RerankArgs {
+    const uint64_t *cand;
+    const float *tq;
+    int splits, c;
+    int64_t m;
+    const void *X;       // [n, d] training coordinates (float)
+    const void *Zc;      // [m, d] query coordinates (float)
+    int d;
+    const double *nzq;   // [m] exact ||z~||^2 of the screened query rows
+    const double *eq;    // [m] rounding radius of the screened query rows
+    double e_max;        // max rounding radius over training rows
+    double acc_coef;     // A_q = acc_coef * (2.01 nx_max + nz_q) + 1e-6 nx_max
+    double nx_max;
+    int k;               // neighbours to keep
+    int self_first;      // write q first, then k results (SELF mode)
+    int32_t *out;
+    int out_stride;
+    int32_t *fb_list;    // rows that failed the certificate
+    int32_t *fb_count;
+};
+
+struct ExactArgs {
+    const void *X;        // [n, d] training coordinates (float or double)
+    int64_t n;
+    int d;
+    const void *Qc;       // [*, d] query coordinates
+    const int32_t *list;  // optional list of query rows
+    const int32_t *count; // optional device count of `list`
+    int64_t nq;           // number of query rows when count == nullptr
+    int loo;              // exclude candidate == query row index
+    int k;                // 1..64
+    int self_first;
+    int32_t *out;
+    int out_stride;
+};
+
+struct PrecomputeArgs {
+    const void *X;   // [n, d]
+    const void *Y;   // [n, ell]
+    int64_t n;
+    int d, ell, k;
+    const int32_t *N;  // [n, k]
+    void *C;           // [n, k, ell]
+    int32_t *status;   // [n] 0 ok, 1 not positive definite
+    int kc;            // kernel code (fmg_device.h)
+    double inv_rho, amp, noise;
+};
+
+struct GatherArgs {
+    const void *X;
+    const void *Z;
+    const int32_t *nn;
+    const int32_t *N;
+    const void *C;
+    int64_t m;
+    int d, ell, k;
+    int kc;
+    double inv_rho, amp;
+    void *out;
+};
+
+hipError_t launch_col_mean(const void *X, bool f64, int64_t n, int d, float *mu, hipStream_t s);
+hipError_t launch_finite_check(const void *A, bool f64, int64_t count, int *flag, hipStream_t s);
+hipError_t launch_prep_rows(const ScreenGeom &g, const float *X, int64_t n, int64_t n_pad, int d,
+                            const float *mu, void *Qrows, void *Prows, double *e_out,
+                            double *nz_out, unsigned long long *emax_bits,
+                            unsigned long long *nxmax_bits, hipStream_t s);
+hipError_t launch_screen(const ScreenGeom &g, const ScreenArgs &a, hipStream_t s);
+hipError_t launch_rerank(const RerankArgs &a, hipStream_t s);
+hipError_t launch_exact_topk(bool f64, const ExactArgs &a, int64_t max_items, hipStream_t s);
+hipError_t launch_precompute(bool f64, bool refine, const PrecomputeArgs &a, hipStream_t s);
+hipError_t launch_gather(bool f64, const GatherArgs &a, hipStream_t s);
+hipError_t launch_count_nonzero(const int32_t *a, int64_t n, unsigned long long *out,
+                                hipStream_t s);
+// N[i] = i for every row (self-inclusive neighbourhoods of size 1).
+hipError_t launch_self_rows(int32_t *N, int64_t n, hipStream_t s);
+// Zero `count` 32-bit words with a kernel (safe inside captured graphs).
+hipError_t launch_zero_u32(void *ptr, int64_t count, hipStream_t s);
+// *dst += *src
+hipError_t launch_accum(const int32_t *src, unsigned long long *dst, hipStream_t s);
+
+}  // namespace fmg

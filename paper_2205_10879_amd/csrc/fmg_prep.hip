@@ -1,0 +1,239 @@
+// Ingest kernels: input checks, the centring vector, and the screening rows.
+//
+// Screening rows let one MFMA product return the screened squared distance
+// minus the query norm:
+//   candidate row  P_p = [-2 x~_p , ||x~_p||^2 split into parts , 0 ...]
+//   query row      Q_q = [   z~_q , 1 for every part          , 0 ...]
+//   <P_p, Q_q> = ||x~_p||^2 - 2 <x~_p, z~_q> = ||x~_p - z~_q||^2 - ||z~_q||^2
+// where x~ is x - mu rounded to the screening type.  BF16 carries the norm
+// as three BF16 parts (hi + mid + lo, 24 significant bits together); FP32
+// carries it as one FP32 value.  For every row the kernels also record the
+// exact ||x~||^2 (FP64) and the rounding radius e = ||(x - mu) - x~||_2,
+// which the exactness certificate of the re-rank uses.
+#include "fmg_device.h"
+#include "fmg_kernels.h"
+
+namespace fmg {
+
+namespace {
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rn(float f) {
+    uint32_t u = __float_as_uint(f);
+    uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(r >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+    return __uint_as_float((uint32_t)h << 16);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void col_mean_kernel(const T *__restrict__ X, int64_t n, int d,
+                                                       float *__restrict__ mu) {
+    // One block per column; fixed summation order, so the result is
+    // deterministic.
+    const int c = blockIdx.x;
+    __shared__ double part[256];
+    double s = 0.0;
+    for (int64_t r = threadIdx.x; r < n; r += 256) s += (double)X[r * d + c];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) mu[c] = (float)(part[0] / (double)n);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void finite_kernel(const T *__restrict__ A, int64_t count,
+                                                     int *__restrict__ flag) {
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * 256) {
+        double v = (double)A[i];
+        bad |= !isfinite(v);
+    }
+    if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(flag, 1);
+}
+
+__global__ __launch_bounds__(256) void prep_bf16_kernel(
+    const float *__restrict__ X, int64_t n, int64_t n_pad, int d, const float *__restrict__ mu,
+    int kp, uint16_t *__restrict__ Q, uint16_t *__restrict__ P, double *__restrict__ e_out,
+    double *__restrict__ nz_out, unsigned long long *emax_bits,
+    unsigned long long *nxmax_bits) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= n_pad) return;
+    uint16_t *q = Q ? Q + r * kp : nullptr;
+    uint16_t *p = P ? P + r * kp : nullptr;
+    if (r >= n) {
+        // Padding candidate: a huge norm part keeps it out of every selection.
+        for (int c = 0; c < kp; ++c) {
+            if (q) q[c] = 0;
+            if (p) p[c] = 0;
+        }
+        if (p) p[d] = f32_to_bf16_rn(1.0e30f);
+        return;
+    }
+    double e2 = 0.0, nz = 0.0;
+    for (int c = 0; c < d; ++c) {
+        const double xc = (double)X[r * d + c] - (double)mu[c];
+        const uint16_t h = f32_to_bf16_rn((float)xc);
+        const double xt = (double)bf16_to_f32(h);
+        const double diff = xc - xt;
+        e2 += diff * diff;
+        nz += xt * xt;
+        if (q) q[c] = h;
+        if (p) p[c] = f32_to_bf16_rn(-2.0f * bf16_to_f32(h));  // exact: a power-of-two scale
+    }
+    // norm split: nz = hi + mid + lo (+ a remainder below 2^-26 nz)
+    const uint16_t hi = f32_to_bf16_rn((float)nz);
+    const double r1 = nz - (double)bf16_to_f32(hi);
+    const uint16_t mid = f32_to_bf16_rn((float)r1);
+    const double r2 = r1 - (double)bf16_to_f32(mid);
+    const uint16_t lo = f32_to_bf16_rn((float)r2);
+    const uint16_t one = f32_to_bf16_rn(1.0f);
+    for (int c = d; c < kp; ++c) {
+        if (q) q[c] = (c < d + 3) ? one : 0;
+        if (p) p[c] = (c == d) ? hi : (c == d + 1) ? mid : (c == d + 2) ? lo : 0;
+    }
+    const double e = sqrt(e2) * (1.0 + 1.0e-12);
+    if (e_out) e_out[r] = e;
+    if (nz_out) nz_out[r] = nz;
+    if (emax_bits) atomicMax(emax_bits, (unsigned long long)__double_as_longlong(e));
+    if (nxmax_bits) atomicMax(nxmax_bits, (unsigned long long)__double_as_longlong(nz));
+}
+
+__global__ __launch_bounds__(256) void prep_f32_kernel(
+    const float *__restrict__ X, int64_t n, int64_t n_pad, int d, const float *__restrict__ mu,
+    int kp, float *__restrict__ Q, float *__restrict__ P, double *__restrict__ e_out,
+    double *__restrict__ nz_out, unsigned long long *emax_bits,
+    unsigned long long *nxmax_bits) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= n_pad) return;
+    float *q = Q ? Q + r * kp : nullptr;
+    float *p = P ? P + r * kp : nullptr;
+    if (r >= n) {
+        for (int c = 0; c < kp; ++c) {
+            if (q) q[c] = 0.0f;
+            if (p) p[c] = 0.0f;
+        }
+        if (p) p[d] = 1.0e30f;
+        return;
+    }
+    double e2 = 0.0, nz = 0.0;
+    for (int c = 0; c < d; ++c) {
+        const double xc = (double)X[r * d + c] - (double)mu[c];
+        const float xt = (float)xc;
+        const double diff = xc - (double)xt;
+        e2 += diff * diff;
+        nz += (double)xt * (double)xt;
+        if (q) q[c] = xt;
+        if (p) p[c] = -2.0f * xt;
+    }
+    for (int c = d; c < kp; ++c) {
+        if (q) q[c] = (c == d) ? 1.0f : 0.0f;
+        if (p) p[c] = (c == d) ? (float)nz : 0.0f;
+    }
+    const double e = (e2 > 0.0) ? sqrt(e2) * (1.0 + 1.0e-12) : 0.0;
+    if (e_out) e_out[r] = e;
+    if (nz_out) nz_out[r] = nz;
+    if (emax_bits) atomicMax(emax_bits, (unsigned long long)__double_as_longlong(e));
+    if (nxmax_bits) atomicMax(nxmax_bits, (unsigned long long)__double_as_longlong(nz));
+}
+
+__global__ __launch_bounds__(256) void count_nonzero_kernel(const int32_t *__restrict__ a,
+                                                            int64_t n,
+                                                            unsigned long long *out) {
+    unsigned long long c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256)
+        c += (a[i] != 0);
+    for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m);
+    if (lane_id() == 0 && c) atomicAdd(out, c);
+}
+
+__global__ __launch_bounds__(256) void self_rows_kernel(int32_t *N, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) N[i] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(256) void zero_kernel(uint32_t *p, int64_t count) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * 256)
+        p[i] = 0u;
+}
+
+__global__ void accum_kernel(const int32_t *src, unsigned long long *dst) {
+    if (threadIdx.x == 0) atomicAdd(dst, (unsigned long long)(*src));
+}
+
+}  // namespace
+
+hipError_t launch_self_rows(int32_t *N, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(self_rows_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, N, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(void *ptr, int64_t count, hipStream_t s) {
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (uint32_t *)ptr, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_accum(const int32_t *src, unsigned long long *dst, hipStream_t s) {
+    hipLaunchKernelGGL(accum_kernel, dim3(1), dim3(64), 0, s, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_col_mean(const void *X, bool f64, int64_t n, int d, float *mu, hipStream_t s) {
+    if (f64)
+        hipLaunchKernelGGL(col_mean_kernel<double>, dim3(d), dim3(256), 0, s,
+                           (const double *)X, n, d, mu);
+    else
+        hipLaunchKernelGGL(col_mean_kernel<float>, dim3(d), dim3(256), 0, s, (const float *)X,
+                           n, d, mu);
+    return hipGetLastError();
+}
+
+hipError_t launch_finite_check(const void *A, bool f64, int64_t count, int *flag,
+                               hipStream_t s) {
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    if (f64)
+        hipLaunchKernelGGL(finite_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           (const double *)A, count, flag);
+    else
+        hipLaunchKernelGGL(finite_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           (const float *)A, count, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep_rows(const ScreenGeom &g, const float *X, int64_t n, int64_t n_pad, int d,
+                            const float *mu, void *Qrows, void *Prows, double *e_out,
+                            double *nz_out, unsigned long long *emax_bits,
+                            unsigned long long *nxmax_bits, hipStream_t s) {
+    const unsigned blocks = (unsigned)((n_pad + 255) / 256);
+    if (g.mode == SCREEN_BF16)
+        hipLaunchKernelGGL(prep_bf16_kernel, dim3(blocks), dim3(256), 0, s, X, n, n_pad, d, mu,
+                           g.kp, (uint16_t *)Qrows, (uint16_t *)Prows, e_out, nz_out, emax_bits,
+                           nxmax_bits);
+    else
+        hipLaunchKernelGGL(prep_f32_kernel, dim3(blocks), dim3(256), 0, s, X, n, n_pad, d, mu,
+                           g.kp, (float *)Qrows, (float *)Prows, e_out, nz_out, emax_bits,
+                           nxmax_bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_nonzero(const int32_t *a, int64_t n, unsigned long long *out,
+                                hipStream_t s) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(count_nonzero_kernel, dim3((unsigned)blocks), dim3(256), 0, s, a, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace fmg

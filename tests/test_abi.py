@@ -1,0 +1,85 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point the
+header declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fastmuygps.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fastmuygps_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2205_10879_amd as fmg
+    if not os.path.exists(fmg.LIB_PATH):
+        pytest.fail("HIP library not built: run `python -m paper_2205_10879_amd.build`")
+    return fmg.lib()
+
+
+def test_header_declares_the_paper_calls():
+    names = declared_functions()
+    for required in ("fastmuygps_build", "fastmuygps_predict", "fastmuygps_free",
+                     "fastmuygps_info", "fastmuygps_last_error"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    import paper_2205_10879_amd as fmg
+    names = declared_functions()
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(fmg.EXPORTS)
+
+
+def test_version(lib):
+    import paper_2205_10879_amd as fmg
+    assert fmg.version().startswith("fastmuygps-gfx950")
+
+
+def test_bad_arguments_fail_before_any_device_call(lib):
+    import paper_2205_10879_amd as fmg
+    h = ctypes.c_void_p()
+    hyper = fmg.FmgHyper(fmg.KERNEL_MATERN, 1.5, 1.0, 0.1, 1.0)
+    st = lib.fastmuygps_build(None, None, 10, 2, 1, 3, ctypes.byref(hyper), fmg.PREC_FP32, 0,
+                              None, ctypes.byref(h))
+    assert st == fmg.FMG_E_INVALID_ARG and not h.value
+    assert b"null" in lib.fastmuygps_last_error()
+    fake = ctypes.c_void_p(16)  # never dereferenced: arguments are checked first
+    for n, d, ell, k, prec, nu, rho, noise, flags in [
+            (1, 2, 1, 1, fmg.PREC_FP32, 1.5, 1.0, 0.1, 0),      # n < 2
+            (10, 0, 1, 3, fmg.PREC_FP32, 1.5, 1.0, 0.1, 0),     # d < 1
+            (10, 2, 0, 3, fmg.PREC_FP32, 1.5, 1.0, 0.1, 0),     # ell < 1
+            (10, 2, 17, 3, fmg.PREC_FP32, 1.5, 1.0, 0.1, 0),    # ell > 16
+            (10, 2, 1, 10, fmg.PREC_FP32, 1.5, 1.0, 0.1, 0),    # LOO k > n-1
+            (10, 2, 1, 11, fmg.PREC_FP32, 1.5, 1.0, 0.1, fmg.FLAG_SELF_INCLUSIVE),  # k > n
+            (100, 2, 1, 65, fmg.PREC_FP32, 1.5, 1.0, 0.1, 0),   # k > 64
+            (10, 2, 1, 3, fmg.PREC_FP32, 0.7, 1.0, 0.1, 0),     # nu
+            (10, 2, 1, 3, fmg.PREC_FP32, 1.5, 0.0, 0.1, 0),     # rho
+            (10, 2, 1, 3, fmg.PREC_FP32, 1.5, 1.0, -0.1, 0),    # noise
+            (10, 2, 1, 3, 7, 1.5, 1.0, 0.1, 0)]:                # precision
+        hy = fmg.FmgHyper(fmg.KERNEL_MATERN, nu, rho, noise, 1.0)
+        st = lib.fastmuygps_build(fake, fake, n, d, ell, k, ctypes.byref(hy), prec, flags, None,
+                                  ctypes.byref(h))
+        assert st == fmg.FMG_E_INVALID_ARG, (n, d, ell, k, prec, nu, rho, noise)
+    hy = fmg.FmgHyper(fmg.KERNEL_RBF, 0.0, 1.0, 0.1, 1.0)
+    st = lib.fastmuygps_build(fake, fake, 100, 62, 1, 3, ctypes.byref(hy), fmg.PREC_MIXED, 0,
+                              None, ctypes.byref(h))
+    assert st == fmg.FMG_E_UNSUPPORTED
+    st = lib.fastmuygps_predict(None, fake, 5, fake, None, None)
+    assert st == fmg.FMG_E_INVALID_ARG
+    lib.fastmuygps_free(None)
+
+
+def test_package_has_no_cpu_fallback():
+    """The product path never imports the oracle."""
+    import paper_2205_10879_amd as fmg
+    src = open(fmg.__file__).read()
+    assert "oracle" not in src.replace("no fallback", "")

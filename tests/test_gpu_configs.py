@@ -1,0 +1,104 @@
+"""GPU parity on the full-size workloads, in the launch configuration the
+benchmark times (one build of the whole training set, one predict of the whole
+query set), checked against the FP64 oracle:
+
+  cfg1  n=10,000  d=2   k=30 Matern 3/2  FP64   -> full oracle, every row and query
+  cfg2  n=100,000 d=8   k=50 Matern 5/2  FP32   -> sampled oracle
+  cfg3  n=1,000,000 d=40 k=50 RBF ell=10 MIXED  -> sampled oracle
+
+The sampled oracle recomputes, by brute force, the neighbour list and
+coefficient row of seeded sample rows, and the nearest point, neighbourhood,
+coefficients and mean of seeded sample queries."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.parity_util import TOL_MEAN, TOL_RMSE, backward_error, rel_err, rmse
+
+pytestmark = pytest.mark.gpu
+
+
+def fmg():
+    import paper_2205_10879_amd as f
+    return f
+
+
+def gpu_run(w):
+    f = fmg()
+    tdt = torch.float64 if w.precision == "fp64" else torch.float32
+    Xd = torch.from_numpy(np.ascontiguousarray(w.X)).to("cuda", tdt)
+    Yd = torch.from_numpy(np.ascontiguousarray(w.Y)).to("cuda", tdt)
+    Zd = torch.from_numpy(np.ascontiguousarray(w.Z)).to("cuda", tdt)
+    model = f.fastmuygps_build(Xd, Yd, w.k, w.kernel, w.nu, w.rho, w.noise, precision=w.precision)
+    nn = torch.empty(w.Z.shape[0], dtype=torch.int32, device="cuda")
+    mu = model.predict(Zd, nn_out=nn)
+    torch.cuda.synchronize()
+    res = dict(N=model.neighbors().cpu().numpy(), C=model.coeffs().cpu().numpy(),
+               mu=mu.cpu().numpy(), nn=nn.cpu().numpy(), info=model.info())
+    model.free()
+    del Xd, Yd, Zd
+    torch.cuda.empty_cache()
+    return res
+
+
+def sampled_check(w, res, rows, queries, prec):
+    X64 = w.X.astype(np.float64)
+    Y64 = w.Y.astype(np.float64)
+    Nr, Cr, st = oracle.build_model(X64, Y64, w.k, w.kernel, w.nu, w.rho, w.noise, rows=rows)
+    assert np.all(st == 0)
+    mism = np.nonzero(np.any(res["N"][rows] != Nr, axis=1))[0]
+    assert mism.size == 0, "neighbour lists differ on %d sampled rows" % mism.size
+    be = backward_error(X64, Y64, Nr[:64], res["C"][rows[:64]], w.kernel, w.nu, w.rho, w.noise)
+    assert np.max(be) < 1e-5
+    Zs = w.Z[queries].astype(np.float64)
+    mu, nn, _ = oracle.predict(X64, Y64, Zs, w.k, w.kernel, w.nu, w.rho, w.noise)
+    assert np.array_equal(res["nn"][queries], nn)
+    assert rel_err(res["mu"][queries], mu) <= TOL_MEAN[prec]
+    yq = w.Yz[queries]
+    assert abs(rmse(res["mu"][queries], yq) / rmse(mu, yq) - 1.0) <= TOL_RMSE
+    return mu
+
+
+def test_cfg1_fp64_full_oracle():
+    w = synth.cfg1()
+    res = gpu_run(w)
+    N, C, st = oracle.build_model(w.X, w.Y, w.k, w.kernel, w.nu, w.rho, w.noise)
+    assert np.array_equal(res["N"], N)
+    assert np.all(res["info"]["nonpd_rows"] == 0)
+    be = backward_error(w.X, w.Y, N[::97], res["C"][::97], w.kernel, w.nu, w.rho, w.noise)
+    assert np.max(be) < 1e-13
+    mu, nn, _ = oracle.predict(w.X, w.Y, w.Z, w.k, w.kernel, w.nu, w.rho, w.noise,
+                               model=(N, C, st))
+    assert np.array_equal(res["nn"], nn)
+    assert rel_err(res["mu"], mu) <= TOL_MEAN["fp64"]
+    assert abs(rmse(res["mu"], w.Yz) / rmse(mu, w.Yz) - 1.0) <= 1e-9
+
+
+def test_cfg2_fp32_sampled_oracle():
+    w = synth.cfg2()
+    res = gpu_run(w)
+    rs = synth.rng(2, 4)
+    rows = np.sort(rs.choice(w.X.shape[0], 400, replace=False))
+    queries = np.sort(rs.choice(w.Z.shape[0], 600, replace=False))
+    sampled_check(w, res, rows, queries, "fp32")
+    assert res["info"]["nonpd_rows"] == 0
+
+
+def test_cfg3_mixed_sampled_oracle():
+    w = synth.cfg3()
+    res = gpu_run(w)
+    rs = synth.rng(3, 4)
+    rows = np.sort(rs.choice(w.X.shape[0], 96, replace=False))
+    queries = np.sort(rs.choice(w.Z.shape[0], 160, replace=False))
+    sampled_check(w, res, rows, queries, "mixed")
+    assert res["info"]["nonpd_rows"] == 0
+    # classification accuracy on the whole test set (argmax of the one-hot means)
+    acc = float(np.mean(np.argmax(res["mu"], axis=1) == w.extra["labels_test"]))
+    assert acc > 0.9
+    # every neighbour list is a valid LOO list: distinct, no self, ascending distance
+    N = res["N"]
+    assert np.all(N != np.arange(N.shape[0])[:, None])
+    sample = N[rows]
+    assert all(len(set(r.tolist())) == r.size for r in sample)

@@ -1,0 +1,203 @@
+"""GPU parity at sizes the oracle finishes in seconds: several screen tiles,
+ragged tails, every precision mode, tie-heavy and duplicated inputs, and the
+degenerate cases of the method.  Everything goes through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.parity_util import TOL_MEAN, backward_error, rel_err
+
+pytestmark = pytest.mark.gpu
+
+DT = {"fp64": (np.float64, torch.float64), "fp32": (np.float32, torch.float32),
+      "mixed": (np.float32, torch.float32)}
+
+
+def fmg():
+    import paper_2205_10879_amd as f
+    return f
+
+
+def run(prec, X, Y, Z, k, kernel="matern", nu=1.5, rho=1.0, noise=1e-2, flags=0):
+    f = fmg()
+    npdt, tdt = DT[prec]
+    X = np.ascontiguousarray(X, dtype=npdt)
+    Y = np.ascontiguousarray(Y, dtype=npdt)
+    Z = np.ascontiguousarray(Z, dtype=npdt)
+    Xd = torch.from_numpy(X).cuda()
+    Yd = torch.from_numpy(Y).cuda()
+    Zd = torch.from_numpy(Z).cuda()
+    model = f.fastmuygps_build(Xd, Yd, k, kernel, nu, rho, noise, precision=prec, flags=flags)
+    nn = torch.empty(Z.shape[0], dtype=torch.int32, device="cuda")
+    mu = model.predict(Zd, nn_out=nn)
+    torch.cuda.synchronize()
+    out = dict(N=model.neighbors().cpu().numpy(), C=model.coeffs().cpu().numpy(),
+               mu=mu.cpu().numpy(), nn=nn.cpu().numpy(), info=model.info())
+    model.free()
+    return X, Y, Z, out
+
+
+def check_against_oracle(prec, X, Y, Z, k, kernel, nu, rho, noise, out, mode=oracle.MODE_LOO):
+    X64, Y64, Z64 = (np.asarray(a, dtype=np.float64) for a in (X, Y, Z))
+    N, C, st = oracle.build_model(X64, Y64, k, kernel, nu, rho, noise, 1.0, mode)
+    assert np.array_equal(out["N"], N), "neighbour lists differ from the oracle"
+    mu, nn, _ = oracle.predict(X64, Y64, Z64, k, kernel, nu, rho, noise, 1.0, mode,
+                               model=(N, C, st))
+    assert np.array_equal(out["nn"], nn), "nearest training points differ"
+    assert rel_err(out["mu"], mu) <= TOL_MEAN[prec]
+    be = backward_error(X64, Y64, N[:64], out["C"][:64], kernel, nu, rho, noise)
+    assert np.max(be) < (1e-13 if prec == "fp64" else 1e-5)
+    return N, C, mu
+
+
+# Length scales are chosen so that the neighbourhood matrices are moderately
+# conditioned (kappa <= ~1.6e3): the plain FP32 path's error grows like
+# kappa * u_32, and 2e-4 is only promised where kappa * u_32 is well below it.
+# test_ill_conditioned_needs_refinement covers larger kappa.
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+@pytest.mark.parametrize("n,m,d,k,ell,rho", [(3001, 777, 2, 30, 1, 0.05), (1500, 300, 8, 50, 3, 1.0),
+                                             (700, 130, 5, 17, 2, 0.5)])
+def test_small_parity(prec, n, m, d, k, ell, rho):
+    X, Y, Z = synth.small(n, m, d, ell=ell, seed=n + d, dist="normal")
+    X, Y, Z, out = run(prec, X, Y, Z, k, "matern", 2.5, rho, 1e-2)
+    check_against_oracle(prec, X, Y, Z, k, "matern", 2.5, rho, 1e-2, out)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+@pytest.mark.parametrize("kernel,nu", [("rbf", 0.0), ("matern", 0.5), ("matern", 1.5)])
+def test_kernels(prec, kernel, nu):
+    X, Y, Z = synth.small(900, 200, 3, ell=1, seed=7, dist="uniform")
+    X, Y, Z, out = run(prec, X, Y, Z, 20, kernel, nu, 0.05, 1e-3)
+    check_against_oracle(prec, X, Y, Z, 20, kernel, nu, 0.05, 1e-3, out)
+
+
+@pytest.mark.parametrize("rho,kernel,nu", [(1.0, "matern", 2.5), (0.3, "rbf", 0.0)])
+def test_ill_conditioned_needs_refinement(rho, kernel, nu):
+    """kappa ~ 3e3 .. 2e4.  The refined MIXED coefficients are accurate to the
+    FP32 storage of C: the remaining mean error is bounded by the rounding of
+    the dot product sum_s |phi_s C_s| in FP32, which refinement cannot remove.
+    The plain FP32 coefficients also carry the kappa * u_32 solve error, so
+    refinement must never be worse."""
+    d = 2 if kernel == "matern" else 3
+    k = 20
+    X, Y, Z = synth.small(3001, 400, d, ell=1, seed=31, dist="normal" if d == 2 else "uniform")
+    errs = {}
+    for prec in ("mixed", "fp32"):
+        Xp, Yp, Zp, out = run(prec, X, Y, Z, k, kernel, nu, rho, 1e-3)
+        X64, Y64, Z64 = (np.asarray(a, dtype=np.float64) for a in (Xp, Yp, Zp))
+        N, C, st = oracle.build_model(X64, Y64, k, kernel, nu, rho, 1e-3)
+        assert np.array_equal(out["N"], N)
+        mu, nn, _ = oracle.predict(X64, Y64, Z64, k, kernel, nu, rho, 1e-3, model=(N, C, st))
+        assert np.array_equal(out["nn"], nn)
+        errs[prec] = rel_err(out["mu"], mu)
+    # cancellation factor of the prediction dot product
+    rms = float(np.sqrt(np.mean(mu * mu)))
+    cs = 0.0
+    for t in range(Z64.shape[0]):
+        nb = N[nn[t]]
+        w = oracle.phi(((X64[nb] - Z64[t]) ** 2).sum(axis=1), kernel, nu, rho, 1.0)
+        cs = max(cs, float(np.sum(np.abs(w * C[nn[t], :, 0]))) / max(abs(mu[t, 0]), rms))
+    bound = 4.0 * k * np.finfo(np.float32).eps * cs
+    assert errs["mixed"] <= max(TOL_MEAN["mixed"], bound), (errs, bound)
+    assert errs["mixed"] <= errs["fp32"], errs
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+def test_integer_grid_ties(prec):
+    # exact distance ties everywhere: the index tie-break decides
+    X, Y, Z = synth.small(1200, 300, 2, ell=1, seed=3, dist="grid")
+    X, Y, Z, out = run(prec, X, Y, Z, 24, "matern", 1.5, 4.0, 1e-1)
+    check_against_oracle(prec, X, Y, Z, 24, "matern", 1.5, 4.0, 1e-1, out)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+def test_duplicated_points(prec):
+    X, Y, Z = synth.small(800, 100, 3, ell=2, seed=4, dist="dups")
+    X, Y, Z, out = run(prec, X, Y, Z, 10, "rbf", 0.0, 1.0, 5e-2)
+    check_against_oracle(prec, X, Y, Z, 10, "rbf", 0.0, 1.0, 5e-2, out)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+def test_self_inclusive_mode(prec):
+    f = fmg()
+    X, Y, Z = synth.small(600, 90, 4, ell=1, seed=5)
+    X, Y, Z, out = run(prec, X, Y, Z, 12, "matern", 2.5, 1.0, 1e-2, flags=f.FLAG_SELF_INCLUSIVE)
+    check_against_oracle(prec, X, Y, Z, 12, "matern", 2.5, 1.0, 1e-2, out, oracle.MODE_SELF)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+def test_k_is_n_minus_1_and_tiny_n(prec):
+    for n, k in ((2, 1), (3, 2), (65, 64), (130, 64)):
+        X, Y, Z = synth.small(n, 7, 2, ell=1, seed=n)
+        X, Y, Z, out = run(prec, X, Y, Z, k, "matern", 1.5, 1.0, 1e-1)
+        check_against_oracle(prec, X, Y, Z, k, "matern", 1.5, 1.0, 1e-1, out)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+def test_query_on_training_point_reproduces_loo_prediction(prec):
+    X, Y, _ = synth.small(2000, 1, 3, ell=1, seed=9)
+    rows = np.arange(0, 2000, 37)
+    X, Y, Z, out = run(prec, X, Y, X[rows], 16, "matern", 2.5, 0.3, 1e-2)
+    assert np.array_equal(out["nn"], rows)
+    X64, Y64 = X.astype(np.float64), Y.astype(np.float64)
+    for t, i in enumerate(rows[:10]):
+        nb = oracle.neighborhood(X64, int(i), 16)
+        K = oracle.assemble(X64, nb, "matern", 2.5, 0.3, 1e-2, 1.0)
+        kz = oracle.phi(((X64[nb] - X64[i]) ** 2).sum(axis=1), "matern", 2.5, 0.3, 1.0)
+        ref = kz @ np.linalg.solve(K, Y64[nb, 0])
+        assert abs(out["mu"][t, 0] - ref) <= TOL_MEAN[prec] * max(abs(ref), 1.0)
+
+
+def test_empty_and_single_query():
+    f = fmg()
+    X, Y, Z = synth.small(500, 1, 2, ell=1, seed=11)
+    Xd = torch.from_numpy(X.astype(np.float32)).cuda()
+    Yd = torch.from_numpy(Y.astype(np.float32)).cuda()
+    model = f.fastmuygps_build(Xd, Yd, 8, "matern", 1.5, 1.0, 1e-2, precision="mixed")
+    empty = model.predict(torch.empty((0, 2), dtype=torch.float32, device="cuda"))
+    assert empty.shape == (0, 1)
+    one = model.predict(torch.from_numpy(Z.astype(np.float32)).cuda())
+    torch.cuda.synchronize()
+    assert one.shape == (1, 1) and np.isfinite(one.cpu().numpy()).all()
+    model.free()
+
+
+def test_invalid_arguments_are_rejected():
+    f = fmg()
+    X = torch.zeros((10, 2), dtype=torch.float32, device="cuda")
+    Y = torch.zeros((10, 1), dtype=torch.float32, device="cuda")
+    with pytest.raises(f.FmgError) as e:
+        f.fastmuygps_build(X, Y, 10, "matern", 1.5, 1.0, 0.1, precision="fp32")  # k > n-1
+    assert e.value.status == f.FMG_E_INVALID_ARG
+    with pytest.raises(f.FmgError):
+        f.fastmuygps_build(X, Y, 3, "matern", 0.75, 1.0, 0.1, precision="fp32")  # nu
+    with pytest.raises(f.FmgError):
+        f.fastmuygps_build(X, Y, 3, "matern", 1.5, -1.0, 0.1, precision="fp32")  # rho
+    Xn = X.clone()
+    Xn[3, 1] = float("nan")
+    with pytest.raises(f.FmgError) as e:
+        f.fastmuygps_build(Xn, Y, 3, "matern", 1.5, 1.0, 0.1, precision="mixed")
+    assert e.value.status == f.FMG_E_INVALID_ARG
+    with pytest.raises(f.FmgError) as e:
+        f.fastmuygps_build(torch.zeros((10, 70), dtype=torch.float32, device="cuda"), Y, 3,
+                           precision="mixed")
+    assert e.value.status == f.FMG_E_UNSUPPORTED
+
+
+def test_not_positive_definite_rows_are_flagged():
+    f = fmg()
+    X = np.array([[0.0], [1.0], [1.0], [2.0], [5.0], [6.0]])
+    Y = np.arange(6.0)[:, None]
+    Xd = torch.from_numpy(X).cuda()
+    Yd = torch.from_numpy(Y).cuda()
+    model = f.fastmuygps_build(Xd, Yd, 3, "rbf", 0.0, 1.0, 0.0, precision="fp64",
+                               allow_not_pd=True)
+    assert model.build_status == f.FMG_E_NOT_PD
+    N, C, st = oracle.build_model(X, Y, 3, "rbf", 0.0, 1.0, 0.0)
+    info = model.info()
+    assert info["nonpd_rows"] == int((st != 0).sum()) > 0
+    Cg = model.coeffs().cpu().numpy()
+    assert np.array_equal(np.isnan(Cg).all(axis=(1, 2)), st != 0)
+    model.free()
