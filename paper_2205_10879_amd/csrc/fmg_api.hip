@@ -311,7 +311,7 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
         uint64_t *pool = nullptr, *cand = nullptr;
         float *tq = nullptr;
         int32_t *fbl = nullptr, *fbc = nullptr;
-        HCHK(tmp.alloc((void **)&pool, (size_t)n_pad * SCREEN_CAP * 8), "screen pool");
+        HCHK(tmp.alloc((void **)&pool, (size_t)n_pad * screen_cap(c) * 8), "screen pool");
         HCHK(tmp.alloc((void **)&cand, (size_t)n * c * 8), "scratch");
         HCHK(tmp.alloc((void **)&tq, (size_t)n * 4), "scratch");
         HCHK(tmp.alloc((void **)&fbl, (size_t)n * 4), "scratch");
@@ -478,7 +478,7 @@ fmg_status fastmuygps_predict(const fmg_model *model, const void *Z, int64_t m, 
         uint64_t *pool = nullptr, *cand = nullptr;
         float *tq = nullptr;
         int32_t *fbl = nullptr, *fbc = nullptr;
-        HIPCHK(tmp.alloc((void **)&pool, (size_t)splits * m_pad * SCREEN_CAP * 8), "screen pool");
+        HIPCHK(tmp.alloc((void **)&pool, (size_t)splits * m_pad * screen_cap(c) * 8), "screen pool");
         HIPCHK(tmp.alloc((void **)&cand, (size_t)splits * m * c * 8), "scratch");
         HIPCHK(tmp.alloc((void **)&tq, (size_t)splits * m * 4), "scratch");
         HIPCHK(tmp.alloc((void **)&fbl, (size_t)m * 4), "scratch");

@@ -14,8 +14,9 @@ enum ScreenMode { SCREEN_BF16 = 0, SCREEN_F32 = 1 };
 constexpr int SCREEN_TILE = 64;
 // Queries per screen workgroup (4 waves x 64 queries).
 constexpr int SCREEN_QPB = 256;
-// Pool entries per query in the screen (candidate keys awaiting selection).
-constexpr int SCREEN_CAP = 512;
+// Pool entries per query in the screen (candidate keys awaiting selection):
+// 128 for c <= 64 kept candidates, 256 for c <= 192.
+constexpr int screen_cap(int c) { return c > 64 ? 256 : 128; }
 
 // Row layout of the screening arrays: `kp` elements per row (bf16 or f32),
 // row bytes = kp * elem.  bf16: kp = 64 (2 MFMA k-steps of 32); f32: kp a
@@ -35,8 +36,8 @@ struct ScreenArgs {
     int64_t col_chunk;  // candidate columns per split (multiple of SCREEN_TILE)
     int splits;
     int loo;            // 1: query q never takes candidate q
-    int c;              // candidates kept per (query, split), <= SCREEN_CAP - SCREEN_TILE
-    uint64_t *pool;     // [splits, m_pad, SCREEN_CAP] scratch
+    int c;              // candidates kept per (query, split), <= screen_cap(c) - SCREEN_TILE
+    uint64_t *pool;     // [splits, m_pad, screen_cap(c)] scratch
     uint64_t *cand;     // [splits, m, c] sorted screen keys (value, index)
     float *tq;          // [splits, m] c-th kept value, +inf when fewer than c
 };

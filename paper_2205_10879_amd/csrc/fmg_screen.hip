@@ -16,12 +16,15 @@
 //   workgroup = 4 waves x 64 queries; each wave holds its queries' operand
 //   fragments in registers for the whole column range;
 //   per iteration the workgroup stages 64 candidate rows in LDS (double
-//   buffered, rows padded by 16 bytes against bank conflicts) and every wave
-//   runs 4 (query tiles) x 4 (candidate tiles) x KSTEPS MFMAs;
+//   buffered, loaded by LDS-DMA one tile ahead, 16-byte chunks XOR-swizzled
+//   against bank conflicts) and every wave runs 4 (query tiles) x
+//   4 (candidate tiles) x KSTEPS MFMAs;
 //   lane l of a 16x16 result holds candidates 4*(l/16)+i (i < 4) of the tile
 //   for query l%16 of the tile.
 #include "fmg_device.h"
 #include "fmg_kernels.h"
+
+#include <type_traits>
 
 namespace fmg {
 
@@ -52,49 +55,164 @@ struct OpF32 {
 };
 
 constexpr int TILE = SCREEN_TILE;
-constexpr int CAP = SCREEN_CAP;
-constexpr int PE = CAP / 64;  // pool entries per lane during a selection
 
-// Sort the pool of one query (cnt entries), keep the best c in slots 0..c-1.
-// Returns the c-th key (SKEY_EMPTY when fewer than c entries).
-__device__ __forceinline__ uint64_t select_pool(uint64_t *__restrict__ pool, int cnt, int c,
-                                                int lane) {
+// Pool entries hold the raw pair (index << 32 | float bits of S'); selection
+// works on keys (orderable value << 32 | index), which order by (S', index).
+__device__ __forceinline__ uint64_t raw_entry(float v, uint32_t p) {
+    return ((uint64_t)p << 32) | (uint64_t)__float_as_uint(v);
+}
+__device__ __forceinline__ uint64_t raw_to_key(uint64_t r) {
+    return ((uint64_t)fkey(__uint_as_float((uint32_t)r)) << 32) | (r >> 32);
+}
+__device__ __forceinline__ uint64_t key_to_raw(uint64_t k) {
+    return ((uint64_t)(uint32_t)k << 32) | (uint64_t)__float_as_uint(skey_val(k));
+}
+
+__device__ __forceinline__ int wave_sum_int(int v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint64_t o = shfl_u64(v, lane_id() ^ m);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Radix selection (8-bit digits, most significant first) of the c-th
+// smallest of the wave's 64*PE keys (~0 marks an empty slot).  Returns a bound
+// B such that exactly the c smallest keys satisfy key <= B, or ~0 when fewer
+// than c keys are present (keep them all).  hist: 256 words of LDS.
+template <int PE>
+__device__ __forceinline__ uint64_t radix_kth(const uint64_t (&key)[PE], int c,
+                                              uint32_t *__restrict__ hist, int lane) {
+    int valid = 0;
+#pragma unroll
+    for (int e = 0; e < PE; ++e) valid += __popcll(__ballot(key[e] != ~0ull));
+    if (valid <= c) return ~0ull;
+    uint64_t prefix = 0;
+    int need = c;
+    for (int r = 0; r < 8; ++r) {
+        const int shift = 56 - 8 * r;
+        ((uint4 *)hist)[lane] = uint4{0u, 0u, 0u, 0u};
+        wave_lds_sync();
+#pragma unroll
+        for (int e = 0; e < PE; ++e) {
+            const bool in = key[e] != ~0ull && (r == 0 || (key[e] >> (shift + 8)) == (prefix >> (shift + 8)));
+            if (in) atomicAdd(&hist[(uint32_t)(key[e] >> shift) & 255u], 1u);
+        }
+        wave_lds_sync();
+        const uint4 h = ((const uint4 *)hist)[lane];
+        const int own = (int)(h.x + h.y + h.z + h.w);
+        int incl = own;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int o = __shfl_up(incl, d);
+            if (lane >= d) incl += o;
+        }
+        const int excl = incl - own;
+        const bool mine = excl < need && need <= incl;
+        int bin = 3, before = excl + (int)(h.x + h.y + h.z), inbin = (int)h.w;
+        if (excl + (int)(h.x + h.y + h.z) >= need) { bin = 2; before = excl + (int)(h.x + h.y); inbin = (int)h.z; }
+        if (excl + (int)(h.x + h.y) >= need) { bin = 1; before = excl + (int)h.x; inbin = (int)h.y; }
+        if (excl + (int)h.x >= need) { bin = 0; before = excl; inbin = (int)h.x; }
+        const int L = __ffsll((long long)__ballot(mine)) - 1;
+        const int digit = L * 4 + __builtin_amdgcn_readlane(bin, L);
+        const int cb = __builtin_amdgcn_readlane(before, L);
+        const int cin = __builtin_amdgcn_readlane(inbin, L);
+        prefix |= (uint64_t)digit << shift;
+        need -= cb;
+        wave_lds_sync();
+        if (cin == need) return prefix | ((shift > 0) ? ((1ull << shift) - 1ull) : 0ull);
+    }
+    return prefix;
+}
+
+// Keep the c smallest entries of one query's pool (four sub-pools of SUB
+// entries, counts cg[0..3]).  Entries of the query's own index (leave-one-out)
+// and of padding candidates (index >= n) are dropped here: the screen appends
+// without checking them.  The kept entries go back to the sub-pools round
+// robin (final == false) or to the LDS staging array in any order
+// (final == true).  Returns the kept count; *kmax = largest kept key (~0 if
+// fewer than c were present, meaning no threshold yet).
+template <int PE, int SUB>
+__device__ __forceinline__ int select_pool(uint64_t *__restrict__ qpool, const int (&cg)[4], int c,
+                                           uint32_t self, uint32_t n,
+                                           uint32_t *__restrict__ hist,
+                                           uint64_t *__restrict__ stage, bool final,
+                                           uint64_t *kmax) {
+    const int lane = lane_id();
     uint64_t key[PE];
 #pragma unroll
     for (int e = 0; e < PE; ++e) {
         const int slot = lane * PE + e;
-        key[e] = slot < cnt ? pool[slot] : SKEY_EMPTY;
+        const int g = slot / SUB, idx = slot % SUB;
+        const int cnt = g == 0 ? cg[0] : g == 1 ? cg[1] : g == 2 ? cg[2] : cg[3];
+        key[e] = ~0ull;
+        if (idx < cnt) {
+            const uint64_t r = qpool[g * SUB + idx];
+            const uint32_t p = (uint32_t)(r >> 32);
+            if (p != self && p < n) key[e] = raw_to_key(r);
+        }
     }
-    wave_sort_u64<PE>(key);
+    const uint64_t bound = radix_kth<PE>(key, c, hist, lane);
+    const uint64_t lt = (1ull << lane) - 1ull;
+    int base = 0;
+    uint64_t mx = 0;
 #pragma unroll
     for (int e = 0; e < PE; ++e) {
-        const int slot = lane * PE + e;
-        if (slot < c) pool[slot] = key[e];
+        const bool keep = key[e] != ~0ull && key[e] <= bound;
+        const uint64_t m = __ballot(keep);
+        if (keep) {
+            const int pos = base + __popcll(m & lt);
+            if (final)
+                stage[pos] = key[e];
+            else
+                qpool[(pos & 3) * SUB + (pos >> 2)] = key_to_raw(key[e]);
+            mx = key[e] > mx ? key[e] : mx;
+        }
+        base += __popcll(m);
     }
-    const int cl = (c - 1) / PE, ce = (c - 1) % PE;
-    uint64_t kc = SKEY_EMPTY;
-#pragma unroll
-    for (int e = 0; e < PE; ++e)
-        if (e == ce) kc = readlane_u64(key[e], cl);
-    return kc;
+    *kmax = (bound == ~0ull) ? ~0ull : wave_max_u64(mx);
+    return base;
 }
 
-template <class Op, int KSTEPS>
+template <class Op, int KSTEPS, int CAP>
 __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
     constexpr int RB = 4 * KSTEPS * Op::BPS;  // row bytes
-    constexpr int LR = RB + 16;               // LDS row stride
-    constexpr int CPT = (TILE * RB / 16) / 256;  // 16-byte chunks per thread per tile
-    static_assert(CPT >= 1 && (TILE * RB / 16) % 256 == 0, "tile load split");
-    __shared__ __align__(16) char tile[2][TILE * LR];
+    constexpr int CH = RB / 16;               // 16-byte chunks per row
+    constexpr int SWZ = (CH % 8 == 0) ? 7 : 3;  // chunk XOR swizzle (bank spread)
+    constexpr int LDI = CH / 4;               // LDS-DMA loads per wave per tile
+    constexpr int SUB = CAP / 4;              // sub-pool per lane group
+    constexpr int TRIG = SUB - 16;            // select when a sub-pool exceeds this
+    constexpr int PE = CAP / 64;
+    static_assert(CH % 4 == 0, "tile load split");
+    // Candidate tiles: 64 rows x RB bytes, unpadded; 16-byte chunk c of row r
+    // is stored at chunk position c ^ (r & SWZ).
+    __shared__ __align__(16) char tile0[TILE * RB];
+    __shared__ __align__(16) char tile1[TILE * RB];
+    __shared__ __align__(16) uint32_t hist_all[4][256];
+    __shared__ __align__(16) uint64_t stage_all[4][CAP];
 
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
     const int g = lane >> 4, r16 = lane & 15;
-    const int64_t wq0 = (int64_t)blockIdx.x * SCREEN_QPB + wave * 64;
+    const int wq0 = (int)blockIdx.x * SCREEN_QPB + wave * 64;
     const int split = blockIdx.y;
-    const int64_t cb = (int64_t)split * a.col_chunk;
-    const int64_t ce = (cb + a.col_chunk < a.n_pad) ? cb + a.col_chunk : a.n_pad;
+    const int cb = split * (int)a.col_chunk;
+    const int ce = (cb + a.col_chunk < a.n_pad) ? cb + (int)a.col_chunk : (int)a.n_pad;
+    const int n_real = (int)a.n, m_real = (int)a.m;
     const char *__restrict__ Pb = (const char *)a.P;
+    uint32_t *hist = hist_all[wave];
+    uint64_t *stage = stage_all[wave];
 
     // Query fragments, held for the whole column range.
     typename Op::frag_t bq[4][KSTEPS];
@@ -106,128 +224,168 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
     }
     float thr[4];
     int cnt[4];
+    // pool of query (wave query ql), sub-pool gg: pool + ((ql * 4) + gg) * SUB
+    uint64_t *__restrict__ pool = a.pool + ((int64_t)split * a.m_pad + wq0) * CAP;
+    // this lane's sub-pool of query tile t starts at mysub + t * 64 * SUB
+    uint64_t *const mysub = pool + (r16 * 4 + g) * SUB;
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        const int64_t q = wq0 + t * 16 + r16;
-        thr[t] = (q < a.m) ? INFINITY : -INFINITY;  // padding queries never append
+        const int q = wq0 + t * 16 + r16;
+        thr[t] = (q < m_real) ? INFINITY : -INFINITY;  // padding queries never append
         cnt[t] = 0;
     }
-    const uint64_t sq = 0x0001000100010001ull << r16;          // lanes sharing my query
-    const uint64_t lsq = sq & ((1ull << lane) - 1ull);          // ... below me
-    uint64_t *__restrict__ pool = a.pool + ((int64_t)split * a.m_pad + wq0) * CAP;
 
-    uint4 pre[CPT];
-    auto gload = [&](int64_t col0) {
+    // Tile loads go straight from global memory to LDS (global_load_lds):
+    // wave w fills slots [w*LDI*64, (w+1)*LDI*64), lane l of load j writes slot
+    // (w*LDI + j)*64 + l, i.e. row slot/CH, chunk position slot%CH.
+    auto load_tile = [&](int col0, char *dst) {
 #pragma unroll
-        for (int i = 0; i < CPT; ++i) {
-            const int chunk = threadIdx.x + i * 256;
-            const int row = chunk / (RB / 16), off = (chunk % (RB / 16)) * 16;
-            pre[i] = *(const uint4 *)(Pb + (col0 + row) * RB + off);
+        for (int j = 0; j < LDI; ++j) {
+            const int slot = (wave * LDI + j) * 64 + lane;
+            const int r = slot / CH, pc = slot % CH;
+            const int c = pc ^ (r & SWZ);
+            const char *src = Pb + (size_t)(col0 + r) * RB + c * 16;
+            __builtin_amdgcn_global_load_lds(
+                (const void *)src,
+                (__attribute__((address_space(3))) void *)(dst + (wave * LDI + j) * 1024), 16, 0, 0);
         }
     };
-    auto lstore = [&](int buf) {
+    // This lane's fragment offsets inside a tile (row r16 of each 16-row block).
+    int frag_off[KSTEPS];
 #pragma unroll
-        for (int i = 0; i < CPT; ++i) {
-            const int chunk = threadIdx.x + i * 256;
-            const int row = chunk / (RB / 16), off = (chunk % (RB / 16)) * 16;
-            *(uint4 *)(tile[buf] + row * LR + off) = pre[i];
-        }
-    };
-
-    if (cb < ce) {
-        gload(cb);
-        lstore(0);
+    for (int s = 0; s < KSTEPS; ++s) {
+        const int byte = g * KSTEPS * Op::BPS + s * Op::BPS;
+        frag_off[s] = r16 * RB + (((byte >> 4) ^ (r16 & SWZ)) << 4) + (byte & 15);
     }
+
+    // Counts of the four sub-pools of wave query (t, rl).
+    auto counts = [&](int t, int rl, int (&cg)[4]) {
+        const int ct = t == 0 ? cnt[0] : t == 1 ? cnt[1] : t == 2 ? cnt[2] : cnt[3];
+#pragma unroll
+        for (int gg = 0; gg < 4; ++gg) cg[gg] = __builtin_amdgcn_readlane(ct, rl + 16 * gg);
+    };
+
+    // Select in every query of the wave with a sub-pool above the trigger.
+    auto flush_full = [&]() {
+        for (int t = 0; t < 4; ++t) {
+            const int ct = t == 0 ? cnt[0] : t == 1 ? cnt[1] : t == 2 ? cnt[2] : cnt[3];
+            const uint64_t m = __ballot(ct > TRIG);
+            uint64_t need = (m | (m >> 16) | (m >> 32) | (m >> 48)) & 0xffffull;
+            while (need != 0) {
+                const int rl = __ffsll((long long)need) - 1;
+                need &= need - 1;
+                int cg[4];
+                counts(t, rl, cg);
+                uint64_t kmax;
+                const uint32_t self = a.loo ? (uint32_t)(wq0 + t * 16 + rl) : 0xffffffffu;
+                const int kept = select_pool<PE, SUB>(pool + (t * 16 + rl) * 4 * SUB, cg, a.c, self,
+                                                      (uint32_t)n_real, hist, stage, false, &kmax);
+                if (r16 == rl) {
+                    const int nc = (kept + 3 - g) >> 2;
+                    const float nt = skey_val(kmax);
+#pragma unroll
+                    for (int tt = 0; tt < 4; ++tt) {
+                        if (tt == t) {
+                            cnt[tt] = nc;
+                            if (kmax != ~0ull) thr[tt] = nt;
+                        }
+                    }
+                }
+            }
+        }
+    };
+
+    if (cb < ce) load_tile(cb, tile0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    int buf = 0;
-    for (int64_t col = cb; col < ce; col += TILE) {
-        const bool has_next = col + TILE < ce;
-        if (has_next) gload(col + TILE);
+    // One candidate tile: MFMA screen of the tile in `cur` while the next tile
+    // streams into `nxt`, then candidate selection.
+    auto step = [&](int col, const char *cur, char *nxt) {
+        if (col + TILE < ce) load_tile(col + TILE, nxt);
 
         f32x4 acc[4][4];
 #pragma unroll
         for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) acc[t][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-        const char *tb = tile[buf] + r16 * LR + g * KSTEPS * Op::BPS;
 #pragma unroll
         for (int s = 0; s < KSTEPS; ++s) {
             typename Op::frag_t af[4];
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) af[mt] = Op::load(tb + mt * 16 * LR + s * Op::BPS);
+            for (int mt = 0; mt < 4; ++mt) af[mt] = Op::load(cur + mt * 16 * RB + frag_off[s]);
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int mt = 0; mt < 4; ++mt) acc[t][mt] = Op::mfma(af[mt], bq[t][s], acc[t][mt]);
         }
 
-        // Candidate selection.
-        bool appended = false;
+        // Candidate selection: one compare per value; a 16x16 tile whose four
+        // values fail in every lane costs one wave-wide test, otherwise each
+        // passing lane appends to its own sub-pool.  The query's own index and
+        // padding candidates may be appended here; the selection drops them.
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            float mn = acc[t][0][0];
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt)
+            for (int mt = 0; mt < 4; ++mt) {
+                bool pass[4];
+                uint64_t any = 0;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) mn = fminf(mn, acc[t][mt][i]);
-            if (__ballot(mn <= thr[t]) != 0) {
-                appended = true;
-                const int64_t self = a.loo ? wq0 + t * 16 + r16 : -1;
-                uint64_t *__restrict__ qp = pool + (t * 16 + r16) * CAP;
-#pragma unroll
-                for (int mt = 0; mt < 4; ++mt) {
+                for (int i = 0; i < 4; ++i) {
+                    pass[i] = acc[t][mt][i] <= thr[t];
+                    any |= __ballot(pass[i]);
+                }
+                if (any != 0) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const int64_t p = col + mt * 16 + g * 4 + i;
-                        const float v = acc[t][mt][i];
-                        const bool pass = (v <= thr[t]) && (p != self) && (p < a.n);
-                        const uint64_t mask = __ballot(pass);
-                        if (mask != 0) {
-                            const int below = __popcll(mask & lsq);
-                            const int tot = __popcll(mask & sq);
-                            if (pass) qp[cnt[t] + below] = skey(v, (uint32_t)p);
-                            cnt[t] += tot;
+                        if (pass[i]) {
+                            const uint32_t p = (uint32_t)(col + mt * 16 + g * 4 + i);
+                            mysub[(uint32_t)(t * 64 * SUB) + (uint32_t)cnt[t]] =
+                                raw_entry(acc[t][mt][i], p);
+                            cnt[t] += 1;
                         }
                     }
                 }
             }
         }
-        if (appended) {
-            // Select in every pool that could overflow during the next tile.
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                uint64_t need = __ballot(cnt[t] > CAP - TILE) & 0xffffull;
-                while (need != 0) {
-                    const int rl = __ffsll((long long)need) - 1;
-                    need &= need - 1;
-                    const int c_now = __builtin_amdgcn_readlane(cnt[t], rl);
-                    const uint64_t kc = select_pool(pool + (t * 16 + rl) * CAP, c_now, a.c, lane);
-                    if (r16 == rl) {
-                        cnt[t] = a.c < c_now ? a.c : c_now;
-                        if (kc != SKEY_EMPTY) thr[t] = skey_val(kc);
-                    }
-                }
-            }
-        }
-        if (has_next) lstore(buf ^ 1);
+        // Select in every query whose sub-pool could overflow during the next tile.
+        if (__ballot(cnt[0] > TRIG || cnt[1] > TRIG || cnt[2] > TRIG || cnt[3] > TRIG) != 0)
+            flush_full();
+        // the next tile must have landed in LDS before any wave reads it
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
-        buf ^= 1;
+    };
+    for (int col = cb; col < ce; col += 2 * TILE) {
+        step(col, tile0, tile1);
+        if (col + TILE < ce) step(col + TILE, tile1, tile0);
     }
 
-    // Final selection and output of every real query of this wave.
+    // Final selection, sort and output of every real query of this wave.
     for (int ql = 0; ql < 64; ++ql) {
-        const int64_t q = wq0 + ql;
-        if (q >= a.m) break;
-        const int t = ql >> 4, rl = ql & 15;
-        int c_now = 0;
+        const int q = wq0 + ql;
+        if (q >= m_real) break;
+        int cg[4];
+        counts(ql >> 4, ql & 15, cg);
+        uint64_t kmax;
+        const uint32_t self = a.loo ? (uint32_t)q : 0xffffffffu;
+        const int kept = select_pool<PE, SUB>(pool + ql * 4 * SUB, cg, a.c, self, (uint32_t)n_real,
+                                              hist, stage, true, &kmax);
+        wave_lds_sync();
+        uint64_t key[PE];
 #pragma unroll
-        for (int tt = 0; tt < 4; ++tt)
-            if (tt == t) c_now = __builtin_amdgcn_readlane(cnt[tt], rl);
-        uint64_t *qp = pool + ql * CAP;
-        const uint64_t kc = select_pool(qp, c_now, a.c, lane);
+        for (int e = 0; e < PE; ++e) {
+            const int slot = lane * PE + e;
+            key[e] = slot < kept ? stage[slot] : ~0ull;
+        }
+        wave_sort_u64<PE>(key);
         uint64_t *__restrict__ out = a.cand + ((int64_t)split * a.m + q) * a.c;
-        for (int r = lane; r < a.c; r += 64) out[r] = r < c_now ? qp[r] : SKEY_EMPTY;
-        if (lane == 0) a.tq[(int64_t)split * a.m + q] = (kc != SKEY_EMPTY) ? skey_val(kc) : INFINITY;
+#pragma unroll
+        for (int e = 0; e < PE; ++e) {
+            const int slot = lane * PE + e;
+            if (slot < a.c) out[slot] = key[e];
+        }
+        if (lane == 0)
+            a.tq[(int64_t)split * a.m + q] = (kmax != ~0ull) ? skey_val(kmax) : INFINITY;
+        wave_lds_sync();
     }
 }
 
@@ -235,20 +393,28 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
 
 hipError_t launch_screen(const ScreenGeom &g, const ScreenArgs &a, hipStream_t s) {
     dim3 grid((unsigned)(a.m_pad / SCREEN_QPB), (unsigned)a.splits);
+    const bool big = a.c > 64;  // pool of 256 entries, else 128
+    if (a.c > screen_cap(a.c) - SCREEN_TILE) return hipErrorInvalidValue;
+#define FMG_SCREEN_LAUNCH(OP, KS)                                                            \
+    do {                                                                                     \
+        if (big)                                                                             \
+            hipLaunchKernelGGL((screen_kernel<OP, KS, 256>), grid, dim3(256), 0, s, a);      \
+        else                                                                                 \
+            hipLaunchKernelGGL((screen_kernel<OP, KS, 128>), grid, dim3(256), 0, s, a);      \
+    } while (0)
     if (g.mode == SCREEN_BF16) {
-        if (g.ksteps == 2)
-            hipLaunchKernelGGL((screen_kernel<OpBF16, 2>), grid, dim3(256), 0, s, a);
-        else
-            return hipErrorInvalidValue;
+        if (g.ksteps != 2) return hipErrorInvalidValue;
+        FMG_SCREEN_LAUNCH(OpBF16, 2);
     } else {
         switch (g.ksteps) {
-        case 4: hipLaunchKernelGGL((screen_kernel<OpF32, 4>), grid, dim3(256), 0, s, a); break;
-        case 8: hipLaunchKernelGGL((screen_kernel<OpF32, 8>), grid, dim3(256), 0, s, a); break;
-        case 12: hipLaunchKernelGGL((screen_kernel<OpF32, 12>), grid, dim3(256), 0, s, a); break;
-        case 16: hipLaunchKernelGGL((screen_kernel<OpF32, 16>), grid, dim3(256), 0, s, a); break;
+        case 4: FMG_SCREEN_LAUNCH(OpF32, 4); break;
+        case 8: FMG_SCREEN_LAUNCH(OpF32, 8); break;
+        case 12: FMG_SCREEN_LAUNCH(OpF32, 12); break;
+        case 16: FMG_SCREEN_LAUNCH(OpF32, 16); break;
         default: return hipErrorInvalidValue;
         }
     }
+#undef FMG_SCREEN_LAUNCH
     return hipGetLastError();
 }
 
