@@ -233,13 +233,16 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
             HCHK(hipEventCreate(&M->evp[e]), "hipEventCreate");
         }
     }
-    MCHK(model_alloc(M, &M->X, (size_t)n * d * esz, "model X"));
+    // X carries 64 zero elements past its last row: kernels may read a fixed
+    // number of coordinates past the end of a row.
+    MCHK(model_alloc(M, &M->X, ((size_t)n * d + 64) * esz, "model X"));
     MCHK(model_alloc(M, (void **)&M->N, (size_t)n * k * 4, "model N"));
     MCHK(model_alloc(M, &M->C, (size_t)n * k * ell * esz, "model C"));
     MCHK(model_alloc(M, (void **)&M->pred_fb, 8, "counters"));
     HCHK(hipMemsetAsync(M->pred_fb, 0, 8, s), "hipMemsetAsync");
     record(M, M->evb, EV_START, s);
     HCHK(hipMemcpyAsync(M->X, X, (size_t)n * d * esz, hipMemcpyDeviceToDevice, s), "copy X");
+    HCHK(hipMemsetAsync((char *)M->X + (size_t)n * d * esz, 0, 64 * esz, s), "hipMemsetAsync");
 
     // Inputs must be finite.
     int *flag = nullptr;
@@ -311,7 +314,7 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
         uint64_t *pool = nullptr, *cand = nullptr;
         float *tq = nullptr;
         int32_t *fbl = nullptr, *fbc = nullptr;
-        HCHK(tmp.alloc((void **)&pool, (size_t)n_pad * screen_cap(c) * 8), "screen pool");
+        HCHK(tmp.alloc((void **)&pool, (size_t)n_pad * SCREEN_CAP * 8), "screen pool");
         HCHK(tmp.alloc((void **)&cand, (size_t)n * c * 8), "scratch");
         HCHK(tmp.alloc((void **)&tq, (size_t)n * 4), "scratch");
         HCHK(tmp.alloc((void **)&fbl, (size_t)n * 4), "scratch");
@@ -383,7 +386,7 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
     HCHK(tmp.alloc((void **)&nbad, 8), "scratch");
     HCHK(hipMemsetAsync(nbad, 0, 8, s), "hipMemsetAsync");
     PrecomputeArgs pa{};
-    pa.X = M->X;
+    pa.X = M->X;  // the model's padded copy
     pa.Y = Y;
     pa.n = n;
     pa.d = d;
@@ -478,7 +481,7 @@ fmg_status fastmuygps_predict(const fmg_model *model, const void *Z, int64_t m, 
         uint64_t *pool = nullptr, *cand = nullptr;
         float *tq = nullptr;
         int32_t *fbl = nullptr, *fbc = nullptr;
-        HIPCHK(tmp.alloc((void **)&pool, (size_t)splits * m_pad * screen_cap(c) * 8), "screen pool");
+        HIPCHK(tmp.alloc((void **)&pool, (size_t)splits * m_pad * SCREEN_CAP * 8), "screen pool");
         HIPCHK(tmp.alloc((void **)&cand, (size_t)splits * m * c * 8), "scratch");
         HIPCHK(tmp.alloc((void **)&tq, (size_t)splits * m * 4), "scratch");
         HIPCHK(tmp.alloc((void **)&fbl, (size_t)m * 4), "scratch");

@@ -208,6 +208,48 @@ __device__ __forceinline__ float phi32(float D, int kc, float inv_rho, float amp
     return amp * (1.0f + s + s * s * (1.0f / 3.0f)) * expf(-s);
 }
 
+// The same four kernels in one branch-free form,
+//     phi = amp (1 + c1 s + c2 s^2) exp(-s),  s = scale * (D or sqrt(D)),
+// with the uniform parameters chosen once per launch; unrolled loops over
+// many entries then inline one short sequence instead of four.
+template <typename T>
+struct PhiForm {
+    bool root;  // s from sqrt(D) (Matern) or from D (RBF)
+    T scale, c1, c2, amp;
+};
+
+template <typename T>
+__device__ __forceinline__ PhiForm<T> phi_form(int kc, double inv_rho, double amp) {
+    PhiForm<T> f;
+    f.root = kc != KC_RBF;
+    f.amp = (T)amp;
+    f.c1 = (T)0;
+    f.c2 = (T)0;
+    if (kc == KC_RBF) {
+        f.scale = (T)(0.5 * inv_rho * inv_rho);
+    } else if (kc == KC_M12) {
+        f.scale = (T)inv_rho;
+    } else if (kc == KC_M32) {
+        f.scale = (T)(1.7320508075688772 * inv_rho);
+        f.c1 = (T)1;
+    } else {
+        f.scale = (T)(2.2360679774997896 * inv_rho);
+        f.c1 = (T)1;
+        f.c2 = (T)(1.0 / 3.0);
+    }
+    return f;
+}
+
+__device__ __forceinline__ float phi_eval(const PhiForm<float> &f, float D) {
+    const float s = f.scale * (f.root ? sqrtf(D) : D);
+    return f.amp * fmaf(fmaf(f.c2, s, f.c1), s, 1.0f) * expf(-s);
+}
+
+__device__ __forceinline__ double phi_eval(const PhiForm<double> &f, double D) {
+    const double s = f.scale * (f.root ? sqrt(D) : D);
+    return f.amp * fma(fma(f.c2, s, f.c1), s, 1.0) * exp(-s);
+}
+
 template <typename T>
 __device__ __forceinline__ T phi_t(T D, int kc, T inv_rho, T amp);
 template <>

@@ -14,9 +14,10 @@ enum ScreenMode { SCREEN_BF16 = 0, SCREEN_F32 = 1 };
 constexpr int SCREEN_TILE = 64;
 // Queries per screen workgroup (4 waves x 64 queries).
 constexpr int SCREEN_QPB = 256;
-// Pool entries per query in the screen (candidate keys awaiting selection):
-// 128 for c <= 64 kept candidates, 256 for c <= 192.
-constexpr int screen_cap(int c) { return c > 64 ? 256 : 128; }
+// Pool entries per query in the screen (candidate keys awaiting selection),
+// and the largest number of candidates kept per query and split.
+constexpr int SCREEN_CAP = 512;
+constexpr int SCREEN_CMAX = 128;
 
 // Row layout of the screening arrays: `kp` elements per row (bf16 or f32),
 // row bytes = kp * elem.  bf16: kp = 64 (2 MFMA k-steps of 32); f32: kp a
@@ -36,8 +37,8 @@ struct ScreenArgs {
     int64_t col_chunk;  // candidate columns per split (multiple of SCREEN_TILE)
     int splits;
     int loo;            // 1: query q never takes candidate q
-    int c;              // candidates kept per (query, split), <= screen_cap(c) - SCREEN_TILE
-    uint64_t *pool;     // [splits, m_pad, screen_cap(c)] scratch
+    int c;              // candidates kept per (query, split), 1..SCREEN_CMAX
+    uint64_t *pool;     // [splits, m_pad, SCREEN_CAP] scratch
     uint64_t *cand;     // [splits, m, c] sorted screen keys (value, index)
     float *tq;          // [splits, m] c-th kept value, +inf when fewer than c
 };
@@ -113,6 +114,8 @@ hipError_t launch_screen(const ScreenGeom &g, const ScreenArgs &a, hipStream_t s
 hipError_t launch_rerank(const RerankArgs &a, hipStream_t s);
 hipError_t launch_exact_topk(bool f64, const ExactArgs &a, int64_t max_items, hipStream_t s);
 hipError_t launch_precompute(bool f64, bool refine, const PrecomputeArgs &a, hipStream_t s);
+// FP32 precompute (FP32 and MIXED precision), refinement optional.
+hipError_t launch_precompute32(bool refine, const PrecomputeArgs &a, hipStream_t s);
 hipError_t launch_gather(bool f64, const GatherArgs &a, hipStream_t s);
 hipError_t launch_count_nonzero(const int32_t *a, int64_t n, unsigned long long *out,
                                 hipStream_t s);

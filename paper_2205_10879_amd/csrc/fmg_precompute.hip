@@ -208,8 +208,7 @@ hipError_t launch_pc_k(const PrecomputeArgs &a, hipStream_t s) {
 hipError_t launch_precompute(bool f64, bool refine, const PrecomputeArgs &a, hipStream_t s) {
     if (a.n <= 0) return hipSuccess;
     if (f64) return launch_pc_k<double, false>(a, s);
-    if (refine) return launch_pc_k<float, true>(a, s);
-    return launch_pc_k<float, false>(a, s);
+    return launch_precompute32(refine, a, s);
 }
 
 }  // namespace fmg

@@ -191,16 +191,18 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
     constexpr int CH = RB / 16;               // 16-byte chunks per row
     constexpr int SWZ = (CH % 8 == 0) ? 7 : 3;  // chunk XOR swizzle (bank spread)
     constexpr int LDI = CH / 4;               // LDS-DMA loads per wave per tile
+    constexpr int TPB = 4;                    // tiles per barrier period
     constexpr int SUB = CAP / 4;              // sub-pool per lane group
-    constexpr int TRIG = SUB - 16;            // select when a sub-pool exceeds this
+    constexpr int TRIG = SUB - 16 * TPB;      // select when a sub-pool exceeds this
     constexpr int PE = CAP / 64;
     static_assert(CH % 4 == 0, "tile load split");
     // Candidate tiles: 64 rows x RB bytes, unpadded; 16-byte chunk c of row r
-    // is stored at chunk position c ^ (r & SWZ).
-    __shared__ __align__(16) char tile0[TILE * RB];
-    __shared__ __align__(16) char tile1[TILE * RB];
+    // is stored at chunk position c ^ (r & SWZ).  Two rings of TPB tiles: one
+    // is screened while LDS-DMA fills the other.
+    __shared__ __align__(16) char ringA[TPB][TILE * RB];
+    __shared__ __align__(16) char ringB[TPB][TILE * RB];
     __shared__ __align__(16) uint32_t hist_all[4][256];
-    __shared__ __align__(16) uint64_t stage_all[4][CAP];
+    __shared__ __align__(16) uint64_t stage_all[4][SCREEN_CMAX];
 
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
@@ -295,14 +297,8 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
         }
     };
 
-    if (cb < ce) load_tile(cb, tile0);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
-    // One candidate tile: MFMA screen of the tile in `cur` while the next tile
-    // streams into `nxt`, then candidate selection.
-    auto step = [&](int col, const char *cur, char *nxt) {
-        if (col + TILE < ce) load_tile(col + TILE, nxt);
-
+    // MFMA screen of one tile and candidate selection.
+    auto screen_tile = [&](int col, const char *cur) {
         f32x4 acc[4][4];
 #pragma unroll
         for (int t = 0; t < 4; ++t)
@@ -347,16 +343,34 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
                 }
             }
         }
-        // Select in every query whose sub-pool could overflow during the next tile.
+    };
+
+    // One barrier period: LDS-DMA of the next period's TPB tiles into `nxt`
+    // while this period's tiles in `cur` are screened (a period of compute
+    // covers the load latency); then pool maintenance and one workgroup
+    // barrier.
+    auto period = [&](int col, char (*cur)[TILE * RB], char (*nxt)[TILE * RB]) {
+#pragma unroll
+        for (int j = 0; j < TPB; ++j)
+            if (col + (TPB + j) * TILE < ce) load_tile(col + (TPB + j) * TILE, nxt[j]);
+#pragma unroll 1
+        for (int j = 0; j < TPB; ++j)
+            if (col + j * TILE < ce) screen_tile(col + j * TILE, cur[j]);
         if (__ballot(cnt[0] > TRIG || cnt[1] > TRIG || cnt[2] > TRIG || cnt[3] > TRIG) != 0)
             flush_full();
-        // the next tile must have landed in LDS before any wave reads it
+        // the next period's tiles must have landed in LDS before any wave reads them
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
     };
-    for (int col = cb; col < ce; col += 2 * TILE) {
-        step(col, tile0, tile1);
-        if (col + TILE < ce) step(col + TILE, tile1, tile0);
+
+#pragma unroll
+    for (int j = 0; j < TPB; ++j)
+        if (cb + j * TILE < ce) load_tile(cb + j * TILE, ringA[j]);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    for (int col = cb; col < ce; col += 2 * TPB * TILE) {
+        period(col, ringA, ringB);
+        if (col + TPB * TILE < ce) period(col + TPB * TILE, ringB, ringA);
     }
 
     // Final selection, sort and output of every real query of this wave.
@@ -370,17 +384,18 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
         const int kept = select_pool<PE, SUB>(pool + ql * 4 * SUB, cg, a.c, self, (uint32_t)n_real,
                                               hist, stage, true, &kmax);
         wave_lds_sync();
-        uint64_t key[PE];
+        constexpr int E2 = SCREEN_CMAX / 64;
+        uint64_t key[E2];
 #pragma unroll
-        for (int e = 0; e < PE; ++e) {
-            const int slot = lane * PE + e;
+        for (int e = 0; e < E2; ++e) {
+            const int slot = lane * E2 + e;
             key[e] = slot < kept ? stage[slot] : ~0ull;
         }
-        wave_sort_u64<PE>(key);
+        wave_sort_u64<E2>(key);
         uint64_t *__restrict__ out = a.cand + ((int64_t)split * a.m + q) * a.c;
 #pragma unroll
-        for (int e = 0; e < PE; ++e) {
-            const int slot = lane * PE + e;
+        for (int e = 0; e < E2; ++e) {
+            const int slot = lane * E2 + e;
             if (slot < a.c) out[slot] = key[e];
         }
         if (lane == 0)
@@ -393,15 +408,9 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
 
 hipError_t launch_screen(const ScreenGeom &g, const ScreenArgs &a, hipStream_t s) {
     dim3 grid((unsigned)(a.m_pad / SCREEN_QPB), (unsigned)a.splits);
-    const bool big = a.c > 64;  // pool of 256 entries, else 128
-    if (a.c > screen_cap(a.c) - SCREEN_TILE) return hipErrorInvalidValue;
-#define FMG_SCREEN_LAUNCH(OP, KS)                                                            \
-    do {                                                                                     \
-        if (big)                                                                             \
-            hipLaunchKernelGGL((screen_kernel<OP, KS, 256>), grid, dim3(256), 0, s, a);      \
-        else                                                                                 \
-            hipLaunchKernelGGL((screen_kernel<OP, KS, 128>), grid, dim3(256), 0, s, a);      \
-    } while (0)
+    if (a.c < 1 || a.c > SCREEN_CMAX) return hipErrorInvalidValue;
+#define FMG_SCREEN_LAUNCH(OP, KS) \
+    hipLaunchKernelGGL((screen_kernel<OP, KS, SCREEN_CAP>), grid, dim3(256), 0, s, a)
     if (g.mode == SCREEN_BF16) {
         if (g.ksteps != 2) return hipErrorInvalidValue;
         FMG_SCREEN_LAUNCH(OpBF16, 2);
