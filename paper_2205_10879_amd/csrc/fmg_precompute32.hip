@@ -8,17 +8,20 @@
 //      (v_mfma_f32_16x16x4f32) and D_ab = G_aa + G_bb - 2 G_ab (centring
 //      keeps the cancellation small).  G is transposed through LDS in halves
 //      of 32 columns so that each lane receives its row.
-//   2. Right-looking Cholesky in registers, with the forward substitution
-//      folded into the same loop; the register window slides one column per
-//      step so the loop stays rolled and the code fits the instruction cache.
-//   3. Back substitution; solved values are broadcast with v_readlane.
+//   2. Cholesky in the form K = U D U^T (U unit lower triangular, D the
+//      pivots), right-looking, with the forward substitution U w = y folded
+//      into the same loop.  Register K[b] of lane a holds entry (a, j + b) at
+//      step j; the window slides one column per step, and shrinks in steps
+//      of 16 columns as the trailing matrix does, so the loops stay rolled.
+//   3. v = D^{-1} w, then back substitution U^T x = v.  Every solve step is
+//      one v_readlane and one FMA per right-hand side: the unit diagonal
+//      leaves nothing to scale inside the loop.
 //   4. MIXED only: one refinement step.  The rows, centred on x_i, are exact
 //      in FP64; their Gram matrix on FP64 MFMA (v_mfma_f64_16x16x4f64) gives
 //      FP64 distances and kernel values, a second FP64 MFMA product gives
-//      r = Y_N - (K64 + sigma^2 I) C, and C += solve(L, r) with the FP32
-//      factor.
-// L is kept in LDS as a packed lower triangle; LDS per wavefront is about
-// 15 KB (FP32) or 35 KB (MIXED, d = 40, k = 50, ell = 10).
+//      r = Y_N - (K64 + sigma^2 I) C, and C += solve(U D U^T, r).
+// U is kept in LDS packed by rows.  LDS per wavefront is about 15 KB (FP32)
+// or 27 KB (MIXED) for d = 40, k = 50, ell = 10.
 // A non-positive or non-finite pivot marks the point: its C row is NaN and
 // its status is 1.
 #include "fmg_device.h"
@@ -52,12 +55,11 @@ struct PcLayout {
     int x64_ld;     // doubles per staged FP64 row (refinement)
     int g_ld;       // floats per Gram column (column-major, 32 columns at a time)
     int off_r1;     // staged rows, then Gram halves, then FP64 rows
-    int off_l;      // Cholesky factor, packed by rows (row a at a(a+1)/2), 1/L_jj on
-                    // the diagonal
-    int off_bc;     // broadcast buffer [64][ELLMAX] floats
+    int off_l;      // U, strictly lower part packed by rows (row a at a(a-1)/2)
+    int off_bc;     // column broadcast [64] floats; with refinement the
+                    // coefficients [64][ELLMAX] floats
     int off_nrm;    // [64] floats
     int off_nrm64;  // [64] doubles
-    int off_kc;     // refinement: K64 C, [64][ELLMAX] doubles
     int bytes;
 };
 
@@ -72,63 +74,175 @@ __host__ __device__ __forceinline__ PcLayout pc_layout(int k, int d, int kmax, i
     L.xs_ld = xs_stride(d);
     L.x64_ld = x64_stride(d);
     L.g_ld = kmax + 4;
-    const int r1 = imax3(k * L.xs_ld * 4, 32 * L.g_ld * 4, refine ? k * L.x64_ld * 8 : 0);
+    // The FP64 rows (refinement) reuse the staging space; K64 C reuses
+    // theirs once the product is done.
+    const int r64 = refine ? imax3(k * L.x64_ld * 8, 64 * ellmax * 8, 0) : 0;
+    const int r1 = imax3(k * L.xs_ld * 4, 32 * L.g_ld * 4, r64);
     L.off_r1 = 0;
     L.off_l = (r1 + 15) & ~15;
-    L.off_bc = (L.off_l + (k * (k + 1) / 2) * 4 + 15) & ~15;
-    L.off_nrm = L.off_bc + 64 * ellmax * 4;
+    L.off_bc = (L.off_l + (k * (k - 1) / 2) * 4 + 15) & ~15;
+    L.off_nrm = L.off_bc + 64 * (refine ? ellmax : 1) * 4;
     L.off_nrm64 = L.off_nrm + 64 * 4;
-    L.off_kc = L.off_nrm64 + 64 * 8;
-    L.bytes = L.off_kc + (refine ? 64 * ellmax * 8 : 0);
+    L.bytes = L.off_nrm64 + 64 * 8;
     return L;
 }
 
 // Stage rows N(i)_b (b < k) centred on x_i (difference in FP64, rounded to
-// FP32) into xs[b][0..d), zero padded to xs_ld; lane b loads row b.
+// FP32) into xs[b][0..d), zero padded to a multiple of 4; lane b loads row b,
+// four coordinates per load when rows are 16-byte aligned.
 __device__ __forceinline__ void stage_rows(const float *__restrict__ X, int d, int k, int64_t i,
                                            int64_t p, float *__restrict__ xs, int ld, int a) {
     const float *__restrict__ xi = X + i * d;
     const float *__restrict__ xp = X + p * d;
-    if (a < k) {
-        float *row = xs + a * ld;
+    if (a >= k) return;
+    float *row = xs + a * ld;
+    if ((d & 3) == 0) {
+#pragma unroll 4
+        for (int c = 0; c < d; c += 4) {
+            const float4 u = *(const float4 *)(xp + c);
+            const float4 v = *(const float4 *)(xi + c);
+            row[c] = (float)((double)u.x - (double)v.x);
+            row[c + 1] = (float)((double)u.y - (double)v.y);
+            row[c + 2] = (float)((double)u.z - (double)v.z);
+            row[c + 3] = (float)((double)u.w - (double)v.w);
+        }
+    } else {
+#pragma unroll 4
         for (int c = 0; c < d; ++c) row[c] = (float)((double)xp[c] - (double)xi[c]);
-        for (int c = d; c < ld; ++c) row[c] = 0.0f;
+        for (int c = d; c < ((d + 3) & ~3); ++c) row[c] = 0.0f;
     }
 }
 
-// Triangular solves with L in LDS as a packed lower triangle, row a at
-// a(a+1)/2, whose diagonal slots hold 1/L_jj.  Lane a holds row a of the
-// ELLMAX right-hand sides; the value solved at step j is read from lane j
-// (v_readlane), so no LDS round trip or barrier sits on the dependency chain.
+// The same rows exactly in FP64 (refinement); returns |x_a - x_i|^2.
+__device__ __forceinline__ double stage_rows64(const float *__restrict__ X, int d, int k,
+                                               int64_t i, int64_t p, double *__restrict__ x64,
+                                               int ld, int a) {
+    const float *__restrict__ xi = X + i * d;
+    const float *__restrict__ xp = X + p * d;
+    double n64 = 0.0;
+    if (a >= k) return n64;
+    double *row = x64 + a * ld;
+    if ((d & 3) == 0) {
+#pragma unroll 4
+        for (int c = 0; c < d; c += 4) {
+            const float4 u = *(const float4 *)(xp + c);
+            const float4 v = *(const float4 *)(xi + c);
+            const double e0 = (double)u.x - (double)v.x, e1 = (double)u.y - (double)v.y;
+            const double e2 = (double)u.z - (double)v.z, e3 = (double)u.w - (double)v.w;
+            row[c] = e0;
+            row[c + 1] = e1;
+            row[c + 2] = e2;
+            row[c + 3] = e3;
+            n64 = fma(e0, e0, n64);
+            n64 = fma(e1, e1, n64);
+            n64 = fma(e2, e2, n64);
+            n64 = fma(e3, e3, n64);
+        }
+    } else {
+#pragma unroll 4
+        for (int c = 0; c < d; ++c) {
+            const double e = (double)xp[c] - (double)xi[c];
+            row[c] = e;
+            n64 = fma(e, e, n64);
+        }
+        for (int c = d; c < ((d + 3) & ~3); ++c) row[c] = 0.0;
+    }
+    return n64;
+}
+
+// exp(x) for x <= 0 in FP64: additive range reduction x = n ln2 + r,
+// |r| <= ln2/2 (Cody and Waite, with the product n ln2 taken in two FMAs),
+// then the Taylor series of exp(r) to degree 12 (truncation below 1e-15
+// relative) and a final scaling by 2^n.  Underflows to 0 below about -745.
+__device__ __forceinline__ double exp_nonpos64(double x) {
+    const double kLn2 = 0.6931471805599453;       // ln 2 rounded to FP64
+    const double kLn2Lo = 2.3190468138462996e-17;  // ln 2 - kLn2
+    const double n = rint(x * 1.4426950408889634);  // x / ln 2
+    double r = fma(-n, kLn2, x);
+    r = fma(-n, kLn2Lo, r);
+    double q = 1.0 / 479001600.0;  // 1/12!
+    q = fma(q, r, 1.0 / 39916800.0);
+    q = fma(q, r, 1.0 / 3628800.0);
+    q = fma(q, r, 1.0 / 362880.0);
+    q = fma(q, r, 1.0 / 40320.0);
+    q = fma(q, r, 1.0 / 5040.0);
+    q = fma(q, r, 1.0 / 720.0);
+    q = fma(q, r, 1.0 / 120.0);
+    q = fma(q, r, 1.0 / 24.0);
+    q = fma(q, r, 1.0 / 6.0);
+    q = fma(q, r, 0.5);
+    q = fma(q, r, 1.0);
+    q = fma(q, r, 1.0);
+    const int e = n < -1100.0 ? -1100 : (int)n;
+    return ldexp(q, e);
+}
+
+// phi in FP64 for the refinement residual, through exp_nonpos64.
+__device__ __forceinline__ double phi_eval64(const PhiForm<double> &f, double D) {
+    const double s = f.scale * (f.root ? sqrt(D) : D);
+    return f.amp * fma(fma(f.c2, s, f.c1), s, 1.0) * exp_nonpos64(-s);
+}
+
+// Solves with U (unit lower, strictly lower part packed by rows in LDS, row
+// a at a(a-1)/2).  Lane a holds row a of the ELLMAX right-hand sides; the
+// value final at step j is read from lane j with v_readlane.
 template <int ELLMAX>
-__device__ __forceinline__ void solve_forward(const float *__restrict__ Lm, int k, int ell, int a,
-                                              float (&y)[ELLMAX]) {
-    const int arow = a * (a + 1) / 2;
-    for (int j = 0; j < k; ++j) {
-        const float rjj = Lm[j * (j + 1) / 2 + j];
-        const float laj = (a > j && a < k) ? Lm[arow + j] : 0.0f;
+__device__ __forceinline__ void solve_unit_forward(const float *__restrict__ U, int k, int ell,
+                                                   int a, float (&y)[ELLMAX]) {
+    const int arow = a * (a - 1) / 2;
+    for (int j = 0; j < k - 1; ++j) {
+        const float u = (a > j && a < k) ? U[arow + j] : 0.0f;
 #pragma unroll
         for (int c = 0; c < ELLMAX; ++c) {
             if (c >= ell) break;
-            const float zj = readlane_f32(y[c], j) * rjj;
-            y[c] = (a == j) ? zj : fmaf(-laj, zj, y[c]);
+            y[c] = fmaf(-u, readlane_f32(y[c], j), y[c]);
         }
     }
 }
 
 template <int ELLMAX>
-__device__ __forceinline__ void solve_backward(const float *__restrict__ Lm, int k, int ell, int a,
-                                               float (&y)[ELLMAX]) {
-    for (int j = k - 1; j >= 0; --j) {
-        const int jrow = j * (j + 1) / 2;
-        const float rjj = Lm[jrow + j];
-        const float lja = (a < j) ? Lm[jrow + a] : 0.0f;
+__device__ __forceinline__ void solve_unit_backward(const float *__restrict__ U, int k, int ell,
+                                                    int a, float (&y)[ELLMAX]) {
+    for (int j = k - 1; j > 0; --j) {
+        const float u = (a < j) ? U[j * (j - 1) / 2 + a] : 0.0f;
 #pragma unroll
         for (int c = 0; c < ELLMAX; ++c) {
             if (c >= ell) break;
-            const float xj = readlane_f32(y[c], j) * rjj;
-            y[c] = (a == j) ? xj : fmaf(-lja, xj, y[c]);
+            y[c] = fmaf(-u, readlane_f32(y[c], j), y[c]);
         }
+    }
+}
+
+// Cholesky steps j in [j0, j1) with a register window of W columns.
+template <int KMAX, int ELLMAX, int W>
+__device__ __forceinline__ void chol_steps(float (&K)[KMAX], float (&y)[ELLMAX], int j0, int j1,
+                                           int k, int ell, int a, float *__restrict__ U,
+                                           float *__restrict__ bc, float &dinv, bool &bad) {
+    const int arow = a * (a - 1) / 2;
+    for (int j = j0; j < j1; ++j) {
+        float piv = readlane_f32(K[0], j);
+        if (!(piv > 0.0f) || !isfinite(piv)) {
+            bad = true;
+            piv = 1.0f;
+        }
+        const float rp = 1.0f / piv;
+        const bool below = a > j && a < k;
+        const float u = below ? K[0] * rp : 0.0f;
+        if (a == j) dinv = rp;
+        if (below) U[arow + j] = u;
+#pragma unroll
+        for (int c = 0; c < ELLMAX; ++c) {
+            if (c >= ell) break;
+            y[c] = fmaf(-u, readlane_f32(y[c], j), y[c]);
+        }
+        // Entry b of the broadcast is column j of the trailing matrix at row
+        // j + 1 + b; the positions past the last row are zero.
+        bc[(a - j - 1) & 63] = (a > j) ? K[0] : 0.0f;
+        lds_sync();
+#pragma unroll
+        for (int b = 0; b + 1 < W; ++b) K[b] = fmaf(-u, bc[b], K[b + 1]);
+        K[W - 1] = 0.0f;
+        lds_sync();
     }
 }
 
@@ -143,7 +257,7 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
     float *xs = (float *)(smem + L.off_r1);
     float *G = (float *)(smem + L.off_r1);
     double *x64 = (double *)(smem + L.off_r1);
-    float *Lm = (float *)(smem + L.off_l);
+    float *U = (float *)(smem + L.off_l);
     float *bc = (float *)(smem + L.off_bc);
     float *nrm = (float *)(smem + L.off_nrm);
     double *nrm64 = (double *)(smem + L.off_nrm64);
@@ -224,41 +338,34 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
         K[b] = (a < k) ? v : ((a == b) ? 1.0f : 0.0f);
     }
 
-    // 2. Right-looking Cholesky with the forward solve folded in.  Register
-    // K[b] of lane a holds entry (a, j + b) at step j: after each step the
-    // window moves one column, so the loop over j stays rolled and the code
-    // small.  Column j of L is broadcast through LDS, stored shifted so that
-    // entry b of the broadcast pairs with register b; the tail of the buffer
-    // is zero.  L is kept packed by rows with 1/L_jj on the diagonal.
+    // 2. K = U D U^T with U w = y folded in; the window narrows by 16 columns
+    // whenever the trailing matrix fits a narrower one.
     bool bad = false;
-    const int arow = a * (a + 1) / 2;
-    for (int j = 0; j < k; ++j) {
-        float piv = readlane_f32(K[0], j);
-        if (!(piv > 0.0f) || !isfinite(piv)) {
-            bad = true;
-            piv = 1.0f;
+    float dinv = 0.0f;
+    {
+        int j = 0;
+        if constexpr (KMAX > 48) {
+            const int e = k - 48 > 0 ? k - 48 : 0;
+            chol_steps<KMAX, ELLMAX, 64>(K, y, j, e, k, ell, a, U, bc, dinv, bad);
+            j = e;
         }
-        const float ljj = sqrtf(piv);
-        const float rjj = 1.0f / ljj;
-        const float lj = (a == j) ? ljj : ((a > j && a < k) ? K[0] * rjj : 0.0f);
-        if (a == j) Lm[arow + j] = rjj;
-        if (a > j && a < k) Lm[arow + j] = lj;
-#pragma unroll
-        for (int c = 0; c < ELLMAX; ++c) {
-            if (c >= ell) break;
-            const float zj = readlane_f32(y[c], j) * rjj;
-            y[c] = (a == j) ? zj : fmaf(-lj, zj, y[c]);  // lj = 0 above row j
+        if constexpr (KMAX > 32) {
+            const int e = k - 32 > j ? k - 32 : j;
+            chol_steps<KMAX, ELLMAX, 48>(K, y, j, e, k, ell, a, U, bc, dinv, bad);
+            j = e;
         }
-        bc[(a - j - 1) & 63] = (a > j) ? lj : 0.0f;
-        lds_sync();
-#pragma unroll
-        for (int b = 0; b + 1 < KMAX; ++b) K[b] = fmaf(-lj, bc[b], K[b + 1]);
-        K[KMAX - 1] = 0.0f;
-        lds_sync();
+        {
+            const int e = k - 16 > j ? k - 16 : j;
+            chol_steps<KMAX, ELLMAX, 32>(K, y, j, e, k, ell, a, U, bc, dinv, bad);
+            j = e;
+        }
+        chol_steps<KMAX, ELLMAX, 16>(K, y, j, k, k, ell, a, U, bc, dinv, bad);
     }
 
-    // 3. Back substitution for all right-hand sides.
-    solve_backward<ELLMAX>(Lm, k, ell, a, y);
+    // 3. v = D^{-1} w, then U^T x = v.
+#pragma unroll
+    for (int c = 0; c < ELLMAX; ++c) y[c] *= dinv;
+    solve_unit_backward<ELLMAX>(U, k, ell, a, y);
 
     if constexpr (REFINE) {
         // 4. One refinement step, r = Y_N - (K64 + sigma^2 I) C, in FP64 on
@@ -269,40 +376,33 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
         // lane l holds entries (4g + l/16, l%16), g = 0..3, of a tile, which
         // (K being symmetric) is exactly the A operand of the product for
         // the transposed tile, so K never leaves registers.
-        double *KC = (double *)(smem + L.off_kc);  // [64][ELLMAX]
         const int ld = L.x64_ld, d4 = (d + 3) & ~3;
-        double n64 = 0.0;
-        if (a < k) {
-            const float *__restrict__ xi = X + i * d;
-            const float *__restrict__ xa = X + p * d;
-            double *row = x64 + a * ld;
-            for (int c = 0; c < d; ++c) {
-                const double v = (double)xa[c] - (double)xi[c];
-                row[c] = v;
-                n64 = fma(v, v, n64);
-            }
-            for (int c = d; c < d4; ++c) row[c] = 0.0;
-        }
-        nrm64[a] = n64;
+        lds_sync();  // the Gram staging area is dead
+        nrm64[a] = stage_rows64(X, d, k, i, p, x64, ld, a);
         float *cb = bc;  // [64][ELLMAX] current coefficients, zero past k / ell
 #pragma unroll
         for (int c = 0; c < ELLMAX; ++c) cb[a * ELLMAX + c] = (a < k && c < ell) ? y[c] : 0.0f;
         lds_sync();
         const double diag64 = P.amp + P.noise;
         const PhiForm<double> pf64 = phi_form<double>(P.kc, P.inv_rho, P.amp);
-        const int nt = (k + 15) >> 4;
-        for (int ct = 0; ct < nt; ++ct) {
+        f64x4 R[NT];
+#pragma unroll
+        for (int ct = 0; ct < NT; ++ct) {
             f64x4 g[NT];
 #pragma unroll
             for (int r = 0; r < NT; ++r) g[r] = f64x4{0.0, 0.0, 0.0, 0.0};
             const int rb = ct * 16 + fr;
-            for (int s = 0; s < d4; s += 4) {
-                const double fb = (rb < k) ? x64[rb * ld + s + fk] : 0.0;
+            if (ct * 16 < k) {
+                for (int s = 0; s < d4; s += 4) {
+                    double f[NT];
 #pragma unroll
-                for (int r = 0; r < NT; ++r) {
-                    const int row = r * 16 + fr;
-                    const double fa = (row < k) ? x64[row * ld + s + fk] : 0.0;
-                    g[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa, fb, g[r], 0, 0, 0);
+                    for (int r = 0; r < NT; ++r) {
+                        const int row = r * 16 + fr;
+                        f[r] = (row < k) ? x64[row * ld + s + fk] : 0.0;
+                    }
+#pragma unroll
+                    for (int r = 0; r < NT; ++r)
+                        g[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[r], f[ct], g[r], 0, 0, 0);
                 }
             }
             const double ncol = nrm64[rb];
@@ -314,22 +414,23 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
                     const int row = r * 16 + 4 * q + fk;
                     double kab = 0.0;
                     if (row < k && rb < k) {
-                        if (row == rb) {
-                            kab = diag64;
-                        } else {
-                            double D = nrm64[row] + ncol - 2.0 * g[r][q];
-                            D = D > 0.0 ? D : 0.0;
-                            kab = phi_eval(pf64, D);
-                        }
+                        double D = nrm64[row] + ncol - 2.0 * g[r][q];
+                        D = D > 0.0 ? D : 0.0;
+                        kab = (row == rb) ? diag64 : phi_eval64(pf64, D);
                     }
                     const double cv = (fr < ell) ? (double)cb[row * ELLMAX + fr] : 0.0;
                     acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(kab, cv, acc64, 0, 0, 0);
                 }
             }
-            if (fr < ell) {
+            R[ct] = acc64;
+        }
+        lds_sync();  // the FP64 rows are dead; their space takes K64 C
+        double *KC = x64;  // [64][ELLMAX]
+        if (fr < ell) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) KC[(ct * 16 + 4 * q + fk) * ELLMAX + fr] = acc64[q];
-            }
+            for (int ct = 0; ct < NT; ++ct)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) KC[(ct * 16 + 4 * q + fk) * ELLMAX + fr] = R[ct][q];
         }
         lds_sync();
         float dl[ELLMAX];
@@ -337,8 +438,10 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
         for (int c = 0; c < ELLMAX; ++c)
             dl[c] = (a < k && c < ell) ? (float)((double)Y[p * ell + c] - KC[a * ELLMAX + c])
                                        : 0.0f;
-        solve_forward<ELLMAX>(Lm, k, ell, a, dl);
-        solve_backward<ELLMAX>(Lm, k, ell, a, dl);
+        solve_unit_forward<ELLMAX>(U, k, ell, a, dl);
+#pragma unroll
+        for (int c = 0; c < ELLMAX; ++c) dl[c] *= dinv;
+        solve_unit_backward<ELLMAX>(U, k, ell, a, dl);
 #pragma unroll
         for (int c = 0; c < ELLMAX; ++c) y[c] += dl[c];
     }
