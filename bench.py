@@ -44,6 +44,9 @@ def main():
     ap.add_argument("--cpu-queries", type=int, default=512, help="oracle sample: queries")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=8.0,
+                    help="length of each served (Poisson stream) run; 0 skips serving")
+    ap.add_argument("--serve-qps", type=float, default=2.0e6, help="offered queries per second")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -158,6 +161,20 @@ def main():
             "max_abs_mean_diff_vs_mixed": float(np.max(np.abs(mu32 - mu_mixed))),
         }
 
+    if args.serve_seconds > 0:
+        result["served"] = {}
+        for prec in ("mixed", "fp32"):
+            log("served run (%s): Poisson stream, %.0f queries/s offered, %.1f s" % (
+                prec, args.serve_qps, args.serve_seconds))
+            model = fmg.fastmuygps_build(X, Y, w.k, w.kernel, w.nu, w.rho, w.noise,
+                                         precision=prec, stream=stream)
+            result["served"][prec] = serve_run(fmg, synth, np, model, args.serve_qps,
+                                               args.serve_seconds)
+            model.free()
+            log("served %s: %s" % (prec, result["served"][prec]))
+        result["p99_ms_served_mixed"] = result["served"]["mixed"]["p99_ms"]
+        result["p99_ms_served_fp32"] = result["served"]["fp32"]["p99_ms"]
+
     if not args.no_cpu_baseline:
         import oracle
         threads = oracle.max_threads()
@@ -191,6 +208,59 @@ def main():
         result["oracle_sample_max_rel_err_mixed"] = err
 
     print(json.dumps(result), flush=True)
+
+
+def serve_run(fmg, synth, np, model, qps, seconds, bmax=4096):
+    """Open-loop served run: requests arrive as a Poisson stream with batch
+    sizes log-uniform in [1, bmax] (mean offered load `qps` queries/s); latency
+    runs from each request's scheduled arrival to its results in host memory."""
+    import queue
+    import threading
+    mean_b = (bmax + 1) / math.log(bmax + 1) - 1.0  # E[floor(exp(U ln(bmax+1)))] ~
+    rate = qps / mean_b
+    t_arr, B = synth.poisson_stream(rate, seconds, bmax)
+    pool = synth.cfg3_queries(1 << 20)
+    offs = np.concatenate([[0], np.cumsum(B)[:-1]]) % (len(pool) - bmax)
+    srv = fmg.Server(slots=3, max_batch=16384)
+    mid, _ = srv.add_model(model)
+    # warm-up: one request per batch-size bucket the stream can form
+    for b in (1, 300, 600, 1000, 2000, 4000, 8000, 16000):
+        for _ in range(3):
+            srv.submit(mid, pool[:b]).wait()
+    srv.reset_stats()
+    tickets = queue.Queue()
+    lat = []
+
+    def waiter():
+        while True:
+            t = tickets.get()
+            if t is None:
+                return
+            lat.append(t.wait()[1])
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.monotonic_ns() + 20_000_000
+    for i in range(len(t_arr)):
+        due = t0 + int(t_arr[i] * 1e9)
+        while True:
+            now = time.monotonic_ns()
+            if now >= due:
+                break
+            if due - now > 200_000:
+                time.sleep((due - now - 100_000) * 1e-9)
+        o = int(offs[i])
+        tickets.put(srv.submit(mid, pool[o:o + int(B[i])], arrival_ns=due))
+    tickets.put(None)
+    th.join()
+    st = srv.stats()
+    srv.close()
+    return {"requests": int(st["requests"]), "queries": int(st["queries"]),
+            "batches": int(st["batches"]), "offered_qps": qps,
+            "predictions_per_s": round(st["queries_per_s"], 1),
+            "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+            "mean_ms": round(st["mean_ms"], 3), "max_ms": round(st["max_ms"], 3),
+            "hbm_peak_bytes": int(st["hbm_peak"])}
 
 
 if __name__ == "__main__":

@@ -155,6 +155,90 @@ fmg_status fastmuygps_coeffs(const fmg_model *model, void *dev_out, void *stream
  * (FMG_FLAG_TIMING models only; FMG_E_INVALID_ARG otherwise). */
 fmg_status fastmuygps_timings(const fmg_model *model, fmg_timings *t);
 
+/* ------------------------------------------------------------------------
+ * Serving: resident models and continuous batching of query requests.
+ *
+ * The paper motivates prediction inside online loops (Section 1) but gives no
+ * serving design; this is the library's.  A server keeps built models on the
+ * device within an HBM budget and runs a request loop: requests (host query
+ * buffers of uneven size) are queued per model; whenever one of `slots`
+ * in-flight slots is free, all queued requests of one model, up to
+ * `max_batch` queries, are coalesced into one batch, copied to the device and
+ * predicted there (Algorithm 2, prediction loop) on that slot's stream, while
+ * other slots' batches run.  Every slot owns its buffers (allocated at
+ * creation), so a batch allocates nothing; with `use_graphs` the copy-in,
+ * prediction and copy-out of a batch replay a HIP graph captured once per
+ * (model, slot, batch-size bucket).  Each result is the one
+ * fastmuygps_predict returns for the same query alone.
+ * ------------------------------------------------------------------------ */
+typedef struct fmg_server fmg_server;
+typedef struct fmg_request *fmg_ticket;
+
+typedef struct {
+    int32_t slots;      /* batches in flight (one stream each), 1..8; 0 = 3 */
+    int32_t max_batch;  /* queries per batch and per request, 1..65536; 0 = 16384 */
+    int32_t use_graphs; /* replay captured HIP graphs per batch (1) or launch (0) */
+} fmg_server_opts;
+
+typedef struct {
+    int64_t requests, queries, batches; /* completed since creation or reset */
+    double p50_ms, p99_ms, mean_ms, max_ms; /* request latency: arrival to results
+                                               in the caller's host buffer */
+    double wall_s;          /* first arrival to last completion */
+    double queries_per_s;   /* queries / wall_s */
+    uint64_t hbm_resident;  /* bytes: admitted models + slot workspaces */
+    uint64_t hbm_peak;
+    int32_t models_resident, models_waiting;
+} fmg_server_stats;
+
+/* Create a server on the current device.  hbm_budget (bytes) bounds the
+ * admitted models plus the slot workspaces; 0 means the device's free memory.
+ * opts may be NULL (defaults).  Errors: FMG_E_INVALID_ARG, FMG_E_OOM (the
+ * slot workspaces alone exceed the budget), FMG_E_DEVICE. */
+fmg_status fastmuygps_server_create(uint64_t hbm_budget, const fmg_server_opts *opts,
+                                    fmg_server **out);
+
+/* Register a built model (the caller keeps ownership and frees it after
+ * removing it or destroying the server).  FMG_OK: admitted, resident.
+ * FMG_E_BUSY: over budget now -- the model's arrays are moved to pinned host
+ * memory and it is admitted (moved back) when a removal frees enough budget;
+ * *id is valid and requests may be submitted meanwhile (they wait).
+ * FMG_E_OOM: the model alone exceeds the budget.  FMG_E_INVALID_ARG: null
+ * arguments, a model built with FMG_FLAG_TIMING, or d/ell beyond the slots. */
+fmg_status fastmuygps_server_add_model(fmg_server *server, fmg_model *model, int32_t *id);
+
+/* Unregister a model once its queued and running requests are done; its
+ * budget goes to waiting models (first come, first admitted).  The model is
+ * left resident on the device for the caller when memory allows.  */
+fmg_status fastmuygps_server_remove_model(fmg_server *server, int32_t id);
+
+/* Queue B queries for model `id`.  Z_host: host pointer [B, d] in the
+ * model's dtype; out_host: host pointer [B, ell] in the model's dtype; both
+ * stay owned by the caller and must stay valid until fastmuygps_server_wait
+ * returns for this ticket.  arrival_ns: the request's scheduled arrival on
+ * CLOCK_MONOTONIC in nanoseconds (latency is measured from it), 0 = now.
+ * Returns at once.  Errors: FMG_E_INVALID_ARG (unknown id, B < 1 or B >
+ * max_batch, null pointers). */
+fmg_status fastmuygps_server_submit(fmg_server *server, int32_t id, const void *Z_host,
+                                    int32_t B, void *out_host, int64_t arrival_ns,
+                                    fmg_ticket *ticket);
+
+/* Block until the request is done; releases the ticket.  latency_ms may be
+ * NULL.  Returns the request's status. */
+fmg_status fastmuygps_server_wait(fmg_ticket ticket, double *latency_ms);
+
+/* Latency and throughput statistics (host struct). */
+fmg_status fastmuygps_server_stats(fmg_server *server, fmg_server_stats *stats);
+
+/* Clear the statistics (not the HBM peak). */
+fmg_status fastmuygps_server_reset_stats(fmg_server *server);
+
+/* Finish every queued request of admitted models, fail those of models never
+ * admitted (FMG_E_BUSY), stop the request loop and free the slots.  Models
+ * stay owned by the caller and are moved back to the device when memory
+ * allows.  NULL is a no-op.  Outstanding tickets stay valid until waited on. */
+void fastmuygps_server_destroy(fmg_server *server);
+
 /* Release the model and all its device memory.  NULL is a no-op. */
 void fastmuygps_free(fmg_model *model);
 

@@ -42,7 +42,10 @@ FLAG_TIMING = 0x8
 # Public C entry points (checked by the CPU tests against include/fastmuygps.h).
 EXPORTS = ("fastmuygps_build", "fastmuygps_predict", "fastmuygps_info", "fastmuygps_neighbors",
            "fastmuygps_coeffs", "fastmuygps_timings", "fastmuygps_free", "fastmuygps_last_error",
-           "fastmuygps_version")
+           "fastmuygps_version", "fastmuygps_server_create", "fastmuygps_server_add_model",
+           "fastmuygps_server_remove_model", "fastmuygps_server_submit", "fastmuygps_server_wait",
+           "fastmuygps_server_stats", "fastmuygps_server_reset_stats",
+           "fastmuygps_server_destroy")
 
 
 class FmgHyper(ctypes.Structure):
@@ -64,6 +67,21 @@ class FmgTimings(ctypes.Structure):
         "build_prep_ms", "build_screen_ms", "build_rerank_ms", "build_fallback_ms",
         "build_precompute_ms", "build_total_ms", "predict_prep_ms", "predict_screen_ms",
         "predict_rerank_ms", "predict_fallback_ms", "predict_gather_ms", "predict_total_ms")]
+
+
+class FmgServerOpts(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("use_graphs", ctypes.c_int32)]
+
+
+class FmgServerStats(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_int64), ("queries", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("max_ms", ctypes.c_double), ("wall_s", ctypes.c_double),
+                ("queries_per_s", ctypes.c_double), ("hbm_resident", ctypes.c_uint64),
+                ("hbm_peak", ctypes.c_uint64), ("models_resident", ctypes.c_int32),
+                ("models_waiting", ctypes.c_int32)]
 
 
 class FmgError(RuntimeError):
@@ -98,6 +116,24 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fastmuygps_last_error.restype = ctypes.c_char_p
     lib.fastmuygps_version.argtypes = []
     lib.fastmuygps_version.restype = ctypes.c_char_p
+    lib.fastmuygps_server_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(FmgServerOpts),
+                                             ctypes.POINTER(P)]
+    lib.fastmuygps_server_create.restype = ctypes.c_int
+    lib.fastmuygps_server_add_model.argtypes = [P, P, ctypes.POINTER(ctypes.c_int32)]
+    lib.fastmuygps_server_add_model.restype = ctypes.c_int
+    lib.fastmuygps_server_remove_model.argtypes = [P, ctypes.c_int32]
+    lib.fastmuygps_server_remove_model.restype = ctypes.c_int
+    lib.fastmuygps_server_submit.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, P,
+                                             ctypes.c_int64, ctypes.POINTER(P)]
+    lib.fastmuygps_server_submit.restype = ctypes.c_int
+    lib.fastmuygps_server_wait.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
+    lib.fastmuygps_server_wait.restype = ctypes.c_int
+    lib.fastmuygps_server_stats.argtypes = [P, ctypes.POINTER(FmgServerStats)]
+    lib.fastmuygps_server_stats.restype = ctypes.c_int
+    lib.fastmuygps_server_reset_stats.argtypes = [P]
+    lib.fastmuygps_server_reset_stats.restype = ctypes.c_int
+    lib.fastmuygps_server_destroy.argtypes = [P]
+    lib.fastmuygps_server_destroy.restype = None
     return lib
 
 
@@ -243,3 +279,85 @@ def fastmuygps_info(model: Model) -> dict:
 def fastmuygps_free(model: Model) -> None:
     model.free()
 
+
+
+class Ticket:
+    """A submitted request; ``wait()`` returns (means, latency_ms)."""
+
+    def __init__(self, handle: ctypes.c_void_p, Z, out):
+        self._h = handle
+        self._keep = (Z, out)  # the host buffers must outlive the request
+
+    def wait(self):
+        if self._h is None:
+            raise ValueError("ticket already waited on")
+        lat = ctypes.c_double()
+        h, self._h = self._h, None
+        st = lib().fastmuygps_server_wait(h, ctypes.byref(lat))
+        _check(st)
+        return self._keep[1], lat.value
+
+
+class Server:
+    """fastmuygps_server_*: resident models and continuous batching of requests
+    (host numpy query arrays) over several in-flight slots."""
+
+    def __init__(self, hbm_budget: int = 0, slots: int = 3, max_batch: int = 16384,
+                 use_graphs: bool = True):
+        opts = FmgServerOpts(int(slots), int(max_batch), 1 if use_graphs else 0)
+        h = ctypes.c_void_p()
+        _check(lib().fastmuygps_server_create(int(hbm_budget), ctypes.byref(opts),
+                                             ctypes.byref(h)))
+        self._h = h
+        self.max_batch = int(max_batch)
+        self._models = {}
+
+    def add_model(self, model: Model) -> tuple:
+        """Returns (id, admitted); a model that does not fit waits (admitted False)."""
+        mid = ctypes.c_int32()
+        st = lib().fastmuygps_server_add_model(self._h, model.handle, ctypes.byref(mid))
+        _check(st, allow=(FMG_E_BUSY,))
+        self._models[mid.value] = model
+        return mid.value, st == FMG_OK
+
+    def remove_model(self, mid: int) -> None:
+        _check(lib().fastmuygps_server_remove_model(self._h, int(mid)))
+        self._models.pop(mid, None)
+
+    def submit(self, mid: int, Z, arrival_ns: int = 0) -> Ticket:
+        import numpy as np
+        model = self._models[mid]
+        dt = np.float64 if model.dtype == torch.float64 else np.float32
+        Z = np.ascontiguousarray(Z, dtype=dt)
+        if Z.ndim != 2 or Z.shape[1] != model.d:
+            raise ValueError("Z must be [B, %d]" % model.d)
+        out = np.empty((Z.shape[0], model.ell), dtype=dt)
+        t = ctypes.c_void_p()
+        _check(lib().fastmuygps_server_submit(self._h, int(mid), Z.ctypes.data, Z.shape[0],
+                                             out.ctypes.data, int(arrival_ns), ctypes.byref(t)))
+        return Ticket(t, Z, out)
+
+    def stats(self) -> dict:
+        st = FmgServerStats()
+        _check(lib().fastmuygps_server_stats(self._h, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in FmgServerStats._fields_}
+
+    def reset_stats(self) -> None:
+        _check(lib().fastmuygps_server_reset_stats(self._h))
+
+    def close(self) -> None:
+        if self._h:
+            lib().fastmuygps_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

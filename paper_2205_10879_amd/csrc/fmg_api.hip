@@ -12,6 +12,7 @@
 
 #include "fastmuygps.h"
 #include "fmg_device.h"
+#include "fmg_internal.h"
 #include "fmg_kernels.h"
 
 using namespace fmg;
@@ -66,41 +67,7 @@ struct Scratch {
     }
 };
 
-enum { EV_START = 0, EV_PREP, EV_SCREEN, EV_RERANK, EV_FALLBACK, EV_LAST, EV_COUNT };
-
 }  // namespace
-
-struct fmg_model {
-    int64_t n = 0;
-    int d = 0, ell = 0, k = 0;
-    fmg_hyper hyper{};
-    int prec = 0;
-    uint32_t flags = 0;
-    int kc = 0;
-    double inv_rho = 1.0, amp = 1.0;
-    bool self_inc = false;
-    int device = 0;
-
-    void *X = nullptr;   // [n, d]
-    int32_t *N = nullptr;  // [n, k]
-    void *C = nullptr;   // [n, k, ell]
-
-    ScreenGeom geom{};
-    int64_t n_pad = 0;
-    void *Xp = nullptr;  // [n_pad, kp] candidate-side screening rows
-    float *mu = nullptr; // [d]
-    double e_max = 0.0, nx_max = 0.0, acc_coef = 0.0;
-    int c_build = 0, c_query = 0;
-    int64_t nonpd = 0, build_fb = 0;
-    unsigned long long *pred_fb = nullptr;
-    uint64_t bytes = 0;
-
-    bool timing = false;
-    hipEvent_t evb[EV_COUNT]{};
-    hipEvent_t evp[EV_COUNT]{};
-    bool pred_recorded = false;
-    double build_ms[EV_COUNT]{};
-};
 
 namespace {
 
@@ -109,6 +76,8 @@ void free_model(fmg_model *M) {
     void *ptrs[] = {M->X, M->N, M->C, M->Xp, M->mu, M->pred_fb};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
+    for (void *h : M->host)
+        if (h) (void)hipHostFree(h);
     if (M->timing)
         for (int e = 0; e < EV_COUNT; ++e) {
             if (M->evb[e]) (void)hipEventDestroy(M->evb[e]);
@@ -130,11 +99,25 @@ void record(fmg_model *M, hipEvent_t *ev, int idx, hipStream_t s) {
     if (M->timing) (void)hipEventRecord(ev[idx], s);
 }
 
-fmg_status model_alloc(fmg_model *M, void **p, size_t bytes, const char *what) {
-    hipError_t e = hipMalloc(p, bytes ? bytes : 16);
+// Allocate one of the model's device arrays (idx < MA_COUNT: a movable
+// array whose size is recorded for offloading).
+fmg_status model_alloc(fmg_model *M, int idx, void **p, size_t bytes, const char *what) {
+    if (bytes == 0) bytes = 16;
+    hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) return hip_fail(e, what);
     M->bytes += bytes;
+    if (idx >= 0 && idx < MA_COUNT) M->arr_bytes[idx] = bytes;
     return FMG_OK;
+}
+
+void **model_array(fmg_model *M, int idx) {
+    switch (idx) {
+    case MA_X: return &M->X;
+    case MA_N: return (void **)&M->N;
+    case MA_C: return &M->C;
+    case MA_XP: return &M->Xp;
+    default: return (void **)&M->mu;
+    }
 }
 
 // Screening geometry for a precision mode and dimension.
@@ -151,6 +134,302 @@ bool screen_geom(int prec, int d, ScreenGeom *g) {
 }
 
 }  // namespace
+
+namespace fmg {
+
+fmg_status set_error(fmg_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+namespace {
+
+// Screen splits of a prediction: enough (split, query-block) pairs to fill
+// the device when the batch is small, bounded by the pool capacity.
+int64_t predict_splits(const fmg_model *M, int64_t m_pad, const PredictWs *ws) {
+    const int64_t qblocks = m_pad / SCREEN_QPB;
+    int64_t splits = (512 + qblocks - 1) / qblocks;
+    int64_t cap = PREDICT_MAX_SPLITS;
+    if (ws) cap = ws->pool_rows / m_pad < cap ? ws->pool_rows / m_pad : cap;
+    // at least 16 tiles of candidates per split
+    const int64_t min_chunk = 16 * SCREEN_TILE;
+    const int64_t by_size = M->n_pad / min_chunk > 0 ? M->n_pad / min_chunk : 1;
+    if (splits > cap) splits = cap;
+    if (splits > by_size) splits = by_size;
+    return splits < 1 ? 1 : splits;
+}
+
+int64_t ws_pool_rows(int64_t max_m) {
+    const int64_t m_pad = round_up(max_m, SCREEN_QPB);
+    const int64_t qblocks = m_pad / SCREEN_QPB;
+    int64_t splits = (512 + qblocks - 1) / qblocks;
+    if (splits > PREDICT_MAX_SPLITS) splits = PREDICT_MAX_SPLITS;
+    if (splits < 1) splits = 1;
+    return splits * m_pad;
+}
+
+constexpr int64_t WS_ROW_BYTES = 256;  // largest screening row (FP32, kp = 64)
+
+}  // namespace
+
+uint64_t predict_ws_bytes(int64_t max_m) {
+    const int64_t m_pad = round_up(max_m, SCREEN_QPB);
+    const int64_t rows = ws_pool_rows(max_m);
+    uint64_t b = 0;
+    b += (uint64_t)m_pad * WS_ROW_BYTES;                 // Zq
+    b += (uint64_t)max_m * 16;                           // ez, nzz
+    b += (uint64_t)rows * SCREEN_CAP * 8;                // pool
+    b += (uint64_t)rows * SCREEN_CMAX * 8;               // cand (c' <= SCREEN_CMAX)
+    b += (uint64_t)rows * 4;                             // tq
+    b += (uint64_t)max_m * 8 + 16;                       // fbl, nn, fbc
+    return b;
+}
+
+fmg_status predict_ws_alloc(PredictWs *ws, int64_t max_m) {
+    *ws = PredictWs{};
+    if (max_m < 1) return fail(FMG_E_INVALID_ARG, "workspace for %lld queries", (long long)max_m);
+    const int64_t m_pad = round_up(max_m, SCREEN_QPB);
+    const int64_t rows = ws_pool_rows(max_m);
+    struct Item {
+        void **p;
+        size_t bytes;
+    } items[] = {
+        {&ws->Zq, (size_t)m_pad * WS_ROW_BYTES},
+        {(void **)&ws->ez, (size_t)max_m * 8},
+        {(void **)&ws->nzz, (size_t)max_m * 8},
+        {(void **)&ws->pool, (size_t)rows * SCREEN_CAP * 8},
+        {(void **)&ws->cand, (size_t)rows * SCREEN_CMAX * 8},
+        {(void **)&ws->tq, (size_t)rows * 4},
+        {(void **)&ws->fbl, (size_t)max_m * 4},
+        {(void **)&ws->nn, (size_t)max_m * 4},
+        {(void **)&ws->fbc, 16},
+    };
+    for (auto &it : items) {
+        hipError_t e = hipMalloc(it.p, it.bytes);
+        if (e != hipSuccess) {
+            predict_ws_free(ws);
+            return hip_fail(e, "prediction workspace");
+        }
+        ws->bytes += it.bytes;
+    }
+    // Query rows past a batch are read by the screen: keep them finite.
+    hipError_t e = hipMemset(ws->Zq, 0, (size_t)m_pad * WS_ROW_BYTES);
+    if (e != hipSuccess) {
+        predict_ws_free(ws);
+        return hip_fail(e, "hipMemset");
+    }
+    ws->max_m = max_m;
+    ws->pool_rows = rows;
+    return FMG_OK;
+}
+
+void predict_ws_free(PredictWs *ws) {
+    void *ptrs[] = {ws->Zq, ws->ez, ws->nzz, ws->pool, ws->cand, ws->tq, ws->fbl, ws->nn, ws->fbc};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    *ws = PredictWs{};
+}
+
+fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_t *nn_out,
+                       hipStream_t s, const PredictWs *ws) {
+    if (!M->resident)
+        return fail(FMG_E_BUSY, "the model is offloaded to host memory (not admitted)");
+    if (ws && m > ws->max_m)
+        return fail(FMG_E_INVALID_ARG, "batch of %lld queries exceeds the workspace (%lld)",
+                    (long long)m, (long long)ws->max_m);
+    const bool f64 = M->prec == FMG_PREC_FP64;
+    Scratch tmp;
+    tmp.stream = s;
+    tmp.async = true;
+    record(M, M->evp, EV_START, s);
+    int32_t *nn = nn_out;
+    if (!nn) {
+        if (ws)
+            nn = ws->nn;
+        else
+            HIPCHK(tmp.alloc((void **)&nn, (size_t)m * 4), "scratch");
+    }
+    if (f64) {
+        record(M, M->evp, EV_PREP, s);
+        ExactArgs ea{};
+        ea.X = M->X;
+        ea.n = M->n;
+        ea.d = M->d;
+        ea.Qc = Z;
+        ea.nq = m;
+        ea.loo = 0;
+        ea.k = 1;
+        ea.out = nn;
+        ea.out_stride = 1;
+        HIPCHK(launch_exact_topk(true, ea, m, s), "exact search");
+        for (int e = EV_SCREEN; e <= EV_FALLBACK; ++e) record(M, M->evp, e, s);
+    } else {
+        const ScreenGeom &g = M->geom;
+        const int64_t m_pad = round_up(m, SCREEN_QPB);
+        int64_t splits = predict_splits(M, m_pad, ws);
+        int64_t chunk = round_up((M->n_pad + splits - 1) / splits, SCREEN_TILE);
+        splits = (M->n_pad + chunk - 1) / chunk;
+        const int c = M->c_query;
+        void *Zq = nullptr;
+        double *ez = nullptr, *nzz = nullptr;
+        uint64_t *pool = nullptr, *cand = nullptr;
+        float *tq = nullptr;
+        int32_t *fbl = nullptr, *fbc = nullptr;
+        if (ws) {
+            Zq = ws->Zq;
+            ez = ws->ez;
+            nzz = ws->nzz;
+            pool = ws->pool;
+            cand = ws->cand;
+            tq = ws->tq;
+            fbl = ws->fbl;
+            fbc = ws->fbc;
+        } else {
+            HIPCHK(tmp.alloc(&Zq, (size_t)m_pad * g.row_bytes), "scratch");
+            HIPCHK(tmp.alloc((void **)&ez, (size_t)m * 8), "scratch");
+            HIPCHK(tmp.alloc((void **)&nzz, (size_t)m * 8), "scratch");
+            HIPCHK(tmp.alloc((void **)&pool, (size_t)splits * m_pad * SCREEN_CAP * 8),
+                   "screen pool");
+            HIPCHK(tmp.alloc((void **)&cand, (size_t)splits * m * c * 8), "scratch");
+            HIPCHK(tmp.alloc((void **)&tq, (size_t)splits * m * 4), "scratch");
+            HIPCHK(tmp.alloc((void **)&fbl, (size_t)m * 4), "scratch");
+            HIPCHK(tmp.alloc((void **)&fbc, 4), "scratch");
+        }
+        HIPCHK(launch_prep_rows(g, (const float *)Z, m, m_pad, M->d, M->mu, Zq, nullptr, ez, nzz,
+                                nullptr, nullptr, s),
+               "query rows");
+        record(M, M->evp, EV_PREP, s);
+        HIPCHK(launch_zero_u32(fbc, 1, s), "zero");
+        ScreenArgs sa{};
+        sa.Q = Zq;
+        sa.P = M->Xp;
+        sa.m = m;
+        sa.m_pad = m_pad;
+        sa.n = M->n;
+        sa.n_pad = M->n_pad;
+        sa.col_chunk = chunk;
+        sa.splits = (int)splits;
+        sa.loo = 0;
+        sa.c = c;
+        sa.pool = pool;
+        sa.cand = cand;
+        sa.tq = tq;
+        HIPCHK(launch_screen(g, sa, s), "screen");
+        record(M, M->evp, EV_SCREEN, s);
+        RerankArgs ra{};
+        ra.cand = cand;
+        ra.tq = tq;
+        ra.splits = (int)splits;
+        ra.c = c;
+        ra.m = m;
+        ra.X = M->X;
+        ra.Zc = Z;
+        ra.d = M->d;
+        ra.nzq = nzz;
+        ra.eq = ez;
+        ra.e_max = M->e_max;
+        ra.acc_coef = M->acc_coef;
+        ra.nx_max = M->nx_max;
+        ra.k = 1;
+        ra.self_first = 0;
+        ra.out = nn;
+        ra.out_stride = 1;
+        ra.fb_list = fbl;
+        ra.fb_count = fbc;
+        HIPCHK(launch_rerank(ra, s), "re-rank");
+        record(M, M->evp, EV_RERANK, s);
+        ExactArgs ea{};
+        ea.X = M->X;
+        ea.n = M->n;
+        ea.d = M->d;
+        ea.Qc = Z;
+        ea.list = fbl;
+        ea.count = fbc;
+        ea.loo = 0;
+        ea.k = 1;
+        ea.out = nn;
+        ea.out_stride = 1;
+        HIPCHK(launch_exact_topk(false, ea, m, s), "exact rescan");
+        HIPCHK(launch_accum(fbc, M->pred_fb, s), "count");
+        record(M, M->evp, EV_FALLBACK, s);
+    }
+    GatherArgs ga{};
+    ga.X = M->X;
+    ga.Z = Z;
+    ga.nn = nn;
+    ga.N = M->N;
+    ga.C = M->C;
+    ga.m = m;
+    ga.d = M->d;
+    ga.ell = M->ell;
+    ga.k = M->k;
+    ga.kc = M->kc;
+    ga.inv_rho = M->inv_rho;
+    ga.amp = M->amp;
+    ga.out = out;
+    HIPCHK(launch_gather(f64, ga, s), "gather");
+    record(M, M->evp, EV_LAST, s);
+    if (M->timing) M->pred_recorded = true;
+    return FMG_OK;
+}
+
+fmg_status model_offload(fmg_model *M) {
+    if (!M->resident) return FMG_OK;
+    HIPCHK(hipDeviceSynchronize(), "sync");
+    for (int a = 0; a < MA_COUNT; ++a) {
+        void **p = model_array(M, a);
+        if (!*p) continue;
+        void *h = nullptr;
+        HIPCHK(hipHostMalloc(&h, M->arr_bytes[a], hipHostMallocDefault), "pinned host memory");
+        M->host[a] = h;
+        HIPCHK(hipMemcpy(h, *p, M->arr_bytes[a], hipMemcpyDeviceToHost), "offload copy");
+    }
+    for (int a = 0; a < MA_COUNT; ++a) {
+        void **p = model_array(M, a);
+        if (!*p) continue;
+        HIPCHK(hipFree(*p), "hipFree");
+        *p = nullptr;
+        M->bytes -= M->arr_bytes[a];
+    }
+    M->resident = false;
+    return FMG_OK;
+}
+
+fmg_status model_restore(fmg_model *M) {
+    if (M->resident) return FMG_OK;
+    for (int a = 0; a < MA_COUNT; ++a) {
+        if (!M->host[a]) continue;
+        void **p = model_array(M, a);
+        hipError_t e = hipMalloc(p, M->arr_bytes[a]);
+        if (e != hipSuccess) {
+            // undo: the model stays offloaded
+            for (int b = 0; b < a; ++b) {
+                void **q = model_array(M, b);
+                if (M->host[b] && *q) {
+                    (void)hipFree(*q);
+                    *q = nullptr;
+                    M->bytes -= M->arr_bytes[b];
+                }
+            }
+            return hip_fail(e, "restore");
+        }
+        M->bytes += M->arr_bytes[a];
+        HIPCHK(hipMemcpy(*p, M->host[a], M->arr_bytes[a], hipMemcpyHostToDevice), "restore copy");
+    }
+    for (int a = 0; a < MA_COUNT; ++a) {
+        if (M->host[a]) (void)hipHostFree(M->host[a]);
+        M->host[a] = nullptr;
+    }
+    M->resident = true;
+    return FMG_OK;
+}
+
+}  // namespace fmg
 
 extern "C" {
 
@@ -235,10 +514,10 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
     }
     // X carries 64 zero elements past its last row: kernels may read a fixed
     // number of coordinates past the end of a row.
-    MCHK(model_alloc(M, &M->X, ((size_t)n * d + 64) * esz, "model X"));
-    MCHK(model_alloc(M, (void **)&M->N, (size_t)n * k * 4, "model N"));
-    MCHK(model_alloc(M, &M->C, (size_t)n * k * ell * esz, "model C"));
-    MCHK(model_alloc(M, (void **)&M->pred_fb, 8, "counters"));
+    MCHK(model_alloc(M, MA_X, &M->X, ((size_t)n * d + 64) * esz, "model X"));
+    MCHK(model_alloc(M, MA_N, (void **)&M->N, (size_t)n * k * 4, "model N"));
+    MCHK(model_alloc(M, MA_C, &M->C, (size_t)n * k * ell * esz, "model C"));
+    MCHK(model_alloc(M, -1, (void **)&M->pred_fb, 8, "counters"));
     HCHK(hipMemsetAsync(M->pred_fb, 0, 8, s), "hipMemsetAsync");
     record(M, M->evb, EV_START, s);
     HCHK(hipMemcpyAsync(M->X, X, (size_t)n * d * esz, hipMemcpyDeviceToDevice, s), "copy X");
@@ -281,12 +560,12 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
     } else {
         const int64_t n_pad = round_up(n, SCREEN_QPB);
         M->n_pad = n_pad;
-        MCHK(model_alloc(M, (void **)&M->mu, (size_t)d * 4, "model mu"));
+        MCHK(model_alloc(M, MA_MU, (void **)&M->mu, (size_t)d * 4, "model mu"));
         if (flags & FMG_FLAG_NO_CENTER)
             HCHK(hipMemsetAsync(M->mu, 0, (size_t)d * 4, s), "hipMemsetAsync");
         else
             HCHK(launch_col_mean(M->X, false, n, d, M->mu, s), "column mean");
-        MCHK(model_alloc(M, &M->Xp, (size_t)n_pad * geom.row_bytes, "model screen rows"));
+        MCHK(model_alloc(M, MA_XP, &M->Xp, (size_t)n_pad * geom.row_bytes, "model screen rows"));
         void *Xq = nullptr;
         double *ex = nullptr, *nzx = nullptr;
         unsigned long long *mx = nullptr;
@@ -434,130 +713,8 @@ fmg_status fastmuygps_predict(const fmg_model *model, const void *Z, int64_t m, 
     if (m == 0) return FMG_OK;
     if (m > 2147483647LL) return fail(FMG_E_INVALID_ARG, "m too large");
     if (!Z || !out) return fail(FMG_E_INVALID_ARG, "Z and out must not be null");
-    fmg_model *M = const_cast<fmg_model *>(model);
-    hipStream_t s = (hipStream_t)stream;
-    const bool f64 = M->prec == FMG_PREC_FP64;
-    Scratch tmp;
-    tmp.stream = s;
-    tmp.async = true;
-    record(M, M->evp, EV_START, s);
-    int32_t *nn = nn_out;
-    if (!nn) HIPCHK(tmp.alloc((void **)&nn, (size_t)m * 4), "scratch");
-    if (f64) {
-        record(M, M->evp, EV_PREP, s);
-        ExactArgs ea{};
-        ea.X = M->X;
-        ea.n = M->n;
-        ea.d = M->d;
-        ea.Qc = Z;
-        ea.nq = m;
-        ea.loo = 0;
-        ea.k = 1;
-        ea.out = nn;
-        ea.out_stride = 1;
-        HIPCHK(launch_exact_topk(true, ea, m, s), "exact search");
-        for (int e = EV_SCREEN; e <= EV_FALLBACK; ++e) record(M, M->evp, e, s);
-    } else {
-        const ScreenGeom &g = M->geom;
-        const int64_t m_pad = round_up(m, SCREEN_QPB);
-        void *Zq = nullptr;
-        double *ez = nullptr, *nzz = nullptr;
-        HIPCHK(tmp.alloc(&Zq, (size_t)m_pad * g.row_bytes), "scratch");
-        HIPCHK(tmp.alloc((void **)&ez, (size_t)m * 8), "scratch");
-        HIPCHK(tmp.alloc((void **)&nzz, (size_t)m * 8), "scratch");
-        HIPCHK(launch_prep_rows(g, (const float *)Z, m, m_pad, M->d, M->mu, Zq, nullptr, ez, nzz,
-                                nullptr, nullptr, s),
-               "query rows");
-        record(M, M->evp, EV_PREP, s);
-        // Split the training columns when there are too few query blocks to
-        // fill the device.
-        const int64_t qblocks = m_pad / SCREEN_QPB;
-        int64_t splits = (512 + qblocks - 1) / qblocks;
-        if (splits > 8) splits = 8;
-        if (splits < 1) splits = 1;
-        int64_t chunk = round_up((M->n_pad + splits - 1) / splits, SCREEN_TILE);
-        splits = (M->n_pad + chunk - 1) / chunk;
-        const int c = M->c_query;
-        uint64_t *pool = nullptr, *cand = nullptr;
-        float *tq = nullptr;
-        int32_t *fbl = nullptr, *fbc = nullptr;
-        HIPCHK(tmp.alloc((void **)&pool, (size_t)splits * m_pad * SCREEN_CAP * 8), "screen pool");
-        HIPCHK(tmp.alloc((void **)&cand, (size_t)splits * m * c * 8), "scratch");
-        HIPCHK(tmp.alloc((void **)&tq, (size_t)splits * m * 4), "scratch");
-        HIPCHK(tmp.alloc((void **)&fbl, (size_t)m * 4), "scratch");
-        HIPCHK(tmp.alloc((void **)&fbc, 4), "scratch");
-        HIPCHK(launch_zero_u32(fbc, 1, s), "zero");
-        ScreenArgs sa{};
-        sa.Q = Zq;
-        sa.P = M->Xp;
-        sa.m = m;
-        sa.m_pad = m_pad;
-        sa.n = M->n;
-        sa.n_pad = M->n_pad;
-        sa.col_chunk = chunk;
-        sa.splits = (int)splits;
-        sa.loo = 0;
-        sa.c = c;
-        sa.pool = pool;
-        sa.cand = cand;
-        sa.tq = tq;
-        HIPCHK(launch_screen(g, sa, s), "screen");
-        record(M, M->evp, EV_SCREEN, s);
-        RerankArgs ra{};
-        ra.cand = cand;
-        ra.tq = tq;
-        ra.splits = (int)splits;
-        ra.c = c;
-        ra.m = m;
-        ra.X = M->X;
-        ra.Zc = Z;
-        ra.d = M->d;
-        ra.nzq = nzz;
-        ra.eq = ez;
-        ra.e_max = M->e_max;
-        ra.acc_coef = M->acc_coef;
-        ra.nx_max = M->nx_max;
-        ra.k = 1;
-        ra.self_first = 0;
-        ra.out = nn;
-        ra.out_stride = 1;
-        ra.fb_list = fbl;
-        ra.fb_count = fbc;
-        HIPCHK(launch_rerank(ra, s), "re-rank");
-        record(M, M->evp, EV_RERANK, s);
-        ExactArgs ea{};
-        ea.X = M->X;
-        ea.n = M->n;
-        ea.d = M->d;
-        ea.Qc = Z;
-        ea.list = fbl;
-        ea.count = fbc;
-        ea.loo = 0;
-        ea.k = 1;
-        ea.out = nn;
-        ea.out_stride = 1;
-        HIPCHK(launch_exact_topk(false, ea, m, s), "exact rescan");
-        HIPCHK(launch_accum(fbc, M->pred_fb, s), "count");
-        record(M, M->evp, EV_FALLBACK, s);
-    }
-    GatherArgs ga{};
-    ga.X = M->X;
-    ga.Z = Z;
-    ga.nn = nn;
-    ga.N = M->N;
-    ga.C = M->C;
-    ga.m = m;
-    ga.d = M->d;
-    ga.ell = M->ell;
-    ga.k = M->k;
-    ga.kc = M->kc;
-    ga.inv_rho = M->inv_rho;
-    ga.amp = M->amp;
-    ga.out = out;
-    HIPCHK(launch_gather(f64, ga, s), "gather");
-    record(M, M->evp, EV_LAST, s);
-    if (M->timing) M->pred_recorded = true;
-    return FMG_OK;
+    return predict_run(const_cast<fmg_model *>(model), Z, m, out, nn_out, (hipStream_t)stream,
+                       nullptr);
 }
 
 fmg_status fastmuygps_info(const fmg_model *model, fmg_info *info) {
@@ -584,6 +741,7 @@ fmg_status fastmuygps_info(const fmg_model *model, fmg_info *info) {
 fmg_status fastmuygps_neighbors(const fmg_model *model, int32_t *dev_out, void *stream) {
     g_err.clear();
     if (!model || !dev_out) return fail(FMG_E_INVALID_ARG, "null argument");
+    if (!model->resident) return fail(FMG_E_BUSY, "the model is offloaded to host memory");
     HIPCHK(hipMemcpyAsync(dev_out, model->N, (size_t)model->n * model->k * 4,
                           hipMemcpyDeviceToDevice, (hipStream_t)stream),
            "copy N");
@@ -593,6 +751,7 @@ fmg_status fastmuygps_neighbors(const fmg_model *model, int32_t *dev_out, void *
 fmg_status fastmuygps_coeffs(const fmg_model *model, void *dev_out, void *stream) {
     g_err.clear();
     if (!model || !dev_out) return fail(FMG_E_INVALID_ARG, "null argument");
+    if (!model->resident) return fail(FMG_E_BUSY, "the model is offloaded to host memory");
     const size_t esz = model->prec == FMG_PREC_FP64 ? 8 : 4;
     HIPCHK(hipMemcpyAsync(dev_out, model->C, (size_t)model->n * model->k * model->ell * esz,
                           hipMemcpyDeviceToDevice, (hipStream_t)stream),

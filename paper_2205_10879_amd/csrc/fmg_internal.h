@@ -1,0 +1,93 @@
+// Host-side internals shared by the library's C ABI (fmg_api.hip) and its
+// request server (fmg_server.hip): the model object, the prediction
+// workspace and the residency helpers.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include "fastmuygps.h"
+#include "fmg_kernels.h"
+
+namespace fmg {
+
+enum { EV_START = 0, EV_PREP, EV_SCREEN, EV_RERANK, EV_FALLBACK, EV_LAST, EV_COUNT };
+
+// Device arrays of a model, in the order they are moved between device and
+// host memory by model_offload / model_restore.
+enum { MA_X = 0, MA_N, MA_C, MA_XP, MA_MU, MA_COUNT };
+
+}  // namespace fmg
+
+struct fmg_model {
+    int64_t n = 0;
+    int d = 0, ell = 0, k = 0;
+    fmg_hyper hyper{};
+    int prec = 0;
+    uint32_t flags = 0;
+    int kc = 0;
+    double inv_rho = 1.0, amp = 1.0;
+    bool self_inc = false;
+    int device = 0;
+
+    void *X = nullptr;     // [n, d] (+ 64 zero elements)
+    int32_t *N = nullptr;  // [n, k]
+    void *C = nullptr;     // [n, k, ell]
+
+    fmg::ScreenGeom geom{};
+    int64_t n_pad = 0;
+    void *Xp = nullptr;   // [n_pad, kp] candidate-side screening rows
+    float *mu = nullptr;  // [d]
+    double e_max = 0.0, nx_max = 0.0, acc_coef = 0.0;
+    int c_build = 0, c_query = 0;
+    int64_t nonpd = 0, build_fb = 0;
+    unsigned long long *pred_fb = nullptr;
+    uint64_t bytes = 0;  // device bytes of the arrays below while resident
+
+    // Residency: sizes of the movable arrays, and their host copies while the
+    // model is offloaded (resident == false).
+    size_t arr_bytes[fmg::MA_COUNT]{};
+    void *host[fmg::MA_COUNT]{};
+    bool resident = true;
+
+    bool timing = false;
+    hipEvent_t evb[fmg::EV_COUNT]{};
+    hipEvent_t evp[fmg::EV_COUNT]{};
+    bool pred_recorded = false;
+    double build_ms[fmg::EV_COUNT]{};
+};
+
+namespace fmg {
+
+// Preallocated device buffers for predictions of up to max_m queries, so
+// that a prediction allocates nothing.  Sized for any model the library can
+// build (screen rows of at most 256 bytes, c' <= SCREEN_CMAX).
+struct PredictWs {
+    int64_t max_m = 0;
+    int64_t pool_rows = 0;  // capacity of the screen pool in (split, query) rows
+    void *Zq = nullptr;
+    double *ez = nullptr, *nzz = nullptr;
+    uint64_t *pool = nullptr, *cand = nullptr;
+    float *tq = nullptr;
+    int32_t *fbl = nullptr, *fbc = nullptr, *nn = nullptr;
+    uint64_t bytes = 0;
+};
+
+constexpr int PREDICT_MAX_SPLITS = 32;
+
+fmg_status set_error(fmg_status st, const char *fmt, ...);
+// Bytes of a workspace for max_m queries.
+uint64_t predict_ws_bytes(int64_t max_m);
+fmg_status predict_ws_alloc(PredictWs *ws, int64_t max_m);
+void predict_ws_free(PredictWs *ws);
+// Prediction for m queries on stream s; ws == nullptr allocates scratch
+// stream-ordered, otherwise every buffer comes from ws (m <= ws->max_m).
+fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_t *nn_out,
+                       hipStream_t s, const PredictWs *ws);
+// Move the model's arrays to pinned host memory and free their device memory
+// (synchronous), or bring them back.
+fmg_status model_offload(fmg_model *M);
+fmg_status model_restore(fmg_model *M);
+
+}  // namespace fmg

@@ -83,3 +83,24 @@ def test_package_has_no_cpu_fallback():
     import paper_2205_10879_amd as fmg
     src = open(fmg.__file__).read()
     assert "oracle" not in src.replace("no fallback", "")
+
+
+def test_server_calls_reject_bad_arguments_before_any_device_call(lib):
+    import paper_2205_10879_amd as fmg
+    h = ctypes.c_void_p()
+    for slots, max_batch in ((9, 100), (-1, 100), (2, 70000), (2, -5)):
+        opts = fmg.FmgServerOpts(slots, max_batch, 1)
+        st = lib.fastmuygps_server_create(0, ctypes.byref(opts), ctypes.byref(h))
+        assert st == fmg.FMG_E_INVALID_ARG and not h.value, (slots, max_batch)
+    assert lib.fastmuygps_server_create(0, None, None) == fmg.FMG_E_INVALID_ARG
+    t = ctypes.c_void_p()
+    fake = ctypes.c_void_p(16)  # never dereferenced: arguments are checked first
+    assert lib.fastmuygps_server_submit(None, 0, fake, 1, fake, 0, ctypes.byref(t)) == \
+        fmg.FMG_E_INVALID_ARG
+    assert lib.fastmuygps_server_wait(None, None) == fmg.FMG_E_INVALID_ARG
+    assert lib.fastmuygps_server_add_model(None, None, None) == fmg.FMG_E_INVALID_ARG
+    assert lib.fastmuygps_server_remove_model(None, 0) == fmg.FMG_E_INVALID_ARG
+    st = fmg.FmgServerStats()
+    assert lib.fastmuygps_server_stats(None, ctypes.byref(st)) == fmg.FMG_E_INVALID_ARG
+    assert lib.fastmuygps_server_reset_stats(None) == fmg.FMG_E_INVALID_ARG
+    lib.fastmuygps_server_destroy(None)
