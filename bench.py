@@ -47,6 +47,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="length of each served (Poisson stream) run; 0 skips serving")
     ap.add_argument("--serve-qps", type=float, default=2.0e6, help="offered queries per second")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy 3 times (scale for HBM counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -63,6 +65,16 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "copies": 3}))
+        return
     log("generating workload n=%d m=%d" % (args.n, args.m))
     w = synth.cfg3(n=args.n, m=args.m)
     X = torch.from_numpy(w.X).to(dev)
@@ -114,7 +126,7 @@ def main():
     roofline = {"bound": "mfma", "kernel": "screen_kernel<OpBF16,2> (build)",
                 "achieved": round(achieved_tflops, 2), "peak": PEAK_BF16_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_BF16_TFLOPS, 4),
-                "traffic": None, "avg_launch_ms": round(screen_ms, 3),
+                "traffic": screen_traffic(args.n), "avg_launch_ms": round(screen_ms, 3),
                 "algorithmic_flops_per_launch": flops}
 
     result = {
@@ -208,6 +220,28 @@ def main():
         result["oracle_sample_max_rel_err_mixed"] = err
 
     print(json.dumps(result), flush=True)
+
+
+def screen_traffic(n):
+    """HBM bytes per launch of the build screen, from the committed counter
+    record (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's reading); None
+    when the record is missing, for another n, or taken on other kernel
+    source than the one built now."""
+    import hashlib
+    rec = os.path.join(ROOT, "profiles", "screen_build_traffic.txt")
+    src = os.path.join(ROOT, "paper_2205_10879_amd", "csrc", "fmg_screen.hip")
+    try:
+        fields = {}
+        for line in open(rec):
+            if ":" in line and not line.startswith("#"):
+                key, val = line.split(":", 1)
+                fields[key.strip()] = val.strip()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if fields.get("source_sha256") != digest or int(fields.get("n", -1)) != n:
+            return None
+        return float(fields["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def serve_run(fmg, synth, np, model, qps, seconds, bmax=4096):

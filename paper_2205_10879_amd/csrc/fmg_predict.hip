@@ -1,10 +1,11 @@
 // Prediction gather-dot (Algorithm 2, prediction loop; Section 3, prediction
 // equation): for query z with nearest training point j,
 //     mu(z)[c] = sum_s phi(||z - x_{N(j)_s}||) * C[j][s][c].
-// One wavefront per query; lane s gathers neighbour N(j)_s, forms its kernel
-// value, multiplies it into row s of C[j] (ell contiguous values, so the
-// wave reads C[j] as one contiguous k*ell block) and the ell sums are wave
-// reductions.  The cross-covariance carries no nugget.
+// One wavefront per query; lane s gathers neighbour N(j)_s with 16-byte
+// loads, forms its kernel value, multiplies it into row s of C[j] (ell
+// contiguous values, so the wave reads C[j] as one contiguous k*ell block)
+// and the ell sums are wave reductions.  The cross-covariance carries no
+// nugget.
 #include "fmg_device.h"
 #include "fmg_kernels.h"
 
@@ -21,7 +22,43 @@ __device__ __forceinline__ float wave_sum_t<float>(float v) { return wave_sum_f3
 template <>
 __device__ __forceinline__ double wave_sum_t<double>(double v) { return wave_sum_f64(v); }
 
-template <typename T>
+// Squared distance of one row pair, coordinates loaded 16 bytes at a time
+// when rows are 16-byte aligned (VEC), with four independent partial sums so
+// that all loads of the row are in flight together.
+template <typename T, bool VEC>
+__device__ __forceinline__ T row_sqdist(const T *__restrict__ z, const T *__restrict__ x, int d) {
+    T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+    if constexpr (VEC && sizeof(T) == 4) {
+#pragma unroll 4
+        for (int c = 0; c < d; c += 4) {
+            const float4 u = *(const float4 *)(z + c);
+            const float4 v = *(const float4 *)(x + c);
+            const float t0 = u.x - v.x, t1 = u.y - v.y, t2 = u.z - v.z, t3 = u.w - v.w;
+            s0 = fmaf(t0, t0, s0);
+            s1 = fmaf(t1, t1, s1);
+            s2 = fmaf(t2, t2, s2);
+            s3 = fmaf(t3, t3, s3);
+        }
+    } else if constexpr (VEC) {
+#pragma unroll 4
+        for (int c = 0; c < d; c += 2) {
+            const double2 u = *(const double2 *)(z + c);
+            const double2 v = *(const double2 *)(x + c);
+            const double t0 = u.x - v.x, t1 = u.y - v.y;
+            s0 = fma(t0, t0, s0);
+            s1 = fma(t1, t1, s1);
+        }
+    } else {
+#pragma unroll 4
+        for (int c = 0; c < d; ++c) {
+            const T t = z[c] - x[c];
+            s0 += t * t;
+        }
+    }
+    return (s0 + s1) + (s2 + s3);
+}
+
+template <typename T, bool VEC>
 __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
     const int lane = lane_id();
     const int64_t q = (int64_t)blockIdx.x * G_WAVES + (threadIdx.x >> 6);
@@ -30,24 +67,25 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
     const T *__restrict__ Z = (const T *)a.Z;
     const T *__restrict__ C = (const T *)a.C;
     const int64_t j = a.nn[q];
+    const int ell = a.ell;
     T w = T(0);
     if (lane < a.k) {
         const int64_t p = a.N[j * a.k + lane];
-        const T *__restrict__ xp = X + p * a.d;
-        const T *__restrict__ zq = Z + q * a.d;
-        T D = T(0);
-        for (int c = 0; c < a.d; ++c) {
-            const T t = zq[c] - xp[c];
-            D += t * t;
-        }
+        const T D = row_sqdist<T, VEC>(Z + q * a.d, X + p * a.d, a.d);
         w = phi_t<T>(D, a.kc, (T)a.inv_rho, (T)a.amp);
     }
-    const T *__restrict__ Cj = C + (j * a.k + lane) * a.ell;
-    T *__restrict__ out = (T *)a.out + q * a.ell;
-    for (int c = 0; c < a.ell; ++c) {
-        T v = (lane < a.k) ? w * Cj[c] : T(0);
-        v = wave_sum_t<T>(v);
-        if (lane == 0) out[c] = v;
+    // Row s of C[j]: ell contiguous values; the wave's rows form one
+    // contiguous block of k * ell values.
+    T v[16];
+    const T *__restrict__ Cj = C + (j * a.k + lane) * ell;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) v[c] = (lane < a.k && c < ell) ? w * Cj[c] : T(0);
+    T *__restrict__ out = (T *)a.out + q * ell;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+        if (c >= ell) break;
+        const T r = wave_sum_t<T>(v[c]);
+        if (lane == 0) out[c] = r;
     }
 }
 
@@ -56,10 +94,20 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
 hipError_t launch_gather(bool f64, const GatherArgs &a, hipStream_t s) {
     if (a.m <= 0) return hipSuccess;
     const unsigned blocks = (unsigned)((a.m + G_WAVES - 1) / G_WAVES);
-    if (f64)
-        hipLaunchKernelGGL(gather_kernel<double>, dim3(blocks), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL(gather_kernel<float>, dim3(blocks), dim3(256), 0, s, a);
+    // Rows are 16-byte aligned when d is a multiple of 4 (float) or 2
+    // (double); device allocations are.
+    if (a.ell > 16) return hipErrorInvalidValue;
+    if (f64) {
+        if (a.d % 2 == 0)
+            hipLaunchKernelGGL((gather_kernel<double, true>), dim3(blocks), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((gather_kernel<double, false>), dim3(blocks), dim3(256), 0, s, a);
+    } else {
+        if (a.d % 4 == 0)
+            hipLaunchKernelGGL((gather_kernel<float, true>), dim3(blocks), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((gather_kernel<float, false>), dim3(blocks), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 
