@@ -87,6 +87,26 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Inclusive prefix sum over the wave with DPP: row shifts by 1, 2, 4 and 8
+// within each row of 16 lanes, then the row-15 and row-31 broadcasts carry
+// the row totals across rows (no LDS round trip).
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+    const int rl = lane & 15;
+    int t = __builtin_amdgcn_mov_dpp(v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    if (rl >= 1) v += t;
+    t = __builtin_amdgcn_mov_dpp(v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    if (rl >= 2) v += t;
+    t = __builtin_amdgcn_mov_dpp(v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    if (rl >= 4) v += t;
+    t = __builtin_amdgcn_mov_dpp(v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    if (rl >= 8) v += t;
+    t = __builtin_amdgcn_mov_dpp(v, 0x142, 0xf, 0xf, false);  // row_bcast:15
+    if ((lane & 31) >= 16) v += t;
+    t = __builtin_amdgcn_mov_dpp(v, 0x143, 0xf, 0xf, false);  // row_bcast:31
+    if (lane >= 32) v += t;
+    return v;
+}
+
 // Radix selection (8-bit digits, most significant first) of the c-th
 // smallest of the wave's 64*PE keys (~0 marks an empty slot).  Returns a bound
 // B such that exactly the c smallest keys satisfy key <= B, or ~0 when fewer
@@ -112,12 +132,7 @@ __device__ __forceinline__ uint64_t radix_kth(const uint64_t (&key)[PE], int c,
         wave_lds_sync();
         const uint4 h = ((const uint4 *)hist)[lane];
         const int own = (int)(h.x + h.y + h.z + h.w);
-        int incl = own;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int o = __shfl_up(incl, d);
-            if (lane >= d) incl += o;
-        }
+        const int incl = wave_incl_scan(own, lane);
         const int excl = incl - own;
         const bool mine = excl < need && need <= incl;
         int bin = 3, before = excl + (int)(h.x + h.y + h.z), inbin = (int)h.w;
@@ -141,8 +156,11 @@ __device__ __forceinline__ uint64_t radix_kth(const uint64_t (&key)[PE], int c,
 // and of padding candidates (index >= n) are dropped here: the screen appends
 // without checking them.  The kept entries go back to the sub-pools round
 // robin (final == false) or to the LDS staging array in any order
-// (final == true).  Returns the kept count; *kmax = largest kept key (~0 if
-// fewer than c were present, meaning no threshold yet).
+// (final == true).  Returns the kept count; *kmax = largest kept key, or ~0
+// if fewer than c were present (then every candidate seen so far is kept and
+// no threshold exists yet).  With exactly c present the largest of them is
+// the threshold: every entry dropped earlier, and every value never appended,
+// lies at or above it.
 template <int PE, int SUB>
 __device__ __forceinline__ int select_pool(uint64_t *__restrict__ qpool, const int (&cg)[4], int c,
                                            uint32_t self, uint32_t n,
@@ -181,7 +199,8 @@ __device__ __forceinline__ int select_pool(uint64_t *__restrict__ qpool, const i
         }
         base += __popcll(m);
     }
-    *kmax = (bound == ~0ull) ? ~0ull : wave_max_u64(mx);
+    const uint64_t mxall = wave_max_u64(mx);
+    *kmax = (base < c) ? ~0ull : mxall;
     return base;
 }
 
@@ -315,29 +334,29 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
                 for (int mt = 0; mt < 4; ++mt) acc[t][mt] = Op::mfma(af[mt], bq[t][s], acc[t][mt]);
         }
 
-        // Candidate selection: one compare per value; a 16x16 tile whose four
-        // values fail in every lane costs one wave-wide test, otherwise each
-        // passing lane appends to its own sub-pool.  The query's own index and
-        // padding candidates may be appended here; the selection drops them.
+        // Candidate selection: the minimum of each lane's four values of a
+        // 16x16 tile is tested first (v_min3 + one compare); a tile whose
+        // minima fail in every lane costs one wave-wide test, otherwise each
+        // passing lane compares its four values and appends to its own
+        // sub-pool.  The query's own index and padding candidates may be
+        // appended here; the selection drops them.
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
-                bool pass[4];
-                uint64_t any = 0;
+                const f32x4 v = acc[t][mt];
+                const float mn = fminf(fminf(v[0], v[1]), fminf(v[2], v[3]));
+                const bool lane_pass = mn <= thr[t];
+                if (__ballot(lane_pass) != 0) {
+                    if (lane_pass) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    pass[i] = acc[t][mt][i] <= thr[t];
-                    any |= __ballot(pass[i]);
-                }
-                if (any != 0) {
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        if (pass[i]) {
-                            const uint32_t p = (uint32_t)(col + mt * 16 + g * 4 + i);
-                            mysub[(uint32_t)(t * 64 * SUB) + (uint32_t)cnt[t]] =
-                                raw_entry(acc[t][mt][i], p);
-                            cnt[t] += 1;
+                        for (int i = 0; i < 4; ++i) {
+                            if (v[i] <= thr[t]) {
+                                const uint32_t p = (uint32_t)(col + mt * 16 + g * 4 + i);
+                                mysub[(uint32_t)(t * 64 * SUB) + (uint32_t)cnt[t]] =
+                                    raw_entry(v[i], p);
+                                cnt[t] += 1;
+                            }
                         }
                     }
                 }
