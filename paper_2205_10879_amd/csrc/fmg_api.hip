@@ -563,8 +563,11 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
         MCHK(model_alloc(M, MA_MU, (void **)&M->mu, (size_t)d * 4, "model mu"));
         if (flags & FMG_FLAG_NO_CENTER)
             HCHK(hipMemsetAsync(M->mu, 0, (size_t)d * 4, s), "hipMemsetAsync");
-        else
-            HCHK(launch_col_mean(M->X, false, n, d, M->mu, s), "column mean");
+        else {
+            double *part = nullptr;
+            HCHK(tmp.alloc((void **)&part, (size_t)col_mean_blocks(n) * d * 8), "scratch");
+            HCHK(launch_col_mean(M->X, false, n, d, M->mu, part, s), "column mean");
+        }
         MCHK(model_alloc(M, MA_XP, &M->Xp, (size_t)n_pad * geom.row_bytes, "model screen rows"));
         void *Xq = nullptr;
         double *ex = nullptr, *nzx = nullptr;

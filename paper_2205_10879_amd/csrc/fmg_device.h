@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #define FMG_WAVE 64
 
 namespace fmg {
@@ -81,6 +83,38 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
 }
 __device__ __forceinline__ XKey readlane_x(const XKey &k, int lane) {
     return XKey{readlane_u64(k.d, lane), (uint32_t)__builtin_amdgcn_readlane((int)k.p, lane)};
+}
+
+// Wave sums through DPP: quad permutes and row rotates give every lane its
+// row-of-16 sum, then the row-15 and row-31 broadcasts carry row totals up;
+// the full sum is valid in lane 63 only.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(uint32_t)lo);
+}
+template <typename T>
+__device__ __forceinline__ T dpp_t_sum_last(T v, int lane) {
+    auto mv = [](auto x, auto ctrl_tag) {
+        constexpr int C = decltype(ctrl_tag)::value;
+        if constexpr (sizeof(T) == 4) return dpp_f32<C>(x);
+        else return dpp_f64<C>(x);
+    };
+    v += mv(v, std::integral_constant<int, 0xb1>{});   // quad_perm [1,0,3,2]
+    v += mv(v, std::integral_constant<int, 0x4e>{});   // quad_perm [2,3,0,1]
+    v += mv(v, std::integral_constant<int, 0x124>{});  // row_ror:4
+    v += mv(v, std::integral_constant<int, 0x128>{});  // row_ror:8
+    T t = mv(v, std::integral_constant<int, 0x142>{}); // row_bcast:15
+    if ((lane & 31) >= 16) v += t;
+    t = mv(v, std::integral_constant<int, 0x143>{});   // row_bcast:31
+    if (lane >= 32) v += t;
+    return v;
 }
 
 __device__ __forceinline__ float wave_sum_f32(float v) {

@@ -104,7 +104,11 @@ struct GatherArgs {
     void *out;
 };
 
-hipError_t launch_col_mean(const void *X, bool f64, int64_t n, int d, float *mu, hipStream_t s);
+// Column mean of X [n, d] into mu [d] (deterministic); part is scratch of
+// col_mean_blocks(n) * d doubles.
+int col_mean_blocks(int64_t n);
+hipError_t launch_col_mean(const void *X, bool f64, int64_t n, int d, float *mu, double *part,
+                           hipStream_t s);
 hipError_t launch_finite_check(const void *A, bool f64, int64_t count, int *flag, hipStream_t s);
 hipError_t launch_prep_rows(const ScreenGeom &g, const float *X, int64_t n, int64_t n_pad, int d,
                             const float *mu, void *Qrows, void *Prows, double *e_out,

@@ -4,7 +4,7 @@
 // One wavefront per query; lane s gathers neighbour N(j)_s with 16-byte
 // loads, forms its kernel value, multiplies it into row s of C[j] (ell
 // contiguous values, so the wave reads C[j] as one contiguous k*ell block)
-// and the ell sums are wave reductions.  The cross-covariance carries no
+// and the ell sums are DPP wave reductions.  The cross-covariance carries no
 // nugget.
 #include "fmg_device.h"
 #include "fmg_kernels.h"
@@ -14,13 +14,6 @@ namespace fmg {
 namespace {
 
 constexpr int G_WAVES = 4;
-
-template <typename T>
-__device__ __forceinline__ T wave_sum_t(T v);
-template <>
-__device__ __forceinline__ float wave_sum_t<float>(float v) { return wave_sum_f32(v); }
-template <>
-__device__ __forceinline__ double wave_sum_t<double>(double v) { return wave_sum_f64(v); }
 
 // Squared distance of one row pair, coordinates loaded 16 bytes at a time
 // when rows are 16-byte aligned (VEC), with four independent partial sums so
@@ -68,24 +61,25 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
     const T *__restrict__ C = (const T *)a.C;
     const int64_t j = a.nn[q];
     const int ell = a.ell;
+    // Row s of C[j]: ell contiguous values; the wave's rows form one
+    // contiguous block of k * ell values.  Its loads only need j, so they
+    // are issued before the neighbour rows.
+    T cv[16];
+    const T *__restrict__ Cj = C + (j * a.k + lane) * ell;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) cv[c] = (lane < a.k && c < ell) ? Cj[c] : T(0);
     T w = T(0);
     if (lane < a.k) {
         const int64_t p = a.N[j * a.k + lane];
         const T D = row_sqdist<T, VEC>(Z + q * a.d, X + p * a.d, a.d);
         w = phi_t<T>(D, a.kc, (T)a.inv_rho, (T)a.amp);
     }
-    // Row s of C[j]: ell contiguous values; the wave's rows form one
-    // contiguous block of k * ell values.
-    T v[16];
-    const T *__restrict__ Cj = C + (j * a.k + lane) * ell;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) v[c] = (lane < a.k && c < ell) ? w * Cj[c] : T(0);
     T *__restrict__ out = (T *)a.out + q * ell;
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
         if (c >= ell) break;
-        const T r = wave_sum_t<T>(v[c]);
-        if (lane == 0) out[c] = r;
+        const T r = dpp_t_sum_last<T>(w * cv[c], lane);
+        if (lane == 63) out[c] = r;
     }
 }
 

@@ -26,22 +26,46 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
     return __uint_as_float((uint32_t)h << 16);
 }
 
+// Column mean in two deterministic passes.  Pass 1: block b sums a fixed
+// chunk of rows; thread (rl, c) of the block adds rows rl, rl + RL, ... of
+// column c (RL = 256 / d row lanes, so a wavefront reads whole rows), and
+// the row lanes are combined in a fixed order.  Pass 2: one block per column
+// sums the chunk partials in a fixed order.
 template <typename T>
-__global__ __launch_bounds__(256) void col_mean_kernel(const T *__restrict__ X, int64_t n, int d,
-                                                       float *__restrict__ mu) {
-    // One block per column; fixed summation order, so the result is
-    // deterministic.
-    const int c = blockIdx.x;
-    __shared__ double part[256];
+__global__ __launch_bounds__(256) void col_partial_kernel(const T *__restrict__ X, int64_t n, int d,
+                                                          int64_t rows_per_block,
+                                                          double *__restrict__ part) {
+    __shared__ double sh[256];
+    const int t = threadIdx.x;
+    const int rlanes = 256 / d;
+    const int c = t % d, rl = t / d;
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r1 = (r0 + rows_per_block < n) ? r0 + rows_per_block : n;
     double s = 0.0;
-    for (int64_t r = threadIdx.x; r < n; r += 256) s += (double)X[r * d + c];
-    part[threadIdx.x] = s;
+    if (rl < rlanes)
+        for (int64_t r = r0 + rl; r < r1; r += rlanes) s += (double)X[r * d + c];
+    sh[t] = s;
+    __syncthreads();
+    if (t < d) {
+        double acc = 0.0;
+        for (int k = 0; k < rlanes; ++k) acc += sh[k * d + t];
+        part[(int64_t)blockIdx.x * d + t] = acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void col_final_kernel(const double *__restrict__ part, int nb,
+                                                        int d, int64_t n, float *__restrict__ mu) {
+    __shared__ double sh[256];
+    const int c = blockIdx.x, t = threadIdx.x;
+    double s = 0.0;
+    for (int b = t; b < nb; b += 256) s += part[(int64_t)b * d + c];
+    sh[t] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        if (t < w) sh[t] += sh[t + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) mu[c] = (float)(part[0] / (double)n);
+    if (t == 0) mu[c] = (float)(sh[0] / (double)n);
 }
 
 template <typename T>
@@ -187,13 +211,24 @@ hipError_t launch_accum(const int32_t *src, unsigned long long *dst, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_col_mean(const void *X, bool f64, int64_t n, int d, float *mu, hipStream_t s) {
+int col_mean_blocks(int64_t n) {
+    int64_t nb = (n + 255) / 256;
+    return (int)(nb > 1024 ? 1024 : (nb < 1 ? 1 : nb));
+}
+
+hipError_t launch_col_mean(const void *X, bool f64, int64_t n, int d, float *mu, double *part,
+                           hipStream_t s) {
+    if (d < 1 || d > 256) return hipErrorInvalidValue;
+    const int nb = col_mean_blocks(n);
+    const int64_t rpb = (n + nb - 1) / nb;
     if (f64)
-        hipLaunchKernelGGL(col_mean_kernel<double>, dim3(d), dim3(256), 0, s,
-                           (const double *)X, n, d, mu);
+        hipLaunchKernelGGL(col_partial_kernel<double>, dim3(nb), dim3(256), 0, s,
+                           (const double *)X, n, d, rpb, part);
     else
-        hipLaunchKernelGGL(col_mean_kernel<float>, dim3(d), dim3(256), 0, s, (const float *)X,
-                           n, d, mu);
+        hipLaunchKernelGGL(col_partial_kernel<float>, dim3(nb), dim3(256), 0, s,
+                           (const float *)X, n, d, rpb, part);
+    hipLaunchKernelGGL(col_final_kernel, dim3(d), dim3(256), 0, s, (const double *)part, nb, d, n,
+                       mu);
     return hipGetLastError();
 }
 
