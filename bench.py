@@ -40,8 +40,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=1_000_000)
     ap.add_argument("--m", type=int, default=200_000)
-    ap.add_argument("--cpu-rows", type=int, default=2048, help="oracle sample: training rows")
-    ap.add_argument("--cpu-queries", type=int, default=2048, help="oracle sample: queries")
+    ap.add_argument("--cpu-rows", type=int, default=8192, help="oracle sample: training rows")
+    ap.add_argument("--cpu-queries", type=int, default=8192, help="oracle sample: queries")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=8.0,
