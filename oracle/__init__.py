@@ -74,6 +74,9 @@ def _load():
         lib.oracle_mean_batch.argtypes = [P, i32, i32, i32, i32, dbl, dbl, dbl, P, i64, P, P,
                                           P, i32]
         lib.oracle_mean_batch.restype = None
+        lib.oracle_muygps_batch.argtypes = [P, P, i64, i32, i32, i32, i32, dbl, dbl, dbl, dbl,
+                                             P, i64, P, P, P, i32]
+        lib.oracle_muygps_batch.restype = None
         lib.oracle_max_threads.argtypes = []
         lib.oracle_max_threads.restype = i32
         _lib = lib
@@ -241,3 +244,25 @@ def predict(X, Y, Z, k: int, kernel="matern", nu=1.5, rho=1.0, noise=0.0, amp=1.
         C_rows = C[inv]
     mu = means(X, Z, nb_rows, C_rows, kernel, nu, rho, amp, nthreads)
     return mu, nn, dm
+
+
+def muygps_predict(X, Y, Z, k: int, kernel="matern", nu=1.5, rho=1.0, noise=0.0, amp=1.0,
+                   nthreads: int = 0):
+    """MuyGPs prediction of novel points (Section 2.1): for each query its own k
+    nearest training points N*, then K(z, X_N*) K(X_N*, X_N*)^{-1} Y(X_N*).
+    Returns (means [m, ell], N* [m, k] int32, status [m])."""
+    X = _f64(X)
+    Y = _f64(Y)
+    if Y.ndim == 1:
+        Y = Y[:, None]
+    Z = _f64(np.atleast_2d(Z))
+    n, d = X.shape
+    ell = Y.shape[1]
+    m = Z.shape[0]
+    nb = np.empty((m, k), dtype=np.int32)
+    out = np.empty((m, ell))
+    st = np.empty(m, dtype=np.int32)
+    _load().oracle_muygps_batch(_ptr(X), _ptr(Y), n, d, ell, int(k), _kernel_code(kernel),
+                                float(nu), float(rho), float(noise), float(amp), _ptr(Z), m,
+                                _ptr(nb), _ptr(out), _ptr(st), int(nthreads))
+    return out, nb, st

@@ -324,6 +324,71 @@ void oracle_mean_batch(const double *X, int d, int ell, int k, int kernel, doubl
                     C + t * (int64_t)k * ell, out + t * ell);
 }
 
+/* MuyGPs prediction of a novel point (Section 2.1, MuyGPs prediction
+ * equation):
+ *   N*(z) = the k nearest training points of z, ties to the smaller index
+ *           (z is not a training point, so nothing is excluded);
+ *   mu(z) = K(z, X_N*) K(X_N*, X_N*)^{-1} Y(X_N*),
+ * with the nugget on the diagonal of K(X_N*, X_N*) only (by index) and none on
+ * the cross-covariance.  The solve is the same Cholesky as the training
+ * loop's; the dot product is the same accumulation as oracle_mean.
+ * Writes nb_out [k] and out [ell]; returns 0, 1 (not positive definite: out
+ * is NaN) or 2 (fewer than k training points). */
+int oracle_muygps_mean(const double *X, const double *Y, int64_t n, int d, int ell, int k,
+                       int kernel, double nu, double rho, double noise, double amp,
+                       const double *z, int32_t *nb_out, double *out)
+{
+    int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * k);
+    double *dist = (double *)malloc(sizeof(double) * k);
+    double *K = (double *)malloc(sizeof(double) * k * k);
+    double *yN = (double *)malloc(sizeof(double) * k * ell);
+    double *w = (double *)malloc(sizeof(double) * k * ell);
+    int st = 0;
+    int64_t got = smallest_keys(X, n, d, z, -1, k, idx, dist);
+    if (got != k) {
+        st = 2;
+    } else {
+        for (int s = 0; s < k; ++s)
+            nb_out[s] = (int32_t)idx[s];
+        oracle_assemble(X, d, nb_out, k, kernel, nu, rho, noise, amp, K);
+        if (oracle_cholesky(K, k) != 0) {
+            st = 1;
+        } else {
+            for (int a = 0; a < k; ++a)
+                for (int c = 0; c < ell; ++c)
+                    yN[a * ell + c] = Y[(int64_t)nb_out[a] * ell + c];
+            for (int c = 0; c < ell; ++c)
+                oracle_cholesky_solve(K, k, yN + c, w + c, ell);
+            oracle_mean(X, d, ell, k, kernel, nu, rho, amp, z, nb_out, w, out);
+        }
+    }
+    if (st != 0)
+        for (int c = 0; c < ell; ++c)
+            out[c] = NAN;
+    free(idx);
+    free(dist);
+    free(K);
+    free(yN);
+    free(w);
+    return st;
+}
+
+/* MuyGPs predictions of m queries: nb_out [m, k], out [m, ell], status [m]. */
+void oracle_muygps_batch(const double *X, const double *Y, int64_t n, int d, int ell, int k,
+                         int kernel, double nu, double rho, double noise, double amp,
+                         const double *Z, int64_t m, int32_t *nb_out, double *out,
+                         int32_t *status_out, int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 8)
+#endif
+    for (int64_t t = 0; t < m; ++t)
+        status_out[t] = oracle_muygps_mean(X, Y, n, d, ell, k, kernel, nu, rho, noise, amp,
+                                           Z + t * d, nb_out + t * k, out + t * ell);
+}
+
 int oracle_max_threads(void)
 {
 #ifdef _OPENMP

@@ -296,3 +296,47 @@ def test_thread_count_does_not_change_results():
     N1, C1, _ = oracle.build_model(X, Y, 10, "matern", 1.5, 0.5, 1e-3, nthreads=1)
     N4, C4, _ = oracle.build_model(X, Y, 10, "matern", 1.5, 0.5, 1e-3, nthreads=4)
     assert np.array_equal(N1, N4) and np.array_equal(C1, C4)
+
+
+# --------------------------------------------------------------------------------------
+# MuyGPs prediction of novel points (Section 2.1, MuyGPs prediction equation)
+# --------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("kernel,nu", [("matern", 0.5), ("matern", 1.5), ("matern", 2.5),
+                                       ("rbf", 0.0)])
+def test_muygps_with_k_equals_n_is_the_dense_gp(kernel, nu):
+    X, Y, Z = synth.small(110, 30, 3, ell=2, seed=31)
+    rho, noise = 1.1, 1e-2
+    mu, nb, st = oracle.muygps_predict(X, Y, Z, X.shape[0], kernel, nu, rho, noise)
+    assert np.all(st == 0)
+    assert rel_err(mu, dense_gp_mean(X, Y, Z, kernel, nu, rho, noise)) < 1e-10
+
+
+@pytest.mark.parametrize("dist,d,k", [("normal", 2, 7), ("grid", 2, 9), ("dups", 3, 5)])
+def test_muygps_neighbourhoods_match_lexsort(dist, d, k):
+    X, Y, Z = synth.small(500, 40, d, ell=1, seed=32, dist=dist)
+    _, nb, _ = oracle.muygps_predict(X, Y, Z, k, "matern", 1.5, 1.0, 1e-2)
+    for t in range(Z.shape[0]):
+        assert nb[t].tolist() == lexsort_order(np_sqdist(X, Z[t]))[:k].tolist()
+
+
+def test_muygps_matches_an_independent_local_solve():
+    X, Y, Z = synth.small(800, 25, 4, ell=3, seed=33)
+    k, rho, noise = 24, 0.8, 2e-2
+    mu, nb, _ = oracle.muygps_predict(X, Y, Z, k, "matern", 2.5, rho, noise)
+    kf = sk_kernel("matern", 2.5, rho)
+    for t in range(Z.shape[0]):
+        idx = lexsort_order(np_sqdist(X, Z[t]))[:k]
+        ref = kf(Z[t:t + 1], X[idx]) @ np.linalg.solve(kf(X[idx]) + noise * np.eye(k), Y[idx])
+        assert rel_err(mu[t], ref[0]) < 1e-11
+
+
+def test_muygps_k1_closed_form():
+    X, Y, Z = synth.small(150, 20, 2, ell=1, seed=34)
+    rho, noise = 0.6, 0.25
+    mu, nb, _ = oracle.muygps_predict(X, Y, Z, 1, "rbf", 0.0, rho, noise)
+    for t in range(Z.shape[0]):
+        p = int(np.argmin(np_sqdist(X, Z[t])))
+        assert nb[t, 0] == p
+        ref = math.exp(-np_sqdist(X[p:p + 1], Z[t])[0] / (2 * rho * rho)) * Y[p, 0] / (1 + noise)
+        assert abs(mu[t, 0] - ref) <= 4e-16 * max(abs(ref), 1e-300) + 1e-300
