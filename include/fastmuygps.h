@@ -115,7 +115,7 @@ typedef struct {
  *   ell : responses per point, 1 <= ell <= 16.
  *   k   : neighbours, 1 <= k <= 64.
  * X and Y are only read during the call; the model keeps its own copies of
- * what prediction needs (X, the neighbour lists N [n,k] and C [n,k,ell]).
+ * what prediction needs (X, Y, the neighbour lists N [n,k] and C [n,k,ell]).
  * The call returns when the model is complete (it synchronises `stream`).
  * Errors: FMG_E_INVALID_ARG (sizes, null pointers, length_scale <= 0,
  * noise_var < 0, nu not supported, non-finite X or Y), FMG_E_UNSUPPORTED,
@@ -139,6 +139,40 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
  * FMG_E_DEVICE. */
 fmg_status fastmuygps_predict(const fmg_model *model, const void *Z, int64_t m, void *out,
                               int32_t *nn_out, void *stream);
+
+/* MuyGPs prediction of novel points (Section 2.1, MuyGPs prediction
+ * equation): the per-query method whose training-data part FastMuyGPs
+ * precomputes.  For every query z:
+ *   N*(z) = the k nearest training points of z (exact, ties to the smaller
+ *           index; the screen, re-rank and certificate of the build, with
+ *           the build's candidate count),
+ *   mu(z) = K(z, X_N*) (K(X_N*, X_N*) + sigma^2 I)^{-1} Y(X_N*),
+ * with the model's k, kernel, hyperparameters and precision (a k x k solve
+ * per query, refined in MIXED as in the build).
+ *   Z       : device pointer [m, d], dtype of the model's X.
+ *   out     : device pointer [m, ell], dtype of the model's X.
+ *   nbr_out : optional device pointer [m, k] int32, receives N*(z) (NULL to
+ *             skip).
+ * Asynchronous on `stream`; scratch is stream-ordered.  A query whose
+ * neighbourhood matrix is not positive definite gets NaN means.
+ * Errors: FMG_E_INVALID_ARG (null model or pointer, m < 0), FMG_E_BUSY
+ * (model offloaded by a server), FMG_E_OOM, FMG_E_DEVICE. */
+fmg_status fastmuygps_predict_muygps(const fmg_model *model, const void *Z, int64_t m, void *out,
+                                     int32_t *nbr_out, void *stream);
+
+/* Leave-one-out predictions of training points (Section 2.1: the MuyGPs
+ * prediction of x_i from its neighbours X_N(i), whose squared errors the
+ * MuyGPs loss Q(theta) averages over a batch): with the model's neighbour
+ * lists and coefficients this is K(x_i, X_N(i)) . C[i] (Section 3,
+ * coefficient equation), no solve needed.  In self-inclusive models
+ * (FMG_FLAG_SELF_INCLUSIVE) the set S_i contains i itself.
+ *   rows : device pointer [b] int32 of training-point indices; an index
+ *          outside [0, n) yields NaN for that row.
+ *   out  : device pointer [b, ell], dtype of the model's X.
+ * Asynchronous on `stream`.  Errors: FMG_E_INVALID_ARG, FMG_E_BUSY,
+ * FMG_E_DEVICE. */
+fmg_status fastmuygps_loo_predict(const fmg_model *model, const int32_t *rows, int64_t b,
+                                  void *out, void *stream);
 
 /* Model metadata (host struct).  Synchronises the device. */
 fmg_status fastmuygps_info(const fmg_model *model, fmg_info *info);

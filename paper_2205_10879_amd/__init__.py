@@ -42,7 +42,8 @@ FLAG_TIMING = 0x8
 # Public C entry points (checked by the CPU tests against include/fastmuygps.h).
 EXPORTS = ("fastmuygps_build", "fastmuygps_predict", "fastmuygps_info", "fastmuygps_neighbors",
            "fastmuygps_coeffs", "fastmuygps_timings", "fastmuygps_free", "fastmuygps_last_error",
-           "fastmuygps_version", "fastmuygps_server_create", "fastmuygps_server_add_model",
+           "fastmuygps_version", "fastmuygps_predict_muygps", "fastmuygps_loo_predict",
+           "fastmuygps_server_create", "fastmuygps_server_add_model",
            "fastmuygps_server_remove_model", "fastmuygps_server_submit", "fastmuygps_server_wait",
            "fastmuygps_server_stats", "fastmuygps_server_reset_stats",
            "fastmuygps_server_destroy")
@@ -102,6 +103,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fastmuygps_build.restype = ctypes.c_int
     lib.fastmuygps_predict.argtypes = [P, P, ctypes.c_int64, P, P, P]
     lib.fastmuygps_predict.restype = ctypes.c_int
+    lib.fastmuygps_predict_muygps.argtypes = [P, P, ctypes.c_int64, P, P, P]
+    lib.fastmuygps_predict_muygps.restype = ctypes.c_int
+    lib.fastmuygps_loo_predict.argtypes = [P, P, ctypes.c_int64, P, P]
+    lib.fastmuygps_loo_predict.restype = ctypes.c_int
     lib.fastmuygps_info.argtypes = [P, ctypes.POINTER(FmgInfo)]
     lib.fastmuygps_info.restype = ctypes.c_int
     lib.fastmuygps_neighbors.argtypes = [P, P, P]
@@ -204,6 +209,38 @@ class Model:
         _check(lib().fastmuygps_predict(self.handle, _dev_ptr(Z, self.dtype, "Z"), m,
                                        _dev_ptr(out, self.dtype, "out"), nn_ptr,
                                        _stream_handle(stream)))
+        return out
+
+    def predict_muygps(self, Z: torch.Tensor, out: torch.Tensor | None = None,
+                       nbr_out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """fastmuygps_predict_muygps: MuyGPs means [m, ell] (Section 2.1), each query
+        solving over its own k nearest training points."""
+        if Z.dim() != 2 or Z.shape[1] != self.d:
+            raise ValueError("Z must be [m, %d]" % self.d)
+        m = Z.shape[0]
+        if out is None:
+            out = torch.empty((m, self.ell), dtype=self.dtype, device=Z.device)
+        nb_ptr = None
+        if nbr_out is not None:
+            if tuple(nbr_out.shape) != (m, self.k):
+                raise ValueError("nbr_out must be [m, %d]" % self.k)
+            nb_ptr = _dev_ptr(nbr_out, torch.int32, "nbr_out")
+        _check(lib().fastmuygps_predict_muygps(self.handle, _dev_ptr(Z, self.dtype, "Z"), m,
+                                              _dev_ptr(out, self.dtype, "out"), nb_ptr,
+                                              _stream_handle(stream)))
+        return out
+
+    def loo_predict(self, rows: torch.Tensor, out: torch.Tensor | None = None,
+                    stream=None) -> torch.Tensor:
+        """fastmuygps_loo_predict: leave-one-out predictions [b, ell] of training rows."""
+        if rows.dim() != 1:
+            raise ValueError("rows must be a 1-D int32 tensor")
+        b = rows.shape[0]
+        if out is None:
+            out = torch.empty((b, self.ell), dtype=self.dtype, device=rows.device)
+        _check(lib().fastmuygps_loo_predict(self.handle, _dev_ptr(rows, torch.int32, "rows"), b,
+                                           _dev_ptr(out, self.dtype, "out"),
+                                           _stream_handle(stream)))
         return out
 
     def info(self) -> dict:

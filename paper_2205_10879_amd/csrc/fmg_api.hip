@@ -73,7 +73,7 @@ namespace {
 
 void free_model(fmg_model *M) {
     if (!M) return;
-    void *ptrs[] = {M->X, M->N, M->C, M->Xp, M->mu, M->pred_fb};
+    void *ptrs[] = {M->X, M->N, M->C, M->Xp, M->mu, M->Y, M->pred_fb};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (void *h : M->host)
@@ -116,6 +116,7 @@ void **model_array(fmg_model *M, int idx) {
     case MA_N: return (void **)&M->N;
     case MA_C: return &M->C;
     case MA_XP: return &M->Xp;
+    case MA_Y: return &M->Y;
     default: return (void **)&M->mu;
     }
 }
@@ -365,6 +366,8 @@ fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_
     ga.N = M->N;
     ga.C = M->C;
     ga.m = m;
+    ga.zrows = m;
+    ga.crows = M->n;
     ga.d = M->d;
     ga.ell = M->ell;
     ga.k = M->k;
@@ -517,10 +520,12 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
     MCHK(model_alloc(M, MA_X, &M->X, ((size_t)n * d + 64) * esz, "model X"));
     MCHK(model_alloc(M, MA_N, (void **)&M->N, (size_t)n * k * 4, "model N"));
     MCHK(model_alloc(M, MA_C, &M->C, (size_t)n * k * ell * esz, "model C"));
+    MCHK(model_alloc(M, MA_Y, &M->Y, (size_t)n * ell * esz, "model Y"));
     MCHK(model_alloc(M, -1, (void **)&M->pred_fb, 8, "counters"));
     HCHK(hipMemsetAsync(M->pred_fb, 0, 8, s), "hipMemsetAsync");
     record(M, M->evb, EV_START, s);
     HCHK(hipMemcpyAsync(M->X, X, (size_t)n * d * esz, hipMemcpyDeviceToDevice, s), "copy X");
+    HCHK(hipMemcpyAsync(M->Y, Y, (size_t)n * ell * esz, hipMemcpyDeviceToDevice, s), "copy Y");
     HCHK(hipMemsetAsync((char *)M->X + (size_t)n * d * esz, 0, 64 * esz, s), "hipMemsetAsync");
 
     // Inputs must be finite.
@@ -718,6 +723,188 @@ fmg_status fastmuygps_predict(const fmg_model *model, const void *Z, int64_t m, 
     if (!Z || !out) return fail(FMG_E_INVALID_ARG, "Z and out must not be null");
     return predict_run(const_cast<fmg_model *>(model), Z, m, out, nn_out, (hipStream_t)stream,
                        nullptr);
+}
+
+fmg_status fastmuygps_predict_muygps(const fmg_model *model, const void *Z, int64_t m, void *out,
+                                     int32_t *nbr_out, void *stream) {
+    g_err.clear();
+    if (!model) return fail(FMG_E_INVALID_ARG, "model is null");
+    if (m < 0) return fail(FMG_E_INVALID_ARG, "m = %lld < 0", (long long)m);
+    if (m == 0) return FMG_OK;
+    if (m > 2147483647LL) return fail(FMG_E_INVALID_ARG, "m too large");
+    if (!Z || !out) return fail(FMG_E_INVALID_ARG, "Z and out must not be null");
+    fmg_model *M = const_cast<fmg_model *>(model);
+    if (!M->resident) return fail(FMG_E_BUSY, "the model is offloaded to host memory");
+    hipStream_t s = (hipStream_t)stream;
+    const bool f64 = M->prec == FMG_PREC_FP64;
+    const int k = M->k;
+    const size_t esz = f64 ? 8 : 4;
+    Scratch tmp;
+    tmp.stream = s;
+    tmp.async = true;
+    int32_t *nb = nbr_out;
+    if (!nb) HIPCHK(tmp.alloc((void **)&nb, (size_t)m * k * 4), "scratch");
+
+    // 1. The query's own k nearest training points (nothing excluded).
+    if (f64) {
+        ExactArgs ea{};
+        ea.X = M->X;
+        ea.n = M->n;
+        ea.d = M->d;
+        ea.Qc = Z;
+        ea.nq = m;
+        ea.loo = 0;
+        ea.k = k;
+        ea.out = nb;
+        ea.out_stride = k;
+        HIPCHK(launch_exact_topk(true, ea, m, s), "exact search");
+    } else {
+        const ScreenGeom &g = M->geom;
+        const int64_t m_pad = round_up(m, SCREEN_QPB);
+        int64_t splits = predict_splits(M, m_pad, nullptr);
+        if (splits > 8) splits = 8;
+        const int64_t chunk = round_up((M->n_pad + splits - 1) / splits, SCREEN_TILE);
+        splits = (M->n_pad + chunk - 1) / chunk;
+        const int c = M->prec == FMG_PREC_MIXED ? 2 * k : k + 8;
+        void *Zq = nullptr;
+        double *ez = nullptr, *nzz = nullptr;
+        uint64_t *pool = nullptr, *cand = nullptr;
+        float *tq = nullptr;
+        int32_t *fbl = nullptr, *fbc = nullptr;
+        HIPCHK(tmp.alloc(&Zq, (size_t)m_pad * g.row_bytes), "scratch");
+        HIPCHK(tmp.alloc((void **)&ez, (size_t)m * 8), "scratch");
+        HIPCHK(tmp.alloc((void **)&nzz, (size_t)m * 8), "scratch");
+        HIPCHK(tmp.alloc((void **)&pool, (size_t)splits * m_pad * SCREEN_CAP * 8), "screen pool");
+        HIPCHK(tmp.alloc((void **)&cand, (size_t)splits * m * c * 8), "scratch");
+        HIPCHK(tmp.alloc((void **)&tq, (size_t)splits * m * 4), "scratch");
+        HIPCHK(tmp.alloc((void **)&fbl, (size_t)m * 4), "scratch");
+        HIPCHK(tmp.alloc((void **)&fbc, 4), "scratch");
+        HIPCHK(launch_prep_rows(g, (const float *)Z, m, m_pad, M->d, M->mu, Zq, nullptr, ez, nzz,
+                                nullptr, nullptr, s),
+               "query rows");
+        HIPCHK(launch_zero_u32((uint32_t *)fbc, 1, s), "zero");
+        ScreenArgs sa{};
+        sa.Q = Zq;
+        sa.P = M->Xp;
+        sa.m = m;
+        sa.m_pad = m_pad;
+        sa.n = M->n;
+        sa.n_pad = M->n_pad;
+        sa.col_chunk = chunk;
+        sa.splits = (int)splits;
+        sa.loo = 0;
+        sa.c = c;
+        sa.pool = pool;
+        sa.cand = cand;
+        sa.tq = tq;
+        HIPCHK(launch_screen(g, sa, s), "screen");
+        RerankArgs ra{};
+        ra.cand = cand;
+        ra.tq = tq;
+        ra.splits = (int)splits;
+        ra.c = c;
+        ra.m = m;
+        ra.X = M->X;
+        ra.Zc = Z;
+        ra.d = M->d;
+        ra.nzq = nzz;
+        ra.eq = ez;
+        ra.e_max = M->e_max;
+        ra.acc_coef = M->acc_coef;
+        ra.nx_max = M->nx_max;
+        ra.k = k;
+        ra.self_first = 0;
+        ra.out = nb;
+        ra.out_stride = k;
+        ra.fb_list = fbl;
+        ra.fb_count = fbc;
+        HIPCHK(launch_rerank(ra, s), "re-rank");
+        ExactArgs ea{};
+        ea.X = M->X;
+        ea.n = M->n;
+        ea.d = M->d;
+        ea.Qc = Z;
+        ea.list = fbl;
+        ea.count = fbc;
+        ea.loo = 0;
+        ea.k = k;
+        ea.out = nb;
+        ea.out_stride = k;
+        HIPCHK(launch_exact_topk(false, ea, m, s), "exact rescan");
+    }
+
+    // 2. Per-query coefficients K(X_N*, X_N*)^{-1} Y(X_N*), centred on z.
+    void *Cz = nullptr;
+    int32_t *stq = nullptr;
+    HIPCHK(tmp.alloc(&Cz, (size_t)m * k * M->ell * esz), "scratch");
+    HIPCHK(tmp.alloc((void **)&stq, (size_t)m * 4), "scratch");
+    PrecomputeArgs pa{};
+    pa.X = M->X;
+    pa.Y = M->Y;
+    pa.n = m;
+    pa.d = M->d;
+    pa.ell = M->ell;
+    pa.k = k;
+    pa.N = nb;
+    pa.C = Cz;
+    pa.status = stq;
+    pa.kc = M->kc;
+    pa.inv_rho = M->inv_rho;
+    pa.amp = M->amp;
+    pa.noise = M->hyper.noise_var;
+    pa.Ctr = f64 ? nullptr : Z;
+    const bool refine = M->prec == FMG_PREC_MIXED && !(M->flags & FMG_FLAG_NO_REFINE);
+    HIPCHK(launch_precompute(f64, refine, pa, s), "precompute");
+
+    // 3. mu(z) = K(z, X_N*) . C_z
+    GatherArgs ga{};
+    ga.X = M->X;
+    ga.Z = Z;
+    ga.N = nb;
+    ga.C = Cz;
+    ga.m = m;
+    ga.zrows = m;
+    ga.crows = m;
+    ga.d = M->d;
+    ga.ell = M->ell;
+    ga.k = k;
+    ga.kc = M->kc;
+    ga.inv_rho = M->inv_rho;
+    ga.amp = M->amp;
+    ga.out = out;
+    HIPCHK(launch_gather(f64, ga, s), "gather");
+    return FMG_OK;
+}
+
+fmg_status fastmuygps_loo_predict(const fmg_model *model, const int32_t *rows, int64_t b,
+                                  void *out, void *stream) {
+    g_err.clear();
+    if (!model) return fail(FMG_E_INVALID_ARG, "model is null");
+    if (b < 0) return fail(FMG_E_INVALID_ARG, "b = %lld < 0", (long long)b);
+    if (b == 0) return FMG_OK;
+    if (b > 2147483647LL) return fail(FMG_E_INVALID_ARG, "b too large");
+    if (!rows || !out) return fail(FMG_E_INVALID_ARG, "rows and out must not be null");
+    const fmg_model *M = model;
+    if (!M->resident) return fail(FMG_E_BUSY, "the model is offloaded to host memory");
+    GatherArgs ga{};
+    ga.X = M->X;
+    ga.Z = M->X;
+    ga.zrow = rows;
+    ga.nn = rows;
+    ga.N = M->N;
+    ga.C = M->C;
+    ga.m = b;
+    ga.zrows = M->n;
+    ga.crows = M->n;
+    ga.d = M->d;
+    ga.ell = M->ell;
+    ga.k = M->k;
+    ga.kc = M->kc;
+    ga.inv_rho = M->inv_rho;
+    ga.amp = M->amp;
+    ga.out = out;
+    HIPCHK(launch_gather(M->prec == FMG_PREC_FP64, ga, (hipStream_t)stream), "gather");
+    return FMG_OK;
 }
 
 fmg_status fastmuygps_info(const fmg_model *model, fmg_info *info) {

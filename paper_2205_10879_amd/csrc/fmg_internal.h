@@ -16,7 +16,7 @@ enum { EV_START = 0, EV_PREP, EV_SCREEN, EV_RERANK, EV_FALLBACK, EV_LAST, EV_COU
 
 // Device arrays of a model, in the order they are moved between device and
 // host memory by model_offload / model_restore.
-enum { MA_X = 0, MA_N, MA_C, MA_XP, MA_MU, MA_COUNT };
+enum { MA_X = 0, MA_N, MA_C, MA_XP, MA_MU, MA_Y, MA_COUNT };
 
 }  // namespace fmg
 
@@ -34,6 +34,7 @@ struct fmg_model {
     void *X = nullptr;     // [n, d] (+ 64 zero elements)
     int32_t *N = nullptr;  // [n, k]
     void *C = nullptr;     // [n, k, ell]
+    void *Y = nullptr;     // [n, ell] responses (MuyGPs and leave-one-out predictions)
 
     fmg::ScreenGeom geom{};
     int64_t n_pad = 0;

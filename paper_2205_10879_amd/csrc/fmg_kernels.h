@@ -87,17 +87,22 @@ struct PrecomputeArgs {
     const int32_t *N;  // [n, k]
     void *C;           // [n, k, ell]
     int32_t *status;   // [n] 0 ok, 1 not positive definite
+    const void *Ctr;   // [n, d] centre of row i's neighbourhood (nullptr: X row i);
+                       // any point works: kernel values depend on differences only
     int kc;            // kernel code (fmg_device.h)
     double inv_rho, amp, noise;
 };
 
 struct GatherArgs {
     const void *X;
-    const void *Z;
-    const int32_t *nn;
-    const int32_t *N;
-    const void *C;
+    const void *Z;         // query coordinates
+    const int32_t *zrow;   // optional: query q is row zrow[q] of Z (else row q)
+    const int32_t *nn;     // optional: coefficient row of query q (else q)
+    const int32_t *N;      // neighbourhood rows [*, k]
+    const void *C;         // coefficient rows [*, k, ell]
     int64_t m;
+    int64_t zrows;         // rows of Z (bound of zrow entries)
+    int64_t crows;         // rows of N and C (bound of nn entries)
     int d, ell, k;
     int kc;
     double inv_rho, amp;

@@ -89,14 +89,15 @@ __host__ __device__ __forceinline__ PcLayout pc_layout(int k, int d, int kmax, i
 
 // Stage rows N(i)_b (b < k) centred on x_i (difference in FP64, rounded to
 // FP32) into xs[b][0..d), zero padded to a multiple of 4; lane b loads row b,
-// four coordinates per load when rows are 16-byte aligned.
-__device__ __forceinline__ void stage_rows(const float *__restrict__ X, int d, int k, int64_t i,
-                                           int64_t p, float *__restrict__ xs, int ld, int a) {
-    const float *__restrict__ xi = X + i * d;
+// four coordinates per load when rows are 16-byte aligned.  xi is the centre
+// (the training point itself, or a query for per-query solves).
+__device__ __forceinline__ void stage_rows(const float *__restrict__ X, int d, int k,
+                                           const float *__restrict__ xi, int64_t p,
+                                           float *__restrict__ xs, int ld, int a) {
     const float *__restrict__ xp = X + p * d;
     if (a >= k) return;
     float *row = xs + a * ld;
-    if ((d & 3) == 0) {
+    if ((d & 3) == 0 && (((uintptr_t)X | (uintptr_t)xi) & 15) == 0) {
 #pragma unroll 4
         for (int c = 0; c < d; c += 4) {
             const float4 u = *(const float4 *)(xp + c);
@@ -115,14 +116,13 @@ __device__ __forceinline__ void stage_rows(const float *__restrict__ X, int d, i
 
 // The same rows exactly in FP64 (refinement); returns |x_a - x_i|^2.
 __device__ __forceinline__ double stage_rows64(const float *__restrict__ X, int d, int k,
-                                               int64_t i, int64_t p, double *__restrict__ x64,
-                                               int ld, int a) {
-    const float *__restrict__ xi = X + i * d;
+                                               const float *__restrict__ xi, int64_t p,
+                                               double *__restrict__ x64, int ld, int a) {
     const float *__restrict__ xp = X + p * d;
     double n64 = 0.0;
     if (a >= k) return n64;
     double *row = x64 + a * ld;
-    if ((d & 3) == 0) {
+    if ((d & 3) == 0 && (((uintptr_t)X | (uintptr_t)xi) & 15) == 0) {
 #pragma unroll 4
         for (int c = 0; c < d; c += 4) {
             const float4 u = *(const float4 *)(xp + c);
@@ -264,13 +264,14 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
     const float *__restrict__ X = (const float *)P.X;
     const float *__restrict__ Y = (const float *)P.Y;
 
-    const int64_t p = (a < k) ? (int64_t)P.N[i * k + a] : i;
+    const int64_t p = (a < k) ? (int64_t)P.N[i * k + a] : (int64_t)P.N[i * k];
+    const float *__restrict__ xi = (P.Ctr ? (const float *)P.Ctr : X) + i * d;
     float y[ELLMAX];
 #pragma unroll
     for (int c = 0; c < ELLMAX; ++c) y[c] = (a < k && c < ell) ? Y[p * ell + c] : 0.0f;
 
     // 1. Gram matrix of the centred rows on FP32 MFMA.
-    stage_rows(X, d, k, i, p, xs, L.xs_ld, a);
+    stage_rows(X, d, k, xi, p, xs, L.xs_ld, a);
     lds_sync();
     constexpr int NT = KMAX / 16;
     f32x4 acc[NT][NT];
@@ -378,7 +379,7 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
         // the transposed tile, so K never leaves registers.
         const int ld = L.x64_ld, d4 = (d + 3) & ~3;
         lds_sync();  // the Gram staging area is dead
-        nrm64[a] = stage_rows64(X, d, k, i, p, x64, ld, a);
+        nrm64[a] = stage_rows64(X, d, k, xi, p, x64, ld, a);
         float *cb = bc;  // [64][ELLMAX] current coefficients, zero past k / ell
 #pragma unroll
         for (int c = 0; c < ELLMAX; ++c) cb[a * ELLMAX + c] = (a < k && c < ell) ? y[c] : 0.0f;

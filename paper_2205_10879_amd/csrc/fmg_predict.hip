@@ -59,8 +59,14 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
     const T *__restrict__ X = (const T *)a.X;
     const T *__restrict__ Z = (const T *)a.Z;
     const T *__restrict__ C = (const T *)a.C;
-    const int64_t j = a.nn[q];
+    const int64_t zr = a.zrow ? (int64_t)a.zrow[q] : q;
+    const int64_t j = a.nn ? (int64_t)a.nn[q] : q;
     const int ell = a.ell;
+    T *__restrict__ out = (T *)a.out + q * ell;
+    if (zr < 0 || zr >= a.zrows || j < 0 || j >= a.crows) {  // a caller's row list
+        if (lane < ell) out[lane] = (T)NAN;
+        return;
+    }
     // Row s of C[j]: ell contiguous values; the wave's rows form one
     // contiguous block of k * ell values.  Its loads only need j, so they
     // are issued before the neighbour rows.
@@ -71,10 +77,9 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
     T w = T(0);
     if (lane < a.k) {
         const int64_t p = a.N[j * a.k + lane];
-        const T D = row_sqdist<T, VEC>(Z + q * a.d, X + p * a.d, a.d);
+        const T D = row_sqdist<T, VEC>(Z + zr * a.d, X + p * a.d, a.d);
         w = phi_t<T>(D, a.kc, (T)a.inv_rho, (T)a.amp);
     }
-    T *__restrict__ out = (T *)a.out + q * ell;
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
         if (c >= ell) break;
@@ -89,15 +94,16 @@ hipError_t launch_gather(bool f64, const GatherArgs &a, hipStream_t s) {
     if (a.m <= 0) return hipSuccess;
     const unsigned blocks = (unsigned)((a.m + G_WAVES - 1) / G_WAVES);
     // Rows are 16-byte aligned when d is a multiple of 4 (float) or 2
-    // (double); device allocations are.
+    // (double) and both arrays start on a 16-byte boundary.
     if (a.ell > 16) return hipErrorInvalidValue;
+    const bool base16 = (((uintptr_t)a.X | (uintptr_t)a.Z) & 15) == 0;
     if (f64) {
-        if (a.d % 2 == 0)
+        if (a.d % 2 == 0 && base16)
             hipLaunchKernelGGL((gather_kernel<double, true>), dim3(blocks), dim3(256), 0, s, a);
         else
             hipLaunchKernelGGL((gather_kernel<double, false>), dim3(blocks), dim3(256), 0, s, a);
     } else {
-        if (a.d % 4 == 0)
+        if (a.d % 4 == 0 && base16)
             hipLaunchKernelGGL((gather_kernel<float, true>), dim3(blocks), dim3(256), 0, s, a);
         else
             hipLaunchKernelGGL((gather_kernel<float, false>), dim3(blocks), dim3(256), 0, s, a);

@@ -104,3 +104,14 @@ def test_server_calls_reject_bad_arguments_before_any_device_call(lib):
     assert lib.fastmuygps_server_stats(None, ctypes.byref(st)) == fmg.FMG_E_INVALID_ARG
     assert lib.fastmuygps_server_reset_stats(None) == fmg.FMG_E_INVALID_ARG
     lib.fastmuygps_server_destroy(None)
+
+
+def test_muygps_and_loo_calls_reject_bad_arguments(lib):
+    import paper_2205_10879_amd as fmg
+    fake = ctypes.c_void_p(16)  # never dereferenced: arguments are checked first
+    assert lib.fastmuygps_predict_muygps(None, fake, 5, fake, None, None) == fmg.FMG_E_INVALID_ARG
+    assert lib.fastmuygps_predict_muygps(fake, None, 5, fake, None, None) == fmg.FMG_E_INVALID_ARG
+    assert lib.fastmuygps_predict_muygps(fake, fake, -1, fake, None, None) == fmg.FMG_E_INVALID_ARG
+    assert lib.fastmuygps_loo_predict(None, fake, 5, fake, None) == fmg.FMG_E_INVALID_ARG
+    assert lib.fastmuygps_loo_predict(fake, None, 5, fake, None) == fmg.FMG_E_INVALID_ARG
+    assert lib.fastmuygps_loo_predict(fake, fake, -2, fake, None) == fmg.FMG_E_INVALID_ARG

@@ -1,0 +1,96 @@
+"""GPU parity of the MuyGPs prediction of novel points (Section 2.1) and of
+the leave-one-out predictions of training points, through the C ABI, against
+the FP64 oracle: neighbourhoods N*(z) bit-exact, means within the mode's
+tolerance."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.parity_util import TOL_MEAN, rel_err
+
+pytestmark = pytest.mark.gpu
+
+DT = {"fp64": (np.float64, torch.float64), "fp32": (np.float32, torch.float32),
+      "mixed": (np.float32, torch.float32)}
+
+
+def fmg():
+    import paper_2205_10879_amd as f
+    return f
+
+
+def build(prec, X, Y, k, kernel, nu, rho, noise, flags=0):
+    npdt, tdt = DT[prec]
+    X = np.ascontiguousarray(X, dtype=npdt)
+    Y = np.ascontiguousarray(Y, dtype=npdt)
+    model = fmg().fastmuygps_build(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), k,
+                                   kernel, nu, rho, noise, precision=prec, flags=flags)
+    return model, X, Y
+
+
+# Length scales keep the neighbourhood matrices moderately conditioned (see
+# test_gpu_small for the FP32 error bound).
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+@pytest.mark.parametrize("n,m,d,k,ell,kernel,nu,rho", [
+    (3001, 333, 3, 20, 2, "matern", 1.5, 0.3),
+    (1500, 257, 8, 50, 3, "matern", 2.5, 1.0),
+    (2200, 64, 5, 64, 1, "rbf", 0.0, 0.8)])
+def test_muygps_matches_oracle(prec, n, m, d, k, ell, kernel, nu, rho):
+    noise = 1e-2
+    X, Y, Z = synth.small(n, m, d, ell=ell, seed=51 + d)
+    model, X, Y = build(prec, X, Y, k, kernel, nu, rho, noise)
+    Z = np.ascontiguousarray(Z, dtype=DT[prec][0])
+    nb = torch.empty((m, k), dtype=torch.int32, device="cuda")
+    mu = model.predict_muygps(torch.from_numpy(Z).cuda(), nbr_out=nb)
+    torch.cuda.synchronize()
+    model.free()
+    ref, nb_ref, st = oracle.muygps_predict(X.astype(np.float64), Y.astype(np.float64),
+                                            Z.astype(np.float64), k, kernel, nu, rho, noise)
+    assert np.all(st == 0)
+    assert np.array_equal(nb.cpu().numpy(), nb_ref)
+    assert rel_err(mu.cpu().numpy(), ref) <= TOL_MEAN[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_muygps_with_k_equals_n(prec):
+    # every training point is in every neighbourhood: the dense GP mean (the
+    # build needs the self-inclusive reading to accept k = n)
+    X, Y, Z = synth.small(48, 40, 2, ell=2, seed=61)
+    model, X, Y = build(prec, X, Y, 48, "matern", 2.5, 0.6, 1e-2,
+                        flags=fmg().FLAG_SELF_INCLUSIVE)
+    Z = np.ascontiguousarray(Z, dtype=DT[prec][0])
+    mu = model.predict_muygps(torch.from_numpy(Z).cuda()).cpu().numpy()
+    model.free()
+    ref, _, _ = oracle.muygps_predict(X.astype(np.float64), Y.astype(np.float64),
+                                      Z.astype(np.float64), 48, "matern", 2.5, 0.6, 1e-2)
+    assert rel_err(mu, ref) <= TOL_MEAN[prec]
+
+
+def test_muygps_empty_and_single_query():
+    X, Y, Z = synth.small(500, 1, 3, ell=1, seed=62, dtype=np.float32)
+    model, X, Y = build("mixed", X, Y, 10, "matern", 1.5, 0.5, 1e-2)
+    empty = model.predict_muygps(torch.empty((0, 3), dtype=torch.float32, device="cuda"))
+    assert empty.shape == (0, 1)
+    mu = model.predict_muygps(torch.from_numpy(Z).cuda()).cpu().numpy()
+    model.free()
+    ref, _, _ = oracle.muygps_predict(X.astype(np.float64), Y.astype(np.float64),
+                                      Z.astype(np.float64), 10, "matern", 1.5, 0.5, 1e-2)
+    assert rel_err(mu, ref) <= TOL_MEAN["mixed"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+def test_loo_predict_matches_oracle(prec):
+    n, k, rho, noise = 4000, 30, 0.9, 1e-2
+    X, Y, _ = synth.small(n, 1, 4, ell=3, seed=63)
+    model, X, Y = build(prec, X, Y, k, "matern", 1.5, rho, noise)
+    rows = np.array([0, 1, 2, 777, 1999, n - 1, -1, n], dtype=np.int32)
+    out = model.loo_predict(torch.from_numpy(rows).cuda()).cpu().numpy()
+    model.free()
+    X64, Y64 = X.astype(np.float64), Y.astype(np.float64)
+    valid = rows[:6]
+    N, C, _ = oracle.build_model(X64, Y64, k, "matern", 1.5, rho, noise, rows=valid)
+    ref = oracle.means(X64, X64[valid], N, C, "matern", 1.5, rho)
+    assert rel_err(out[:6], ref) <= TOL_MEAN[prec]
+    assert np.all(np.isnan(out[6:]))
