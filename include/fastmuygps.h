@@ -174,6 +174,22 @@ fmg_status fastmuygps_predict_muygps(const fmg_model *model, const void *Z, int6
 fmg_status fastmuygps_loo_predict(const fmg_model *model, const int32_t *rows, int64_t b,
                                   void *out, void *stream);
 
+/* Loss of MuyGPs hyperparameter training (Algorithm 1; Section 2.1, loss
+ * Q(theta)): the mean over a batch B of training rows, and over the ell
+ * responses, of (Y(x_i) - Yhat_theta(x_i | X_N(i)))^2, where the
+ * leave-one-out prediction uses the model's neighbour lists (they do not
+ * depend on theta: the kernels are isotropic) and coefficient rows solved
+ * again under `hyper`, in the model's precision.  An optimiser over theta
+ * (e.g. L-BFGS-B on the host) calls this once per candidate theta.
+ *   rows : device pointer [b] int32, b >= 1, training-point indices.
+ *   loss : host pointer, receives Q(theta); NaN when a batch row's
+ *          neighbourhood matrix is not positive definite under theta.
+ * Synchronises `stream`.  Errors: FMG_E_INVALID_ARG (null pointers, b < 1,
+ * a row outside [0, n), invalid hyperparameters, a self-inclusive model),
+ * FMG_E_BUSY, FMG_E_OOM, FMG_E_DEVICE. */
+fmg_status fastmuygps_loo_loss(const fmg_model *model, const int32_t *rows, int64_t b,
+                               const fmg_hyper *hyper, double *loss, void *stream);
+
 /* Model metadata (host struct).  Synchronises the device. */
 fmg_status fastmuygps_info(const fmg_model *model, fmg_info *info);
 

@@ -43,6 +43,7 @@ FLAG_TIMING = 0x8
 EXPORTS = ("fastmuygps_build", "fastmuygps_predict", "fastmuygps_info", "fastmuygps_neighbors",
            "fastmuygps_coeffs", "fastmuygps_timings", "fastmuygps_free", "fastmuygps_last_error",
            "fastmuygps_version", "fastmuygps_predict_muygps", "fastmuygps_loo_predict",
+           "fastmuygps_loo_loss",
            "fastmuygps_server_create", "fastmuygps_server_add_model",
            "fastmuygps_server_remove_model", "fastmuygps_server_submit", "fastmuygps_server_wait",
            "fastmuygps_server_stats", "fastmuygps_server_reset_stats",
@@ -107,6 +108,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fastmuygps_predict_muygps.restype = ctypes.c_int
     lib.fastmuygps_loo_predict.argtypes = [P, P, ctypes.c_int64, P, P]
     lib.fastmuygps_loo_predict.restype = ctypes.c_int
+    lib.fastmuygps_loo_loss.argtypes = [P, P, ctypes.c_int64, ctypes.POINTER(FmgHyper),
+                                        ctypes.POINTER(ctypes.c_double), P]
+    lib.fastmuygps_loo_loss.restype = ctypes.c_int
     lib.fastmuygps_info.argtypes = [P, ctypes.POINTER(FmgInfo)]
     lib.fastmuygps_info.restype = ctypes.c_int
     lib.fastmuygps_neighbors.argtypes = [P, P, P]
@@ -242,6 +246,23 @@ class Model:
                                            _dev_ptr(out, self.dtype, "out"),
                                            _stream_handle(stream)))
         return out
+
+    def loo_loss(self, rows: torch.Tensor, kernel: str = "matern", nu: float = 1.5,
+                 length_scale: float = 1.0, noise_var: float = 0.0, amplitude: float = 1.0,
+                 stream=None) -> float:
+        """fastmuygps_loo_loss: MuyGPs loss Q(theta) over the training rows `rows`
+        with the hyperparameters given here (Algorithm 1)."""
+        if rows.dim() != 1:
+            raise ValueError("rows must be a 1-D int32 tensor")
+        if kernel not in ("rbf", "matern"):
+            raise ValueError("kernel must be 'rbf' or 'matern'")
+        hyper = FmgHyper(KERNEL_RBF if kernel == "rbf" else KERNEL_MATERN, float(nu),
+                         float(length_scale), float(noise_var), float(amplitude))
+        val = ctypes.c_double()
+        _check(lib().fastmuygps_loo_loss(self.handle, _dev_ptr(rows, torch.int32, "rows"),
+                                        rows.shape[0], ctypes.byref(hyper), ctypes.byref(val),
+                                        _stream_handle(stream)))
+        return val.value
 
     def info(self) -> dict:
         inf = FmgInfo()

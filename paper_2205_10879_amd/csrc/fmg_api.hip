@@ -907,6 +907,92 @@ fmg_status fastmuygps_loo_predict(const fmg_model *model, const int32_t *rows, i
     return FMG_OK;
 }
 
+fmg_status fastmuygps_loo_loss(const fmg_model *model, const int32_t *rows, int64_t b,
+                               const fmg_hyper *hyper, double *loss, void *stream) {
+    g_err.clear();
+    if (!model || !rows || !hyper || !loss) return fail(FMG_E_INVALID_ARG, "null argument");
+    if (b < 1 || b > 2147483647LL) return fail(FMG_E_INVALID_ARG, "b = %lld out of range", (long long)b);
+    fmg_model *M = const_cast<fmg_model *>(model);
+    if (M->self_inc)
+        return fail(FMG_E_INVALID_ARG, "the loss needs leave-one-out neighbourhoods (the model "
+                                       "was built self-inclusive)");
+    if (!(hyper->length_scale > 0.0) || !std::isfinite(hyper->length_scale))
+        return fail(FMG_E_INVALID_ARG, "length_scale must be positive and finite");
+    if (!(hyper->noise_var >= 0.0) || !std::isfinite(hyper->noise_var))
+        return fail(FMG_E_INVALID_ARG, "noise_var must be >= 0 and finite");
+    const int kc = kernel_code(*hyper);
+    if (kc < 0) return fail(FMG_E_INVALID_ARG, "kernel must be RBF or Matern with nu in {0.5, 1.5, 2.5}");
+    if (!M->resident) return fail(FMG_E_BUSY, "the model is offloaded to host memory");
+    hipStream_t s = (hipStream_t)stream;
+    const bool f64 = M->prec == FMG_PREC_FP64;
+    const size_t esz = f64 ? 8 : 4;
+    const int d = M->d, k = M->k, ell = M->ell;
+    const double amp = hyper->amplitude > 0.0 ? hyper->amplitude : 1.0;
+    Scratch tmp;
+    tmp.stream = s;
+    tmp.async = true;
+    void *Xb = nullptr, *Yb = nullptr, *Cb = nullptr, *mu = nullptr;
+    int32_t *Nb = nullptr, *st = nullptr;
+    int *bad = nullptr;
+    double *part = nullptr, *sum = nullptr;
+    HIPCHK(tmp.alloc(&Xb, (size_t)b * d * esz), "scratch");
+    HIPCHK(tmp.alloc(&Yb, (size_t)b * ell * esz), "scratch");
+    HIPCHK(tmp.alloc(&Cb, (size_t)b * k * ell * esz), "scratch");
+    HIPCHK(tmp.alloc(&mu, (size_t)b * ell * esz), "scratch");
+    HIPCHK(tmp.alloc((void **)&Nb, (size_t)b * k * 4), "scratch");
+    HIPCHK(tmp.alloc((void **)&st, (size_t)b * 4), "scratch");
+    HIPCHK(tmp.alloc((void **)&bad, 4), "scratch");
+    HIPCHK(tmp.alloc((void **)&part, (size_t)sq_err_blocks(b * ell) * 8), "scratch");
+    HIPCHK(tmp.alloc((void **)&sum, 8), "scratch");
+    HIPCHK(launch_zero_u32(bad, 1, s), "zero");
+    HIPCHK(launch_batch_rows(f64, M->X, M->N, M->Y, rows, b, M->n, d, k, ell, Xb, Nb, Yb, bad, s),
+           "batch rows");
+    // C_i(theta) for the batch rows, over their (theta-independent) lists.
+    PrecomputeArgs pa{};
+    pa.X = M->X;
+    pa.Y = M->Y;
+    pa.n = b;
+    pa.d = d;
+    pa.ell = ell;
+    pa.k = k;
+    pa.N = Nb;
+    pa.C = Cb;
+    pa.status = st;
+    pa.kc = kc;
+    pa.inv_rho = 1.0 / hyper->length_scale;
+    pa.amp = amp;
+    pa.noise = hyper->noise_var;
+    pa.Ctr = f64 ? nullptr : Xb;
+    const bool refine = M->prec == FMG_PREC_MIXED && !(M->flags & FMG_FLAG_NO_REFINE);
+    HIPCHK(launch_precompute(f64, refine, pa, s), "precompute");
+    // Leave-one-out predictions K_theta(x_i, X_N(i)) . C_i(theta).
+    GatherArgs ga{};
+    ga.X = M->X;
+    ga.Z = Xb;
+    ga.N = Nb;
+    ga.C = Cb;
+    ga.m = b;
+    ga.zrows = b;
+    ga.crows = b;
+    ga.d = d;
+    ga.ell = ell;
+    ga.k = k;
+    ga.kc = kc;
+    ga.inv_rho = pa.inv_rho;
+    ga.amp = amp;
+    ga.out = mu;
+    HIPCHK(launch_gather(f64, ga, s), "gather");
+    HIPCHK(launch_sq_err(f64, Yb, mu, b * (int64_t)ell, part, sum, s), "squared errors");
+    double hsum = 0.0;
+    int hbad = 0;
+    HIPCHK(hipMemcpyAsync(&hsum, sum, 8, hipMemcpyDeviceToHost, s), "copy loss");
+    HIPCHK(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s), "copy flag");
+    HIPCHK(hipStreamSynchronize(s), "sync");
+    if (hbad) return fail(FMG_E_INVALID_ARG, "a row index is outside [0, n)");
+    *loss = hsum / ((double)b * ell);
+    return FMG_OK;
+}
+
 fmg_status fastmuygps_info(const fmg_model *model, fmg_info *info) {
     g_err.clear();
     if (!model || !info) return fail(FMG_E_INVALID_ARG, "null argument");

@@ -132,6 +132,17 @@ hipError_t launch_count_nonzero(const int32_t *a, int64_t n, unsigned long long 
 hipError_t launch_self_rows(int32_t *N, int64_t n, hipStream_t s);
 // Zero `count` 32-bit words with a kernel (safe inside captured graphs).
 hipError_t launch_zero_u32(void *ptr, int64_t count, hipStream_t s);
+// Leave-one-out loss helpers (fmg_loss.hip): gather X, N and Y rows of a
+// batch of training points (*bad set for an index outside [0, n)), and the
+// deterministic sum of squared differences of `count` values (part holds
+// sq_err_blocks(count) doubles).
+hipError_t launch_batch_rows(bool f64, const void *X, const int32_t *N, const void *Y,
+                             const int32_t *rows, int64_t b, int64_t n, int d, int k, int ell,
+                             void *Xb, int32_t *Nb, void *Yb, int *bad, hipStream_t s);
+int sq_err_blocks(int64_t count);
+hipError_t launch_sq_err(bool f64, const void *Y, const void *mu, int64_t count, double *part,
+                         double *out, hipStream_t s);
+
 // *dst += *src
 hipError_t launch_accum(const int32_t *src, unsigned long long *dst, hipStream_t s);
 

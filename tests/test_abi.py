@@ -115,3 +115,16 @@ def test_muygps_and_loo_calls_reject_bad_arguments(lib):
     assert lib.fastmuygps_loo_predict(None, fake, 5, fake, None) == fmg.FMG_E_INVALID_ARG
     assert lib.fastmuygps_loo_predict(fake, None, 5, fake, None) == fmg.FMG_E_INVALID_ARG
     assert lib.fastmuygps_loo_predict(fake, fake, -2, fake, None) == fmg.FMG_E_INVALID_ARG
+
+
+def test_loo_loss_rejects_bad_arguments(lib):
+    import paper_2205_10879_amd as fmg
+    fake = ctypes.c_void_p(16)  # never dereferenced: arguments are checked first
+    hy = fmg.FmgHyper(fmg.KERNEL_MATERN, 1.5, 1.0, 0.1, 1.0)
+    out = ctypes.c_double()
+    assert lib.fastmuygps_loo_loss(None, fake, 4, ctypes.byref(hy), ctypes.byref(out),
+                                   None) == fmg.FMG_E_INVALID_ARG
+    assert lib.fastmuygps_loo_loss(fake, fake, 0, ctypes.byref(hy), ctypes.byref(out),
+                                   None) == fmg.FMG_E_INVALID_ARG
+    assert lib.fastmuygps_loo_loss(fake, fake, 4, None, ctypes.byref(out),
+                                   None) == fmg.FMG_E_INVALID_ARG

@@ -94,3 +94,33 @@ def test_loo_predict_matches_oracle(prec):
     ref = oracle.means(X64, X64[valid], N, C, "matern", 1.5, rho)
     assert rel_err(out[:6], ref) <= TOL_MEAN[prec]
     assert np.all(np.isnan(out[6:]))
+
+
+def oracle_loo_loss(X64, Y64, rows, k, kernel, nu, rho, noise):
+    """Q(theta) of Algorithm 1 from the oracle: coefficient rows of the batch
+    under theta, their leave-one-out predictions, the mean squared error."""
+    N, C, _ = oracle.build_model(X64, Y64, k, kernel, nu, rho, noise, rows=rows)
+    mu = oracle.means(X64, X64[rows], N, C, kernel, nu, rho)
+    return float(np.mean((Y64[rows] - mu) ** 2))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+def test_loo_loss_matches_oracle_and_finds_the_same_length_scale(prec):
+    n, k, noise = 3000, 24, 1e-2
+    X, Y, _ = synth.small(n, 1, 3, ell=2, seed=71)
+    Y = np.sin(3.0 * X[:, :1]) * np.cos(2.0 * X[:, 1:2]) + 0.05 * Y  # smooth signal + noise
+    model, X, Y = build(prec, X, Y, k, "matern", 1.5, 1.0, noise)
+    X64, Y64 = X.astype(np.float64), Y.astype(np.float64)
+    rows = np.random.default_rng(5).choice(n, 256, replace=False).astype(np.int32)
+    rows_d = torch.from_numpy(rows).cuda()
+    grid = [0.25, 0.5, 1.0, 2.0]
+    got = [model.loo_loss(rows_d, "matern", 1.5, r, noise) for r in grid]
+    ref = [oracle_loo_loss(X64, Y64, rows, k, "matern", 1.5, r, noise) for r in grid]
+    tol = 1e-9 if prec == "fp64" else 2e-3
+    for g, r in zip(got, ref):
+        assert abs(g - r) <= tol * r
+    assert int(np.argmin(got)) == int(np.argmin(ref))
+    with pytest.raises(fmg().FmgError):
+        model.loo_loss(torch.tensor([0, n], dtype=torch.int32, device="cuda"), "matern", 1.5,
+                       1.0, noise)
+    model.free()
