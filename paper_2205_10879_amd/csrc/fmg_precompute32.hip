@@ -185,7 +185,9 @@ __device__ __forceinline__ double phi_eval64(const PhiForm<double> &f, double D)
 
 // Solves with U (unit lower, strictly lower part packed by rows in LDS, row
 // a at a(a-1)/2).  Lane a holds row a of the ELLMAX right-hand sides; the
-// value final at step j is read from lane j with v_readlane.
+// value final at step j is read from lane j with v_readlane.  Columns past
+// ell hold zeros and stay zero, so every loop over them has a fixed trip
+// count and unrolls (no dynamic register indexing).
 template <int ELLMAX>
 __device__ __forceinline__ void solve_unit_forward(const float *__restrict__ U, int k, int ell,
                                                    int a, float (&y)[ELLMAX]) {
@@ -193,10 +195,7 @@ __device__ __forceinline__ void solve_unit_forward(const float *__restrict__ U, 
     for (int j = 0; j < k - 1; ++j) {
         const float u = (a > j && a < k) ? U[arow + j] : 0.0f;
 #pragma unroll
-        for (int c = 0; c < ELLMAX; ++c) {
-            if (c >= ell) break;
-            y[c] = fmaf(-u, readlane_f32(y[c], j), y[c]);
-        }
+        for (int c = 0; c < ELLMAX; ++c) y[c] = fmaf(-u, readlane_f32(y[c], j), y[c]);
     }
 }
 
@@ -206,10 +205,7 @@ __device__ __forceinline__ void solve_unit_backward(const float *__restrict__ U,
     for (int j = k - 1; j > 0; --j) {
         const float u = (a < j) ? U[j * (j - 1) / 2 + a] : 0.0f;
 #pragma unroll
-        for (int c = 0; c < ELLMAX; ++c) {
-            if (c >= ell) break;
-            y[c] = fmaf(-u, readlane_f32(y[c], j), y[c]);
-        }
+        for (int c = 0; c < ELLMAX; ++c) y[c] = fmaf(-u, readlane_f32(y[c], j), y[c]);
     }
 }
 
@@ -231,10 +227,7 @@ __device__ __forceinline__ void chol_steps(float (&K)[KMAX], float (&y)[ELLMAX],
         if (a == j) dinv = rp;
         if (below) U[arow + j] = u;
 #pragma unroll
-        for (int c = 0; c < ELLMAX; ++c) {
-            if (c >= ell) break;
-            y[c] = fmaf(-u, readlane_f32(y[c], j), y[c]);
-        }
+        for (int c = 0; c < ELLMAX; ++c) y[c] = fmaf(-u, readlane_f32(y[c], j), y[c]);
         // Entry b of the broadcast is column j of the trailing matrix at row
         // j + 1 + b; the positions past the last row are zero.
         bc[(a - j - 1) & 63] = (a > j) ? K[0] : 0.0f;
@@ -467,11 +460,18 @@ hipError_t launch_pc32(const PrecomputeArgs &a, hipStream_t s) {
 template <bool REFINE>
 hipError_t launch_pc32_k(const PrecomputeArgs &a, hipStream_t s) {
     if (a.ell > 16 || a.d > 64) return hipErrorInvalidValue;
+    // Right-hand-side columns are processed up to ELLMAX (zeros past ell).
     if (a.k <= 32) {
         if (a.ell <= 1) return launch_pc32<32, 1, REFINE>(a, s);
+        if (a.ell <= 4) return launch_pc32<32, 4, REFINE>(a, s);
+        if (a.ell <= 8) return launch_pc32<32, 8, REFINE>(a, s);
+        if (a.ell <= 12) return launch_pc32<32, 12, REFINE>(a, s);
         return launch_pc32<32, 16, REFINE>(a, s);
     }
     if (a.ell <= 1) return launch_pc32<64, 1, REFINE>(a, s);
+    if (a.ell <= 4) return launch_pc32<64, 4, REFINE>(a, s);
+    if (a.ell <= 8) return launch_pc32<64, 8, REFINE>(a, s);
+    if (a.ell <= 12) return launch_pc32<64, 12, REFINE>(a, s);
     return launch_pc32<64, 16, REFINE>(a, s);
 }
 

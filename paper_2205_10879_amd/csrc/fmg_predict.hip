@@ -80,11 +80,12 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
         const T D = row_sqdist<T, VEC>(Z + zr * a.d, X + p * a.d, a.d);
         w = phi_t<T>(D, a.kc, (T)a.inv_rho, (T)a.amp);
     }
+    // Fixed trip count (columns past ell are zero and not stored), so the loop
+    // unrolls and cv stays in registers.
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
-        if (c >= ell) break;
         const T r = dpp_t_sum_last<T>(w * cv[c], lane);
-        if (lane == 63) out[c] = r;
+        if (lane == 63 && c < ell) out[c] = r;
     }
 }
 
