@@ -51,7 +51,7 @@ __device__ __forceinline__ T row_sqdist(const T *__restrict__ z, const T *__rest
     return (s0 + s1) + (s2 + s3);
 }
 
-template <typename T, bool VEC>
+template <typename T, bool VEC, int ELLMAX>
 __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
     const int lane = lane_id();
     const int64_t q = (int64_t)blockIdx.x * G_WAVES + (threadIdx.x >> 6);
@@ -70,10 +70,10 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
     // Row s of C[j]: ell contiguous values; the wave's rows form one
     // contiguous block of k * ell values.  Its loads only need j, so they
     // are issued before the neighbour rows.
-    T cv[16];
+    T cv[ELLMAX];
     const T *__restrict__ Cj = C + (j * a.k + lane) * ell;
 #pragma unroll
-    for (int c = 0; c < 16; ++c) cv[c] = (lane < a.k && c < ell) ? Cj[c] : T(0);
+    for (int c = 0; c < ELLMAX; ++c) cv[c] = (lane < a.k && c < ell) ? Cj[c] : T(0);
     T w = T(0);
     if (lane < a.k) {
         const int64_t p = a.N[j * a.k + lane];
@@ -83,10 +83,25 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
     // Fixed trip count (columns past ell are zero and not stored), so the loop
     // unrolls and cv stays in registers.
 #pragma unroll
-    for (int c = 0; c < 16; ++c) {
+    for (int c = 0; c < ELLMAX; ++c) {
         const T r = dpp_t_sum_last<T>(w * cv[c], lane);
         if (lane == 63 && c < ell) out[c] = r;
     }
+}
+
+// Response columns are reduced up to ELLMAX (zeros past ell are not stored).
+template <typename T, bool VEC>
+void launch_gather_t(const GatherArgs &a, unsigned blocks, hipStream_t s) {
+    if (a.ell <= 1)
+        hipLaunchKernelGGL((gather_kernel<T, VEC, 1>), dim3(blocks), dim3(256), 0, s, a);
+    else if (a.ell <= 4)
+        hipLaunchKernelGGL((gather_kernel<T, VEC, 4>), dim3(blocks), dim3(256), 0, s, a);
+    else if (a.ell <= 8)
+        hipLaunchKernelGGL((gather_kernel<T, VEC, 8>), dim3(blocks), dim3(256), 0, s, a);
+    else if (a.ell <= 12)
+        hipLaunchKernelGGL((gather_kernel<T, VEC, 12>), dim3(blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((gather_kernel<T, VEC, 16>), dim3(blocks), dim3(256), 0, s, a);
 }
 
 }  // namespace
@@ -98,16 +113,13 @@ hipError_t launch_gather(bool f64, const GatherArgs &a, hipStream_t s) {
     // (double) and both arrays start on a 16-byte boundary.
     if (a.ell > 16) return hipErrorInvalidValue;
     const bool base16 = (((uintptr_t)a.X | (uintptr_t)a.Z) & 15) == 0;
+    const bool vec = f64 ? (a.d % 2 == 0 && base16) : (a.d % 4 == 0 && base16);
     if (f64) {
-        if (a.d % 2 == 0 && base16)
-            hipLaunchKernelGGL((gather_kernel<double, true>), dim3(blocks), dim3(256), 0, s, a);
-        else
-            hipLaunchKernelGGL((gather_kernel<double, false>), dim3(blocks), dim3(256), 0, s, a);
+        if (vec) launch_gather_t<double, true>(a, blocks, s);
+        else launch_gather_t<double, false>(a, blocks, s);
     } else {
-        if (a.d % 4 == 0 && base16)
-            hipLaunchKernelGGL((gather_kernel<float, true>), dim3(blocks), dim3(256), 0, s, a);
-        else
-            hipLaunchKernelGGL((gather_kernel<float, false>), dim3(blocks), dim3(256), 0, s, a);
+        if (vec) launch_gather_t<float, true>(a, blocks, s);
+        else launch_gather_t<float, false>(a, blocks, s);
     }
     return hipGetLastError();
 }
