@@ -77,6 +77,11 @@ def _load():
         lib.oracle_muygps_batch.argtypes = [P, P, i64, i32, i32, i32, i32, dbl, dbl, dbl, dbl,
                                              P, i64, P, P, P, i32]
         lib.oracle_muygps_batch.restype = None
+        lib.oracle_dphi_drho.argtypes = [dbl, i32, dbl, dbl, dbl]
+        lib.oracle_dphi_drho.restype = dbl
+        lib.oracle_loo_loss_grad.argtypes = [P, P, i64, i32, i32, i32, i32, dbl, dbl, dbl, dbl,
+                                             P, i64, P, P, i32]
+        lib.oracle_loo_loss_grad.restype = i64
         lib.oracle_max_threads.argtypes = []
         lib.oracle_max_threads.restype = i32
         _lib = lib
@@ -119,6 +124,21 @@ def phi(D, kernel="matern", nu=1.5, rho=1.0, amp=1.0):
     flat_out = out.reshape(-1)
     for e in range(flat_in.size):
         flat_out[e] = lib.oracle_phi(float(flat_in[e]), kc, float(nu), float(rho), float(amp))
+    return out
+
+
+def dphi_drho(D, kernel="matern", nu=1.5, rho=1.0, amp=1.0):
+    """Derivative of the kernel values with respect to the length scale, from
+    squared distances D (any shape)."""
+    lib = _load()
+    D = np.asarray(D, dtype=np.float64)
+    out = np.empty_like(D)
+    kc = _kernel_code(kernel)
+    flat_in = D.reshape(-1)
+    flat_out = out.reshape(-1)
+    for e in range(flat_in.size):
+        flat_out[e] = lib.oracle_dphi_drho(float(flat_in[e]), kc, float(nu), float(rho),
+                                           float(amp))
     return out
 
 
@@ -266,3 +286,27 @@ def muygps_predict(X, Y, Z, k: int, kernel="matern", nu=1.5, rho=1.0, noise=0.0,
                                 float(nu), float(rho), float(noise), float(amp), _ptr(Z), m,
                                 _ptr(nb), _ptr(out), _ptr(st), int(nthreads))
     return out, nb, st
+
+
+def loo_loss_grad(X, Y, rows, k: int, kernel="matern", nu=1.5, rho=1.0, noise=0.0, amp=1.0,
+                  nthreads: int = 0):
+    """Leave-one-out loss Q(theta) of MuyGPs training over the batch `rows`
+    (Algorithm 1; Section 2.1) and its gradient with respect to
+    (length scale, noise variance).  Returns (Q, grad [2], terms [b, 3],
+    status [b]); terms are the unnormalised per-row (loss, d/drho, d/dsigma^2),
+    Q and grad their sums over b * ell."""
+    X = _f64(X)
+    Y = _f64(Y)
+    if Y.ndim == 1:
+        Y = Y[:, None]
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    n, d = X.shape
+    ell = Y.shape[1]
+    b = rows.shape[0]
+    terms = np.empty((b, 3))
+    st = np.empty(b, dtype=np.int32)
+    _load().oracle_loo_loss_grad(_ptr(X), _ptr(Y), n, d, ell, int(k), _kernel_code(kernel),
+                                 float(nu), float(rho), float(noise), float(amp), _ptr(rows), b,
+                                 _ptr(terms), _ptr(st), int(nthreads))
+    tot = terms.sum(axis=0) / (b * ell)
+    return float(tot[0]), tot[1:].copy(), terms, st

@@ -389,6 +389,144 @@ void oracle_muygps_batch(const double *X, const double *Y, int64_t n, int d, int
                                            Z + t * d, nb_out + t * k, out + t * ell);
 }
 
+/* Derivative of the kernel value with respect to the length scale rho,
+ * from the squared distance D (Section 2, Matern equation, half-integer
+ * closed forms; RBF limit).  With s the scaled distance of oracle_phi:
+ *   nu = 1/2 : dphi/drho = a s exp(-s) / rho            (s = r / rho)
+ *   nu = 3/2 : dphi/drho = a s^2 exp(-s) / rho          (s = sqrt(3) r / rho)
+ *   nu = 5/2 : dphi/drho = a s^2 (1 + s) exp(-s) / (3 rho)  (s = sqrt(5) r / rho)
+ *   RBF      : dphi/drho = a exp(-D / (2 rho^2)) D / rho^3
+ * (each is d/ds of the closed form times ds/drho = -s / rho).  NaN for an
+ * unsupported nu. */
+double oracle_dphi_drho(double D, int kernel, double nu, double rho, double amp)
+{
+    if (kernel == ORACLE_RBF)
+        return amp * exp(-D / (2.0 * rho * rho)) * D / (rho * rho * rho);
+    double r = sqrt(D);
+    if (nu == 0.5) {
+        double s = r / rho;
+        return amp * s * exp(-s) / rho;
+    }
+    if (nu == 1.5) {
+        double s = sqrt(3.0) * r / rho;
+        return amp * s * s * exp(-s) / rho;
+    }
+    if (nu == 2.5) {
+        double s = sqrt(5.0) * r / rho;
+        return amp * s * s * (1.0 + s) * exp(-s) / (3.0 * rho);
+    }
+    return NAN;
+}
+
+/* Leave-one-out loss of MuyGPs hyperparameter training and its gradient
+ * (Algorithm 1; Section 2.1, leave-one-out prediction and loss Q(theta)).
+ * For batch row t (training point i = rows[t], leave-one-out neighbourhood
+ * N(i) of the k nearest other points):
+ *   K      = K(X_N, X_N) + sigma^2 I,   kz = K(x_i, X_N)  (no nugget),
+ *   mu_c   = kz K^{-1} Y_N[:, c],       e_c = mu_c - y_{i,c},
+ *   loss_t = sum_c e_c^2,
+ * and, for theta in {rho, sigma^2}, with dK^{-1} = -K^{-1} dK K^{-1},
+ *   dmu_c  = dkz K^{-1} Y_N[:, c] - kz K^{-1} dK K^{-1} Y_N[:, c],
+ *   g_t    = sum_c 2 e_c dmu_c,
+ * where dK/drho holds dphi/drho off the diagonal (the diagonal a + sigma^2
+ * does not depend on rho), dK/dsigma^2 = I, dkz/drho = dphi/drho and
+ * dkz/dsigma^2 = 0.  Writes terms [nrows, 3] = (loss_t, g_rho, g_sigma2),
+ * unnormalised (Q = sum loss_t / (nrows ell), likewise its gradient), and
+ * status [nrows] (0 ok, 1 not positive definite: terms NaN, 2 too few
+ * points).  Returns the number of rows with a non-zero status. */
+int64_t oracle_loo_loss_grad(const double *X, const double *Y, int64_t n, int d, int ell, int k,
+                             int kernel, double nu, double rho, double noise, double amp,
+                             const int64_t *rows, int64_t nrows, double *terms,
+                             int32_t *status_out, int nthreads)
+{
+    int64_t bad = 0;
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 8) reduction(+ : bad)
+#endif
+    for (int64_t t = 0; t < nrows; ++t) {
+        int64_t i = rows[t];
+        int32_t *nb = (int32_t *)malloc(sizeof(int32_t) * k);
+        double *K = (double *)malloc(sizeof(double) * k * k);
+        double *dK = (double *)malloc(sizeof(double) * k * k);
+        double *kz = (double *)malloc(sizeof(double) * k);
+        double *dkz = (double *)malloc(sizeof(double) * k);
+        double *yN = (double *)malloc(sizeof(double) * k);
+        double *alpha = (double *)malloc(sizeof(double) * k);
+        double *w = (double *)malloc(sizeof(double) * k);
+        double *u = (double *)malloc(sizeof(double) * k);
+        int st = 0;
+        double loss = 0.0, g_rho = 0.0, g_s2 = 0.0;
+        if (oracle_neighborhood(X, n, d, i, k, ORACLE_MODE_LOO, nb) != 0) {
+            st = 2;
+        } else {
+            oracle_assemble(X, d, nb, k, kernel, nu, rho, noise, amp, K);
+            for (int a = 0; a < k; ++a) {
+                for (int b = 0; b < k; ++b) {
+                    double D = oracle_sqdist(X + (int64_t)nb[a] * d, X + (int64_t)nb[b] * d, d);
+                    dK[a * k + b] = (a == b) ? 0.0 : oracle_dphi_drho(D, kernel, nu, rho, amp);
+                }
+                double Dz = oracle_sqdist(X + i * d, X + (int64_t)nb[a] * d, d);
+                kz[a] = oracle_phi(Dz, kernel, nu, rho, amp);
+                dkz[a] = oracle_dphi_drho(Dz, kernel, nu, rho, amp);
+            }
+            if (oracle_cholesky(K, k) != 0) {
+                st = 1;
+            } else {
+                for (int c = 0; c < ell; ++c) {
+                    for (int a = 0; a < k; ++a)
+                        yN[a] = Y[(int64_t)nb[a] * ell + c];
+                    oracle_cholesky_solve(K, k, yN, alpha, 1);
+                    double mu = 0.0;
+                    for (int a = 0; a < k; ++a)
+                        mu = mu + kz[a] * alpha[a];
+                    double e = mu - Y[i * ell + c];
+                    loss = loss + e * e;
+                    /* rho: dkz alpha - kz K^{-1} (dK alpha) */
+                    for (int a = 0; a < k; ++a) {
+                        double s = 0.0;
+                        for (int b = 0; b < k; ++b)
+                            s = s + dK[a * k + b] * alpha[b];
+                        w[a] = s;
+                    }
+                    oracle_cholesky_solve(K, k, w, u, 1);
+                    double dmu = 0.0;
+                    for (int a = 0; a < k; ++a)
+                        dmu = dmu + dkz[a] * alpha[a] - kz[a] * u[a];
+                    g_rho = g_rho + 2.0 * e * dmu;
+                    /* sigma^2: dK = I, so dmu = -kz K^{-1} alpha */
+                    oracle_cholesky_solve(K, k, alpha, u, 1);
+                    double dmu_s = 0.0;
+                    for (int a = 0; a < k; ++a)
+                        dmu_s = dmu_s - kz[a] * u[a];
+                    g_s2 = g_s2 + 2.0 * e * dmu_s;
+                }
+            }
+        }
+        if (st != 0) {
+            loss = NAN;
+            g_rho = NAN;
+            g_s2 = NAN;
+            ++bad;
+        }
+        terms[t * 3 + 0] = loss;
+        terms[t * 3 + 1] = g_rho;
+        terms[t * 3 + 2] = g_s2;
+        status_out[t] = st;
+        free(nb);
+        free(K);
+        free(dK);
+        free(kz);
+        free(dkz);
+        free(yN);
+        free(alpha);
+        free(w);
+        free(u);
+    }
+    return bad;
+}
+
 int oracle_max_threads(void)
 {
 #ifdef _OPENMP

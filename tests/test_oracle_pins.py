@@ -340,3 +340,85 @@ def test_muygps_k1_closed_form():
         assert nb[t, 0] == p
         ref = math.exp(-np_sqdist(X[p:p + 1], Z[t])[0] / (2 * rho * rho)) * Y[p, 0] / (1 + noise)
         assert abs(mu[t, 0] - ref) <= 4e-16 * max(abs(ref), 1e-300) + 1e-300
+
+
+# --- Leave-one-out loss Q(theta) and its gradient (Algorithm 1) -----------------------
+
+KERNELS4 = [("matern", 0.5), ("matern", 1.5), ("matern", 2.5), ("rbf", 0.0)]
+
+
+@pytest.mark.parametrize("kernel,nu", KERNELS4)
+def test_dphi_drho_matches_finite_differences(kernel, nu):
+    # central differences of the (Bessel- and sklearn-pinned) kernel value in rho
+    D = np.array([0.0, 1e-6, 0.01, 0.3, 1.0, 2.5, 9.0, 40.0])
+    for rho in (0.3, 1.0, 2.7):
+        h = 1e-5 * rho
+        fd = (oracle.phi(D, kernel, nu, rho + h) - oracle.phi(D, kernel, nu, rho - h)) / (2 * h)
+        got = oracle.dphi_drho(D, kernel, nu, rho)
+        assert np.all(np.abs(got - fd) <= 1e-8 * (np.abs(fd) + 1.0 / rho))
+    assert oracle.dphi_drho(np.array([0.0]), kernel, nu, 1.0)[0] == 0.0
+
+
+def composed_loo_loss(X, Y, rows, k, kernel, nu, rho, noise):
+    """Q(theta) composed from pinned parts: the coefficient rows of the batch
+    points and their means at z = x_i, which are MuyGPs' leave-one-out
+    predictions (pinned above by an independent dense solve)."""
+    N, C, _ = oracle.build_model(X, Y, k, kernel, nu, rho, noise, rows=rows)
+    mu = oracle.means(X, X[rows], N, C, kernel, nu, rho)
+    return float(np.mean((Y[rows] - mu) ** 2))
+
+
+@pytest.mark.parametrize("kernel,nu", KERNELS4)
+def test_loo_loss_is_the_composed_loss(kernel, nu):
+    X, Y, _ = synth.small(500, 1, 3, ell=2, seed=81)
+    rows = np.random.default_rng(1).choice(500, 60, replace=False)
+    q, _, terms, st = oracle.loo_loss_grad(X, Y, rows, 12, kernel, nu, 0.9, 1e-2)
+    ref = composed_loo_loss(X, Y, rows, 12, kernel, nu, 0.9, 1e-2)
+    assert np.all(st == 0)
+    assert abs(q - ref) <= 1e-12 * ref
+    assert terms.shape == (60, 3)
+
+
+@pytest.mark.parametrize("kernel,nu", KERNELS4)
+def test_loo_gradient_matches_finite_differences(kernel, nu):
+    X, Y, _ = synth.small(400, 1, 3, ell=2, seed=82)
+    Y = np.sin(2.0 * X[:, :2]) + 0.1 * Y  # smooth signal: an interior optimum in rho
+    rows = np.random.default_rng(2).choice(400, 50, replace=False)
+    k = 10
+    for rho, noise in ((0.7, 1e-2), (1.6, 0.2)):
+        q, g, _, _ = oracle.loo_loss_grad(X, Y, rows, k, kernel, nu, rho, noise)
+        hr, hn = 1e-5 * rho, 1e-5 * noise
+        fr = (composed_loo_loss(X, Y, rows, k, kernel, nu, rho + hr, noise)
+              - composed_loo_loss(X, Y, rows, k, kernel, nu, rho - hr, noise)) / (2 * hr)
+        fn = (composed_loo_loss(X, Y, rows, k, kernel, nu, rho, noise + hn)
+              - composed_loo_loss(X, Y, rows, k, kernel, nu, rho, noise - hn)) / (2 * hn)
+        assert abs(g[0] - fr) <= 1e-6 * abs(fr) + 1e-9 * q / rho
+        assert abs(g[1] - fn) <= 1e-6 * abs(fn) + 1e-9 * q / noise
+
+
+def test_loo_gradient_k1_closed_form():
+    # k = 1: mu_i = phi(r_ip) y_p / (a + sigma^2), p the nearest other point
+    X, Y, _ = synth.small(120, 1, 2, ell=1, seed=83)
+    rho, noise = 0.8, 0.3
+    rows = np.arange(0, 120, 3)
+    q, g, _, _ = oracle.loo_loss_grad(X, Y, rows, 1, "matern", 2.5, rho, noise)
+    sq, gr, gs = 0.0, 0.0, 0.0
+    for i in rows:
+        D = np_sqdist(X, X[i])
+        p = [j for j in lexsort_order(D) if j != i][0]
+        ph = oracle.phi(D[p], "matern", 2.5, rho)
+        dph = oracle.dphi_drho(D[p], "matern", 2.5, rho)
+        e = ph * Y[p, 0] / (1 + noise) - Y[i, 0]
+        sq += e * e
+        gr += 2 * e * dph * Y[p, 0] / (1 + noise)
+        gs += 2 * e * (-ph * Y[p, 0] / (1 + noise) ** 2)
+    b = len(rows)
+    assert abs(q - sq / b) <= 1e-13 * (sq / b)
+    assert abs(g[0] - gr / b) <= 1e-12 * abs(gr / b) + 1e-15
+    assert abs(g[1] - gs / b) <= 1e-12 * abs(gs / b) + 1e-15
+
+
+def test_loo_gradient_rows_without_enough_points_are_flagged():
+    X, Y, _ = synth.small(5, 1, 2, ell=1, seed=84)
+    _, _, terms, st = oracle.loo_loss_grad(X, Y, np.array([0, 1]), 5, "matern", 1.5, 1.0, 0.1)
+    assert st.tolist() == [2, 2] and np.all(np.isnan(terms))
