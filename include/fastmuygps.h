@@ -190,6 +190,28 @@ fmg_status fastmuygps_loo_predict(const fmg_model *model, const int32_t *rows, i
 fmg_status fastmuygps_loo_loss(const fmg_model *model, const int32_t *rows, int64_t b,
                                const fmg_hyper *hyper, double *loss, void *stream);
 
+/* Loss of MuyGPs hyperparameter training and its gradient (Algorithm 1;
+ * Section 2.1, loss Q(theta)), for a gradient-based optimiser over theta
+ * (e.g. L-BFGS-B on the host).  Q is the mean over the batch rows and the
+ * ell responses of the squared leave-one-out error, with the model's
+ * neighbour lists (independent of theta) and the local systems solved again
+ * under `hyper`; the gradient is exact (differentiated through the solve,
+ * dK^{-1} = -K^{-1} dK K^{-1}).  Everything runs in FP64 whatever the model
+ * precision (FP32 inputs widened exactly), so for FP32 and MIXED models the
+ * loss can differ from fastmuygps_loo_loss by that path's rounding.
+ *   rows : device pointer [b] int32, b >= 1, training-point indices.
+ *   loss : host pointer, receives Q(theta).
+ *   grad : host pointer [2], receives dQ/d length_scale and dQ/d noise_var
+ *          (amplitude and kernel are held fixed).
+ * Loss and gradient are NaN when a batch row's matrix is not positive
+ * definite under theta.  Synchronises `stream`.  Errors: FMG_E_INVALID_ARG
+ * (null pointers, b < 1, a row outside [0, n), invalid hyperparameters, a
+ * self-inclusive model), FMG_E_UNSUPPORTED ((k+1)(d+1) + k(k+1)/2 + 128
+ * doubles exceed 64 KB), FMG_E_BUSY, FMG_E_OOM, FMG_E_DEVICE. */
+fmg_status fastmuygps_loo_loss_grad(const fmg_model *model, const int32_t *rows, int64_t b,
+                                    const fmg_hyper *hyper, double *loss, double *grad,
+                                    void *stream);
+
 /* Model metadata (host struct).  Synchronises the device. */
 fmg_status fastmuygps_info(const fmg_model *model, fmg_info *info);
 

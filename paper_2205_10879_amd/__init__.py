@@ -43,7 +43,7 @@ FLAG_TIMING = 0x8
 EXPORTS = ("fastmuygps_build", "fastmuygps_predict", "fastmuygps_info", "fastmuygps_neighbors",
            "fastmuygps_coeffs", "fastmuygps_timings", "fastmuygps_free", "fastmuygps_last_error",
            "fastmuygps_version", "fastmuygps_predict_muygps", "fastmuygps_loo_predict",
-           "fastmuygps_loo_loss",
+           "fastmuygps_loo_loss", "fastmuygps_loo_loss_grad",
            "fastmuygps_server_create", "fastmuygps_server_add_model",
            "fastmuygps_server_remove_model", "fastmuygps_server_submit", "fastmuygps_server_wait",
            "fastmuygps_server_stats", "fastmuygps_server_reset_stats",
@@ -111,6 +111,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fastmuygps_loo_loss.argtypes = [P, P, ctypes.c_int64, ctypes.POINTER(FmgHyper),
                                         ctypes.POINTER(ctypes.c_double), P]
     lib.fastmuygps_loo_loss.restype = ctypes.c_int
+    lib.fastmuygps_loo_loss_grad.argtypes = [P, P, ctypes.c_int64, ctypes.POINTER(FmgHyper),
+                                             ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_double), P]
+    lib.fastmuygps_loo_loss_grad.restype = ctypes.c_int
     lib.fastmuygps_info.argtypes = [P, ctypes.POINTER(FmgInfo)]
     lib.fastmuygps_info.restype = ctypes.c_int
     lib.fastmuygps_neighbors.argtypes = [P, P, P]
@@ -263,6 +267,60 @@ class Model:
                                         rows.shape[0], ctypes.byref(hyper), ctypes.byref(val),
                                         _stream_handle(stream)))
         return val.value
+
+    def loo_loss_grad(self, rows: torch.Tensor, kernel: str = "matern", nu: float = 1.5,
+                      length_scale: float = 1.0, noise_var: float = 0.0,
+                      amplitude: float = 1.0, stream=None):
+        """fastmuygps_loo_loss_grad: Q(theta) over the training rows `rows` and its
+        gradient (dQ/d length_scale, dQ/d noise_var), in FP64 (Algorithm 1).
+        Returns (loss, numpy array [2])."""
+        if rows.dim() != 1:
+            raise ValueError("rows must be a 1-D int32 tensor")
+        if kernel not in ("rbf", "matern"):
+            raise ValueError("kernel must be 'rbf' or 'matern'")
+        hyper = FmgHyper(KERNEL_RBF if kernel == "rbf" else KERNEL_MATERN, float(nu),
+                         float(length_scale), float(noise_var), float(amplitude))
+        val = ctypes.c_double()
+        grad = (ctypes.c_double * 2)()
+        _check(lib().fastmuygps_loo_loss_grad(self.handle, _dev_ptr(rows, torch.int32, "rows"),
+                                             rows.shape[0], ctypes.byref(hyper),
+                                             ctypes.byref(val), grad, _stream_handle(stream)))
+        import numpy as np
+        return val.value, np.array([grad[0], grad[1]])
+
+    def fit_hyper(self, rows: torch.Tensor, kernel: str = "matern", nu: float = 1.5,
+                  length_scale: float = 1.0, noise_var: float = 1e-2,
+                  fit_noise: bool = True, length_scale_bounds=(1e-3, 1e3),
+                  noise_bounds=(1e-8, 10.0), maxiter: int = 100) -> dict:
+        """MuyGPs hyperparameter training (Algorithm 1): minimise Q(theta) over
+        the batch `rows` with L-BFGS-B on the host, in log(length_scale) and
+        log(noise_var), each step one fastmuygps_loo_loss_grad on the device.
+        Returns the fitted values, the final loss and gradient, and the
+        optimiser's counts.  The model's own coefficients are not changed."""
+        import numpy as np
+        from scipy.optimize import minimize
+
+        def objective(u):
+            rho = float(np.exp(u[0]))
+            s2 = float(np.exp(u[1])) if fit_noise else float(noise_var)
+            q, g = self.loo_loss_grad(rows, kernel, nu, rho, s2)
+            if not np.isfinite(q) or not np.all(np.isfinite(g)):
+                return 1e300, np.zeros_like(u)  # not positive definite here: back off
+            gu = [g[0] * rho] + ([g[1] * s2] if fit_noise else [])
+            return q, np.array(gu)
+
+        u0 = [np.log(length_scale)] + ([np.log(noise_var)] if fit_noise else [])
+        bounds = [tuple(np.log(length_scale_bounds))]
+        if fit_noise:
+            bounds.append(tuple(np.log(noise_bounds)))
+        res = minimize(objective, np.array(u0, dtype=np.float64), jac=True, method="L-BFGS-B",
+                       bounds=bounds, options={"maxiter": int(maxiter)})
+        rho = float(np.exp(res.x[0]))
+        s2 = float(np.exp(res.x[1])) if fit_noise else float(noise_var)
+        q, g = self.loo_loss_grad(rows, kernel, nu, rho, s2)
+        return {"length_scale": rho, "noise_var": s2, "loss": q, "grad": g,
+                "iterations": int(res.nit), "evaluations": int(res.nfev),
+                "success": bool(res.success), "message": str(res.message)}
 
     def info(self) -> dict:
         inf = FmgInfo()

@@ -993,6 +993,67 @@ fmg_status fastmuygps_loo_loss(const fmg_model *model, const int32_t *rows, int6
     return FMG_OK;
 }
 
+fmg_status fastmuygps_loo_loss_grad(const fmg_model *model, const int32_t *rows, int64_t b,
+                                    const fmg_hyper *hyper, double *loss, double *grad,
+                                    void *stream) {
+    g_err.clear();
+    if (!model || !rows || !hyper || !loss || !grad) return fail(FMG_E_INVALID_ARG, "null argument");
+    if (b < 1 || b > 2147483647LL) return fail(FMG_E_INVALID_ARG, "b = %lld out of range", (long long)b);
+    const fmg_model *M = model;
+    if (M->self_inc)
+        return fail(FMG_E_INVALID_ARG, "the loss needs leave-one-out neighbourhoods (the model "
+                                       "was built self-inclusive)");
+    if (!(hyper->length_scale > 0.0) || !std::isfinite(hyper->length_scale))
+        return fail(FMG_E_INVALID_ARG, "length_scale must be positive and finite");
+    if (!(hyper->noise_var >= 0.0) || !std::isfinite(hyper->noise_var))
+        return fail(FMG_E_INVALID_ARG, "noise_var must be >= 0 and finite");
+    const int kc = kernel_code(*hyper);
+    if (kc < 0) return fail(FMG_E_INVALID_ARG, "kernel must be RBF or Matern with nu in {0.5, 1.5, 2.5}");
+    if (loo_grad_lds_bytes(M->k, M->d) > 65536)
+        return fail(FMG_E_UNSUPPORTED, "k = %d, d = %d: the gradient's staged rows exceed 64 KB",
+                    M->k, M->d);
+    if (!M->resident) return fail(FMG_E_BUSY, "the model is offloaded to host memory");
+    hipStream_t s = (hipStream_t)stream;
+    Scratch tmp;
+    tmp.stream = s;
+    tmp.async = true;
+    double *terms = nullptr, *part = nullptr, *sums = nullptr;
+    int *bad = nullptr;
+    HIPCHK(tmp.alloc((void **)&terms, (size_t)b * 3 * 8), "scratch");
+    HIPCHK(tmp.alloc((void **)&part, (size_t)loo_grad_blocks(b) * 3 * 8), "scratch");
+    HIPCHK(tmp.alloc((void **)&sums, 3 * 8), "scratch");
+    HIPCHK(tmp.alloc((void **)&bad, 4), "scratch");
+    HIPCHK(launch_zero_u32(bad, 1, s), "zero");
+    GradArgs ga{};
+    ga.X = M->X;
+    ga.Y = M->Y;
+    ga.N = M->N;
+    ga.rows = rows;
+    ga.b = b;
+    ga.n = M->n;
+    ga.d = M->d;
+    ga.ell = M->ell;
+    ga.k = M->k;
+    ga.kc = kc;
+    ga.inv_rho = 1.0 / hyper->length_scale;
+    ga.amp = hyper->amplitude > 0.0 ? hyper->amplitude : 1.0;
+    ga.noise = hyper->noise_var;
+    ga.terms = terms;
+    ga.bad = bad;
+    HIPCHK(launch_loo_grad(M->prec == FMG_PREC_FP64, ga, part, sums, s), "loss gradient");
+    double h[3] = {0.0, 0.0, 0.0};
+    int hbad = 0;
+    HIPCHK(hipMemcpyAsync(h, sums, 3 * 8, hipMemcpyDeviceToHost, s), "copy sums");
+    HIPCHK(hipMemcpyAsync(&hbad, bad, 4, hipMemcpyDeviceToHost, s), "copy flag");
+    HIPCHK(hipStreamSynchronize(s), "sync");
+    if (hbad) return fail(FMG_E_INVALID_ARG, "a row index is outside [0, n)");
+    const double scale = 1.0 / ((double)b * M->ell);
+    *loss = h[0] * scale;
+    grad[0] = h[1] * scale;
+    grad[1] = h[2] * scale;
+    return FMG_OK;
+}
+
 fmg_status fastmuygps_info(const fmg_model *model, fmg_info *info) {
     g_err.clear();
     if (!model || !info) return fail(FMG_E_INVALID_ARG, "null argument");

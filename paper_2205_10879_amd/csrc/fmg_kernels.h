@@ -109,6 +109,19 @@ struct GatherArgs {
     void *out;
 };
 
+struct GradArgs {
+    const void *X;        // [n, d] training coordinates (float or double)
+    const void *Y;        // [n, ell] responses
+    const int32_t *N;     // [n, k] leave-one-out neighbour lists
+    const int32_t *rows;  // [b] batch training points
+    int64_t b, n;
+    int d, ell, k;
+    int kc;               // kernel code (fmg_device.h)
+    double inv_rho, amp, noise;
+    double *terms;        // [b, 3] per-point (sum_c e_c^2, d/drho, d/dsigma^2)
+    int *bad;             // set when a row index is outside [0, n)
+};
+
 // Column mean of X [n, d] into mu [d] (deterministic); part is scratch of
 // col_mean_blocks(n) * d doubles.
 int col_mean_blocks(int64_t n);
@@ -142,6 +155,15 @@ hipError_t launch_batch_rows(bool f64, const void *X, const int32_t *N, const vo
 int sq_err_blocks(int64_t count);
 hipError_t launch_sq_err(bool f64, const void *Y, const void *mu, int64_t count, double *part,
                          double *out, hipStream_t s);
+
+// Leave-one-out loss and its gradient in (rho, sigma^2), FP64 (fmg_grad.hip):
+// per-point terms, then their column sums into out[3]; part holds
+// loo_grad_blocks(b) * 3 doubles.  hipErrorInvalidValue when k > 64,
+// ell > 16 or the staged rows exceed 64 KB of LDS (loo_grad_lds_bytes).
+size_t loo_grad_lds_bytes(int k, int d);
+int loo_grad_blocks(int64_t b);
+hipError_t launch_loo_grad(bool f64, const GradArgs &a, double *part, double *out,
+                           hipStream_t s);
 
 // *dst += *src
 hipError_t launch_accum(const int32_t *src, unsigned long long *dst, hipStream_t s);

@@ -128,3 +128,18 @@ def test_loo_loss_rejects_bad_arguments(lib):
                                    None) == fmg.FMG_E_INVALID_ARG
     assert lib.fastmuygps_loo_loss(fake, fake, 4, None, ctypes.byref(out),
                                    None) == fmg.FMG_E_INVALID_ARG
+
+
+def test_loo_loss_grad_rejects_bad_arguments(lib):
+    import paper_2205_10879_amd as fmg
+    fake = ctypes.c_void_p(16)  # never dereferenced: arguments are checked first
+    hy = fmg.FmgHyper(fmg.KERNEL_MATERN, 1.5, 1.0, 0.1, 1.0)
+    out = ctypes.c_double()
+    grad = (ctypes.c_double * 2)()
+    f = lib.fastmuygps_loo_loss_grad
+    assert f(None, fake, 4, ctypes.byref(hy), ctypes.byref(out), grad, None) == fmg.FMG_E_INVALID_ARG
+    assert f(fake, None, 4, ctypes.byref(hy), ctypes.byref(out), grad, None) == fmg.FMG_E_INVALID_ARG
+    assert f(fake, fake, 0, ctypes.byref(hy), ctypes.byref(out), grad, None) == fmg.FMG_E_INVALID_ARG
+    assert f(fake, fake, 4, None, ctypes.byref(out), grad, None) == fmg.FMG_E_INVALID_ARG
+    assert f(fake, fake, 4, ctypes.byref(hy), None, grad, None) == fmg.FMG_E_INVALID_ARG
+    assert f(fake, fake, 4, ctypes.byref(hy), ctypes.byref(out), None, None) == fmg.FMG_E_INVALID_ARG
