@@ -113,7 +113,13 @@ typedef struct {
  *         SELF needs 1 <= k <= n).
  *   d   : 1 <= d <= 64 (FP32), 61 (MIXED), any (FP64).
  *   ell : responses per point, 1 <= ell <= 16.
- *   k   : neighbours, 1 <= k <= 64.
+ *   k   : neighbours, 1 <= k <= 256.  Up to 64 a wavefront owns one
+ *         neighbourhood (one neighbour per lane); wider neighbourhoods take an
+ *         exact FP64-distance search for every training point and one
+ *         workgroup per factorisation with the packed factor in LDS, so they
+ *         need FP64 or FP32 precision and
+ *         esz * (k (d+1) + k (k+1)/2 + 544) <= 160 KB (esz = 8 for FP64,
+ *         4 for FP32); otherwise FMG_E_UNSUPPORTED.
  * X and Y are only read during the call; the model keeps its own copies of
  * what prediction needs (X, Y, the neighbour lists N [n,k] and C [n,k,ell]).
  * The call returns when the model is complete (it synchronises `stream`).
@@ -145,7 +151,8 @@ fmg_status fastmuygps_predict(const fmg_model *model, const void *Z, int64_t m, 
  * precomputes.  For every query z:
  *   N*(z) = the k nearest training points of z (exact, ties to the smaller
  *           index; the screen, re-rank and certificate of the build, with
- *           the build's candidate count),
+ *           the build's candidate count; for k > 64 and in FP64 the exact
+ *           FP64-distance search),
  *   mu(z) = K(z, X_N*) (K(X_N*, X_N*) + sigma^2 I)^{-1} Y(X_N*),
  * with the model's k, kernel, hyperparameters and precision (a k x k solve
  * per query, refined in MIXED as in the build).
@@ -206,8 +213,9 @@ fmg_status fastmuygps_loo_loss(const fmg_model *model, const int32_t *rows, int6
  * Loss and gradient are NaN when a batch row's matrix is not positive
  * definite under theta.  Synchronises `stream`.  Errors: FMG_E_INVALID_ARG
  * (null pointers, b < 1, a row outside [0, n), invalid hyperparameters, a
- * self-inclusive model), FMG_E_UNSUPPORTED ((k+1)(d+1) + k(k+1)/2 + 128
- * doubles exceed 64 KB), FMG_E_BUSY, FMG_E_OOM, FMG_E_DEVICE. */
+ * self-inclusive model), FMG_E_UNSUPPORTED (k > 64, or (k+1)(d+1) +
+ * k(k+1)/2 + 128 doubles exceed 64 KB), FMG_E_BUSY, FMG_E_OOM,
+ * FMG_E_DEVICE. */
 fmg_status fastmuygps_loo_loss_grad(const fmg_model *model, const int32_t *rows, int64_t b,
                                     const fmg_hyper *hyper, double *loss, double *grad,
                                     void *stream);

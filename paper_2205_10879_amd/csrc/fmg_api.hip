@@ -455,7 +455,12 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
     if (n < 2 || n > 2147483647LL) return fail(FMG_E_INVALID_ARG, "n = %lld out of range", (long long)n);
     if (d < 1) return fail(FMG_E_INVALID_ARG, "d = %d must be >= 1", d);
     if (ell < 1 || ell > 16) return fail(FMG_E_INVALID_ARG, "ell = %d must be in [1, 16]", ell);
-    if (k < 1 || k > 64) return fail(FMG_E_INVALID_ARG, "k = %d must be in [1, 64]", k);
+    if (k < 1 || k > 256) return fail(FMG_E_INVALID_ARG, "k = %d must be in [1, 256]", k);
+    if (k > 64 && prec == FMG_PREC_MIXED)
+        return fail(FMG_E_UNSUPPORTED, "k = %d > 64 needs FP64 or FP32 precision", k);
+    if (k > 64 && precompute_wide_lds_bytes(prec == FMG_PREC_FP64, k, d) > PRECOMPUTE_WIDE_LDS_MAX)
+        return fail(FMG_E_UNSUPPORTED, "k = %d, d = %d: the neighbourhood factor does not fit "
+                                       "160 KB of LDS", k, d);
     if (!self_inc && k > n - 1)
         return fail(FMG_E_INVALID_ARG, "leave-one-out needs k <= n-1 (k=%d, n=%lld)", k, (long long)n);
     if (self_inc && k > n)
@@ -543,6 +548,11 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
     }
 
     const int kk = self_inc ? k - 1 : k;  // neighbours found by search
+    // Screening rows (FP32 and MIXED): the candidate side is kept by the
+    // model for the queries' search, the query side serves the build.
+    int64_t n_pad = 0;
+    void *Xq = nullptr;
+    double *ex = nullptr, *nzx = nullptr;
     if (kk == 0) {
         record(M, M->evb, EV_PREP, s);
         HCHK(launch_self_rows(M->N, n, s), "self rows");
@@ -563,7 +573,7 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
         HCHK(launch_exact_topk(true, ea, n, s), "exact search");
         for (int e = EV_SCREEN; e <= EV_FALLBACK; ++e) record(M, M->evb, e, s);
     } else {
-        const int64_t n_pad = round_up(n, SCREEN_QPB);
+        n_pad = round_up(n, SCREEN_QPB);
         M->n_pad = n_pad;
         MCHK(model_alloc(M, MA_MU, (void **)&M->mu, (size_t)d * 4, "model mu"));
         if (flags & FMG_FLAG_NO_CENTER)
@@ -574,8 +584,6 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
             HCHK(launch_col_mean(M->X, false, n, d, M->mu, part, s), "column mean");
         }
         MCHK(model_alloc(M, MA_XP, &M->Xp, (size_t)n_pad * geom.row_bytes, "model screen rows"));
-        void *Xq = nullptr;
-        double *ex = nullptr, *nzx = nullptr;
         unsigned long long *mx = nullptr;
         HCHK(tmp.alloc(&Xq, (size_t)n_pad * geom.row_bytes), "scratch");
         HCHK(tmp.alloc((void **)&ex, (size_t)n * 8), "scratch");
@@ -594,9 +602,26 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
         const double u = std::ldexp(1.0, -23);
         const double nt = 2.0 * geom.kp;
         M->acc_coef = nt * u / (1.0 - nt * u);
-        M->c_build = prec == FMG_PREC_MIXED ? 2 * kk : kk + 8;
         M->c_query = 16;
-
+    }
+    if (kk > 64 && !f64) {
+        // Neighbourhoods wider than a wavefront: pooled exact search (the
+        // screening rows above still serve the queries' nearest-point search).
+        ExactArgs ea{};
+        ea.X = M->X;
+        ea.n = n;
+        ea.d = d;
+        ea.Qc = M->X;
+        ea.nq = n;
+        ea.loo = 1;
+        ea.k = kk;
+        ea.self_first = self_inc;
+        ea.out = M->N;
+        ea.out_stride = k;
+        HCHK(launch_exact_topk(false, ea, n, s), "exact search");
+        for (int e = EV_SCREEN; e <= EV_FALLBACK; ++e) record(M, M->evb, e, s);
+    } else if (kk > 0 && !f64) {
+        M->c_build = prec == FMG_PREC_MIXED ? 2 * kk : kk + 8;
         const int c = M->c_build;
         uint64_t *pool = nullptr, *cand = nullptr;
         float *tq = nullptr;
@@ -745,8 +770,9 @@ fmg_status fastmuygps_predict_muygps(const fmg_model *model, const void *Z, int6
     int32_t *nb = nbr_out;
     if (!nb) HIPCHK(tmp.alloc((void **)&nb, (size_t)m * k * 4), "scratch");
 
-    // 1. The query's own k nearest training points (nothing excluded).
-    if (f64) {
+    // 1. The query's own k nearest training points (nothing excluded); wider
+    // neighbourhoods than a wavefront take the pooled exact search.
+    if (f64 || k > 64) {
         ExactArgs ea{};
         ea.X = M->X;
         ea.n = M->n;
@@ -757,7 +783,7 @@ fmg_status fastmuygps_predict_muygps(const fmg_model *model, const void *Z, int6
         ea.k = k;
         ea.out = nb;
         ea.out_stride = k;
-        HIPCHK(launch_exact_topk(true, ea, m, s), "exact search");
+        HIPCHK(launch_exact_topk(f64, ea, m, s), "exact search");
     } else {
         const ScreenGeom &g = M->geom;
         const int64_t m_pad = round_up(m, SCREEN_QPB);
@@ -1009,6 +1035,9 @@ fmg_status fastmuygps_loo_loss_grad(const fmg_model *model, const int32_t *rows,
         return fail(FMG_E_INVALID_ARG, "noise_var must be >= 0 and finite");
     const int kc = kernel_code(*hyper);
     if (kc < 0) return fail(FMG_E_INVALID_ARG, "kernel must be RBF or Matern with nu in {0.5, 1.5, 2.5}");
+    if (M->k > 64)
+        return fail(FMG_E_UNSUPPORTED, "k = %d: the gradient holds one neighbour per lane (k <= 64)",
+                    M->k);
     if (loo_grad_lds_bytes(M->k, M->d) > 65536)
         return fail(FMG_E_UNSUPPORTED, "k = %d, d = %d: the gradient's staged rows exceed 64 KB",
                     M->k, M->d);

@@ -73,7 +73,7 @@ struct ExactArgs {
     const int32_t *count; // optional device count of `list`
     int64_t nq;           // number of query rows when count == nullptr
     int loo;              // exclude candidate == query row index
-    int k;                // 1..64
+    int k;                // 1..256 (k > 64: the pooled search)
     int self_first;
     int32_t *out;
     int out_stride;
@@ -135,7 +135,14 @@ hipError_t launch_prep_rows(const ScreenGeom &g, const float *X, int64_t n, int6
 hipError_t launch_screen(const ScreenGeom &g, const ScreenArgs &a, hipStream_t s);
 hipError_t launch_rerank(const RerankArgs &a, hipStream_t s);
 hipError_t launch_exact_topk(bool f64, const ExactArgs &a, int64_t max_items, hipStream_t s);
+// k <= 64: one wavefront per point (fmg_precompute*.hip); 64 < k <= 256: one
+// workgroup per point with the factor in LDS (fmg_precompute_wide.hip, no
+// refinement step), needing precompute_wide_lds_bytes(f64, k, d) <=
+// PRECOMPUTE_WIDE_LDS_MAX.
 hipError_t launch_precompute(bool f64, bool refine, const PrecomputeArgs &a, hipStream_t s);
+constexpr size_t PRECOMPUTE_WIDE_LDS_MAX = 160 * 1024;
+size_t precompute_wide_lds_bytes(bool f64, int k, int d);
+hipError_t launch_precompute_wide(bool f64, const PrecomputeArgs &a, hipStream_t s);
 // FP32 precompute (FP32 and MIXED precision), refinement optional.
 hipError_t launch_precompute32(bool refine, const PrecomputeArgs &a, hipStream_t s);
 hipError_t launch_gather(bool f64, const GatherArgs &a, hipStream_t s);

@@ -207,6 +207,7 @@ hipError_t launch_pc_k(const PrecomputeArgs &a, hipStream_t s) {
 
 hipError_t launch_precompute(bool f64, bool refine, const PrecomputeArgs &a, hipStream_t s) {
     if (a.n <= 0) return hipSuccess;
+    if (a.k > 64) return launch_precompute_wide(f64, a, s);
     if (f64) return launch_pc_k<double, false>(a, s);
     return launch_precompute32(refine, a, s);
 }

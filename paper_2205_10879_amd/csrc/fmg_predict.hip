@@ -4,8 +4,9 @@
 // One wavefront per query; lane s gathers neighbour N(j)_s with 16-byte
 // loads, forms its kernel value, multiplies it into row s of C[j] (ell
 // contiguous values, so the wave reads C[j] as one contiguous k*ell block)
-// and the ell sums are DPP wave reductions.  The cross-covariance carries no
-// nugget.
+// and the ell sums are DPP wave reductions.  Neighbourhoods wider than the
+// wave (k <= 256) give lane s the rows s + 64 r as well.  The
+// cross-covariance carries no nugget.
 #include "fmg_device.h"
 #include "fmg_kernels.h"
 
@@ -51,7 +52,7 @@ __device__ __forceinline__ T row_sqdist(const T *__restrict__ z, const T *__rest
     return (s0 + s1) + (s2 + s3);
 }
 
-template <typename T, bool VEC, int ELLMAX>
+template <typename T, bool VEC, int ELLMAX, int KR>
 __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
     const int lane = lane_id();
     const int64_t q = (int64_t)blockIdx.x * G_WAVES + (threadIdx.x >> 6);
@@ -70,38 +71,56 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
     // Row s of C[j]: ell contiguous values; the wave's rows form one
     // contiguous block of k * ell values.  Its loads only need j, so they
     // are issued before the neighbour rows.
-    T cv[ELLMAX];
-    const T *__restrict__ Cj = C + (j * a.k + lane) * ell;
+    T cv[KR][ELLMAX];
 #pragma unroll
-    for (int c = 0; c < ELLMAX; ++c) cv[c] = (lane < a.k && c < ell) ? Cj[c] : T(0);
-    T w = T(0);
-    if (lane < a.k) {
-        const int64_t p = a.N[j * a.k + lane];
-        const T D = row_sqdist<T, VEC>(Z + zr * a.d, X + p * a.d, a.d);
-        w = phi_t<T>(D, a.kc, (T)a.inv_rho, (T)a.amp);
+    for (int r = 0; r < KR; ++r) {
+        const int s = lane + 64 * r;
+        const T *__restrict__ Cj = C + (j * a.k + s) * ell;
+#pragma unroll
+        for (int c = 0; c < ELLMAX; ++c) cv[r][c] = (s < a.k && c < ell) ? Cj[c] : T(0);
+    }
+    T w[KR];
+#pragma unroll
+    for (int r = 0; r < KR; ++r) {
+        const int s = lane + 64 * r;
+        w[r] = T(0);
+        if (s < a.k) {
+            const int64_t p = a.N[j * a.k + s];
+            const T D = row_sqdist<T, VEC>(Z + zr * a.d, X + p * a.d, a.d);
+            w[r] = phi_t<T>(D, a.kc, (T)a.inv_rho, (T)a.amp);
+        }
     }
     // Fixed trip count (columns past ell are zero and not stored), so the loop
     // unrolls and cv stays in registers.
 #pragma unroll
     for (int c = 0; c < ELLMAX; ++c) {
-        const T r = dpp_t_sum_last<T>(w * cv[c], lane);
-        if (lane == 63 && c < ell) out[c] = r;
+        T v = w[0] * cv[0][c];
+#pragma unroll
+        for (int r = 1; r < KR; ++r) v += w[r] * cv[r][c];
+        const T t = dpp_t_sum_last<T>(v, lane);
+        if (lane == 63 && c < ell) out[c] = t;
     }
 }
 
 // Response columns are reduced up to ELLMAX (zeros past ell are not stored).
+template <typename T, bool VEC, int KR>
+void launch_gather_kr(const GatherArgs &a, unsigned blocks, hipStream_t s) {
+    if (a.ell <= 1)
+        hipLaunchKernelGGL((gather_kernel<T, VEC, 1, KR>), dim3(blocks), dim3(256), 0, s, a);
+    else if (a.ell <= 4)
+        hipLaunchKernelGGL((gather_kernel<T, VEC, 4, KR>), dim3(blocks), dim3(256), 0, s, a);
+    else if (a.ell <= 8)
+        hipLaunchKernelGGL((gather_kernel<T, VEC, 8, KR>), dim3(blocks), dim3(256), 0, s, a);
+    else if (a.ell <= 12)
+        hipLaunchKernelGGL((gather_kernel<T, VEC, 12, KR>), dim3(blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((gather_kernel<T, VEC, 16, KR>), dim3(blocks), dim3(256), 0, s, a);
+}
+
 template <typename T, bool VEC>
 void launch_gather_t(const GatherArgs &a, unsigned blocks, hipStream_t s) {
-    if (a.ell <= 1)
-        hipLaunchKernelGGL((gather_kernel<T, VEC, 1>), dim3(blocks), dim3(256), 0, s, a);
-    else if (a.ell <= 4)
-        hipLaunchKernelGGL((gather_kernel<T, VEC, 4>), dim3(blocks), dim3(256), 0, s, a);
-    else if (a.ell <= 8)
-        hipLaunchKernelGGL((gather_kernel<T, VEC, 8>), dim3(blocks), dim3(256), 0, s, a);
-    else if (a.ell <= 12)
-        hipLaunchKernelGGL((gather_kernel<T, VEC, 12>), dim3(blocks), dim3(256), 0, s, a);
-    else
-        hipLaunchKernelGGL((gather_kernel<T, VEC, 16>), dim3(blocks), dim3(256), 0, s, a);
+    if (a.k <= 64) launch_gather_kr<T, VEC, 1>(a, blocks, s);
+    else launch_gather_kr<T, VEC, 4>(a, blocks, s);
 }
 
 }  // namespace
@@ -111,7 +130,7 @@ hipError_t launch_gather(bool f64, const GatherArgs &a, hipStream_t s) {
     const unsigned blocks = (unsigned)((a.m + G_WAVES - 1) / G_WAVES);
     // Rows are 16-byte aligned when d is a multiple of 4 (float) or 2
     // (double) and both arrays start on a 16-byte boundary.
-    if (a.ell > 16) return hipErrorInvalidValue;
+    if (a.ell > 16 || a.k > 256) return hipErrorInvalidValue;
     const bool base16 = (((uintptr_t)a.X | (uintptr_t)a.Z) & 15) == 0;
     const bool vec = f64 ? (a.d % 2 == 0 && base16) : (a.d % 4 == 0 && base16);
     if (f64) {

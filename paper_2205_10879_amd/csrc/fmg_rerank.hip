@@ -85,9 +85,8 @@ __global__ __launch_bounds__(256) void rerank_kernel(RerankArgs a) {
 
     int32_t *o = a.out + q * (int64_t)a.out_stride;
     if (a.self_first) {
-        const uint32_t prev = shfl_u32(list.p, lane > 0 ? lane - 1 : 0);
         if (lane == 0) o[0] = (int32_t)q;
-        else if (lane <= a.k) o[lane] = (int32_t)prev;
+        if (lane < a.k) o[1 + lane] = (int32_t)list.p;  // a.k <= 64 others
     } else if (lane < a.k) {
         o[lane] = (int32_t)list.p;
     }

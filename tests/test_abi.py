@@ -60,7 +60,7 @@ def test_bad_arguments_fail_before_any_device_call(lib):
             (10, 2, 17, 3, fmg.PREC_FP32, 1.5, 1.0, 0.1, 0),    # ell > 16
             (10, 2, 1, 10, fmg.PREC_FP32, 1.5, 1.0, 0.1, 0),    # LOO k > n-1
             (10, 2, 1, 11, fmg.PREC_FP32, 1.5, 1.0, 0.1, fmg.FLAG_SELF_INCLUSIVE),  # k > n
-            (100, 2, 1, 65, fmg.PREC_FP32, 1.5, 1.0, 0.1, 0),   # k > 64
+            (300, 2, 1, 257, fmg.PREC_FP32, 1.5, 1.0, 0.1, 0),  # k > 256
             (10, 2, 1, 3, fmg.PREC_FP32, 0.7, 1.0, 0.1, 0),     # nu
             (10, 2, 1, 3, fmg.PREC_FP32, 1.5, 0.0, 0.1, 0),     # rho
             (10, 2, 1, 3, fmg.PREC_FP32, 1.5, 1.0, -0.1, 0),    # noise
@@ -143,3 +143,21 @@ def test_loo_loss_grad_rejects_bad_arguments(lib):
     assert f(fake, fake, 4, None, ctypes.byref(out), grad, None) == fmg.FMG_E_INVALID_ARG
     assert f(fake, fake, 4, ctypes.byref(hy), None, grad, None) == fmg.FMG_E_INVALID_ARG
     assert f(fake, fake, 4, ctypes.byref(hy), ctypes.byref(out), None, None) == fmg.FMG_E_INVALID_ARG
+
+
+def test_wide_neighbourhood_limits_are_checked_before_any_device_work(lib):
+    import paper_2205_10879_amd as fmg
+    fake = ctypes.c_void_p(16)  # never dereferenced: arguments are checked first
+    hy = fmg.FmgHyper(fmg.KERNEL_MATERN, 1.5, 1.0, 0.1, 1.0)
+    out = ctypes.c_void_p()
+    b = lib.fastmuygps_build
+    # k above 256
+    assert b(fake, fake, 1000, 4, 1, 257, ctypes.byref(hy), fmg.PREC_FP64, 0, None,
+             ctypes.byref(out)) == fmg.FMG_E_INVALID_ARG
+    # k > 64 is not offered in MIXED precision
+    assert b(fake, fake, 1000, 4, 1, 100, ctypes.byref(hy), fmg.PREC_MIXED, 0, None,
+             ctypes.byref(out)) == fmg.FMG_E_UNSUPPORTED
+    # the packed FP64 factor of k = 256 does not fit 160 KB of LDS
+    assert b(fake, fake, 1000, 4, 1, 256, ctypes.byref(hy), fmg.PREC_FP64, 0, None,
+             ctypes.byref(out)) == fmg.FMG_E_UNSUPPORTED
+    assert out.value is None

@@ -1,0 +1,128 @@
+"""GPU parity of neighbourhoods wider than a wavefront (64 < k <= 256: the
+pooled exact search, the workgroup factorisation and the multi-row gather)
+against the FP64 oracle, through the C ABI: neighbour lists bit-exact, means
+within the precision's tolerance, for the build, the prediction, self-inclusive
+sets, MuyGPs prediction and the leave-one-out loss; and the limits that are
+reported instead of computed."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.parity_util import TOL_MEAN, backward_error, rel_err
+
+pytestmark = pytest.mark.gpu
+
+DT = {"fp64": np.float64, "fp32": np.float32}
+
+
+def fmg():
+    import paper_2205_10879_amd as f
+    return f
+
+
+def build(prec, X, Y, k, kernel, nu, rho, noise, flags=0):
+    X = np.ascontiguousarray(X, dtype=DT[prec])
+    Y = np.ascontiguousarray(Y, dtype=DT[prec])
+    model = fmg().fastmuygps_build(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), k,
+                                   kernel, nu, rho, noise, precision=prec, flags=flags)
+    return model, X.astype(np.float64), Y.astype(np.float64)
+
+
+# kappa of the neighbourhood matrices stays <= ~1.2e3 in these configurations,
+# where the FP32 solve is within its 2e-4 bar.
+CONFIGS = [
+    (2000, 150, 3, 100, 2, "matern", 1.5, 0.3, 1e-2),   # two rows per lane in the gather
+    (1200, 97, 8, 150, 1, "rbf", 0.0, 0.8, 5e-2),       # the borehole emulator's k
+    (900, 64, 2, 256, 3, "matern", 2.5, 0.15, 5e-2),    # k at its maximum (FP32)
+    (1500, 33, 4, 65, 2, "matern", 0.5, 0.5, 1e-2),     # one past a wavefront
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,m,d,k,ell,kernel,nu,rho,noise", CONFIGS)
+def test_wide_build_and_predict_match_the_oracle(prec, n, m, d, k, ell, kernel, nu, rho, noise):
+    f = fmg()
+    X, Y, Z = synth.small(n, m, d, ell=ell, seed=100 + k)
+    if prec == "fp64" and k == 256:
+        # the packed FP64 factor of k = 256 exceeds 160 KB of LDS: reported, not run
+        with pytest.raises(f.FmgError) as e:
+            build(prec, X, Y, k, kernel, nu, rho, noise)
+        assert e.value.status == f.FMG_E_UNSUPPORTED
+        return
+    model, X64, Y64 = build(prec, X, Y, k, kernel, nu, rho, noise)
+    Zt = torch.from_numpy(np.ascontiguousarray(Z, dtype=DT[prec])).cuda()
+    nn = torch.empty(m, dtype=torch.int32, device="cuda")
+    mu = model.predict(Zt, nn_out=nn).cpu().numpy()
+    N = model.neighbors().cpu().numpy()
+    C = model.coeffs().cpu().numpy()
+    info = model.info()
+    model.free()
+    Z64 = Z.astype(DT[prec]).astype(np.float64)
+    Nr, Cr, st = oracle.build_model(X64, Y64, k, kernel, nu, rho, noise)
+    assert np.all(st == 0) and info["nonpd_rows"] == 0
+    assert np.array_equal(N, Nr), "neighbour lists differ from the oracle"
+    ref, nnr, _ = oracle.predict(X64, Y64, Z64, k, kernel, nu, rho, noise, 1.0, oracle.MODE_LOO,
+                                 model=(Nr, Cr, st))
+    assert np.array_equal(nn.cpu().numpy(), nnr)
+    assert rel_err(mu, ref) <= TOL_MEAN[prec]
+    be = backward_error(X64, Y64, Nr[:24], C[:24], kernel, nu, rho, noise)
+    assert np.max(be) < (1e-13 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("k", [65, 100])
+def test_wide_self_inclusive_sets(prec, k):
+    # k = 65 searches 64 others (one neighbour per lane) and factors 65 wide
+    X, Y, Z = synth.small(1100, 40, 3, ell=2, seed=7 + k)
+    f = fmg()
+    model, X64, Y64 = build(prec, X, Y, k, "matern", 1.5, 0.4, 2e-2, f.FLAG_SELF_INCLUSIVE)
+    Zt = torch.from_numpy(np.ascontiguousarray(Z, dtype=DT[prec])).cuda()
+    mu = model.predict(Zt).cpu().numpy()
+    N = model.neighbors().cpu().numpy()
+    model.free()
+    Nr, Cr, st = oracle.build_model(X64, Y64, k, "matern", 1.5, 0.4, 2e-2, 1.0, oracle.MODE_SELF)
+    assert np.array_equal(N, Nr)
+    assert np.array_equal(N[:, 0], np.arange(1100))
+    ref, _, _ = oracle.predict(X64, Y64, Z.astype(DT[prec]).astype(np.float64), k, "matern", 1.5,
+                               0.4, 2e-2, 1.0, oracle.MODE_SELF, model=(Nr, Cr, st))
+    assert rel_err(mu, ref) <= TOL_MEAN[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_wide_muygps_prediction(prec):
+    X, Y, Z = synth.small(1600, 70, 4, ell=3, seed=41)
+    k = 120
+    model, X64, Y64 = build(prec, X, Y, k, "rbf", 0.0, 0.7, 3e-2)
+    Zt = torch.from_numpy(np.ascontiguousarray(Z, dtype=DT[prec])).cuda()
+    nb = torch.empty((70, k), dtype=torch.int32, device="cuda")
+    mu = model.predict_muygps(Zt, nbr_out=nb).cpu().numpy()
+    model.free()
+    ref, nbr, st = oracle.muygps_predict(X64, Y64, Z.astype(DT[prec]).astype(np.float64), k,
+                                         "rbf", 0.0, 0.7, 3e-2)
+    assert np.all(st == 0)
+    assert np.array_equal(nb.cpu().numpy(), nbr)
+    assert rel_err(mu, ref) <= TOL_MEAN[prec]
+
+
+def test_wide_loo_loss_and_the_gradient_limit():
+    f = fmg()
+    X, Y, _ = synth.small(1400, 1, 3, ell=2, seed=43)
+    k = 90
+    model, X64, Y64 = build("fp64", X, Y, k, "matern", 2.5, 1.0, 1e-2)
+    rows = np.random.default_rng(3).choice(1400, 200, replace=False).astype(np.int32)
+    rows_d = torch.from_numpy(rows).cuda()
+    for rho in (0.3, 0.8):
+        got = model.loo_loss(rows_d, "matern", 2.5, rho, 1e-2)
+        N, C, _ = oracle.build_model(X64, Y64, k, "matern", 2.5, rho, 1e-2, rows=rows)
+        ref = float(np.mean((Y64[rows] - oracle.means(X64, X64[rows], N, C, "matern", 2.5,
+                                                      rho)) ** 2))
+        assert abs(got - ref) <= 1e-9 * ref
+    out = model.loo_predict(rows_d).cpu().numpy()
+    N, C, _ = oracle.build_model(X64, Y64, k, "matern", 2.5, 1.0, 1e-2, rows=rows)
+    assert rel_err(out, oracle.means(X64, X64[rows], N, C, "matern", 2.5, 1.0)) <= 1e-10
+    with pytest.raises(f.FmgError) as e:
+        model.loo_loss_grad(rows_d, "matern", 2.5, 0.8, 1e-2)
+    assert e.value.status == f.FMG_E_UNSUPPORTED
+    model.free()
