@@ -49,6 +49,10 @@ def main():
     ap.add_argument("--serve-qps", type=float, default=2.0e6, help="offered queries per second")
     ap.add_argument("--no-muygps", action="store_true",
                     help="skip the MuyGPs prediction beside FastMuyGPs")
+    ap.add_argument("--no-borehole", action="store_true",
+                    help="skip the borehole emulator and its MCMC calibration")
+    ap.add_argument("--no-training", action="store_true",
+                    help="skip the leave-one-out loss and gradient timings")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy 3 times (scale for HBM counters)")
     args = ap.parse_args()
@@ -181,6 +185,16 @@ def main():
     if not args.no_muygps:
         muygps_run(fmg, np, torch, w, X, Y, Z, out, stream, args, result)
 
+    # MuyGPs hyperparameter training on the same model (Algorithm 1): the loss
+    # Q(theta) in the model's precision and its FP64 gradient, on a batch.
+    if not args.no_training:
+        training_run(fmg, np, torch, w, X, Y, stream, result)
+
+    # The borehole emulator (Section 4.2): k = 150 in FP64, its single-query
+    # latency and an MCMC calibration driven by its predictions.
+    if not args.no_borehole:
+        borehole_run(fmg, np, torch, synth, stream, result)
+
     if args.serve_seconds > 0:
         result["served"] = {}
         for prec in ("mixed", "fp32"):
@@ -257,6 +271,113 @@ def muygps_run(fmg, np, torch, w, X, Y, Z, out, stream, args, result):
             (mu_fast.cpu().numpy() - w.Yz) ** 2))),
         "accuracy": float(np.mean(np.argmax(mu_mg, 1) == w.extra["labels_test"]))}
     log("MuyGPs predict: %s" % result["muygps_predict"])
+
+
+def training_run(fmg, np, torch, w, X, Y, stream, result, b=65536):
+    log("leave-one-out loss and gradient on %d rows" % b)
+    model = fmg.fastmuygps_build(X, Y, w.k, w.kernel, w.nu, w.rho, w.noise, precision="mixed",
+                                 stream=stream)
+    rows = torch.from_numpy(np.sort(np.random.default_rng(9).choice(
+        X.shape[0], b, replace=False)).astype(np.int32)).cuda()
+    model.loo_loss(rows, w.kernel, w.nu, w.rho, w.noise, stream=stream)  # warm-up
+    model.loo_loss_grad(rows, w.kernel, w.nu, w.rho, w.noise, stream=stream)
+    t0 = time.perf_counter()
+    q = model.loo_loss(rows, w.kernel, w.nu, w.rho, w.noise, stream=stream)
+    t1 = time.perf_counter()
+    qg, g = model.loo_loss_grad(rows, w.kernel, w.nu, w.rho, w.noise, stream=stream)
+    t2 = time.perf_counter()
+    model.free()
+    result["training"] = {
+        "batch_rows": b, "loo_loss_ms": round((t1 - t0) * 1e3, 3),
+        "loo_loss_grad_fp64_ms": round((t2 - t1) * 1e3, 3), "loss_mixed": q, "loss_fp64": qg,
+        "grad_length_scale": float(g[0]), "grad_noise_var": float(g[1])}
+    log("training: %s" % result["training"])
+
+
+def borehole_run(fmg, np, torch, synth, stream, result, chains=4096, steps=300, burn=100,
+                 latency_reps=300):
+    w = synth.borehole()
+    log("borehole emulator: n=%d m=%d k=%d, RBF rho=%g, FP64" % (
+        w.X.shape[0], w.Z.shape[0], w.k, w.rho))
+    X = torch.from_numpy(w.X).cuda()
+    Y = torch.from_numpy(w.Y).cuda()
+    Z = torch.from_numpy(w.Z).cuda()
+    for rep in range(2):  # the first build warms up the kernels
+        model = fmg.fastmuygps_build(X, Y, w.k, w.kernel, w.nu, w.rho, w.noise, precision="fp64",
+                                     flags=fmg.FLAG_TIMING, stream=stream)
+        mu = model.predict(Z, stream=stream)
+        t = model.timings()
+        if rep == 0:
+            model.free()
+    rm = float(np.sqrt(np.mean((mu.cpu().numpy() - w.Yz) ** 2)))
+    # single-query predictions, one after another (the MCMC use of an emulator)
+    one = torch.empty((1, 1), dtype=torch.float64, device="cuda")
+    lat = []
+    for r in range(latency_reps):
+        z = Z[r:r + 1]
+        c0 = time.perf_counter()
+        model.predict(z, out=one, stream=stream)
+        stream.synchronize()
+        lat.append((time.perf_counter() - c0) * 1e3)
+    lat = np.sort(np.array(lat[10:]))
+    mc = borehole_mcmc(fmg, np, torch, synth, w, model, chains, steps, burn)
+    model.free()
+    result["borehole"] = {
+        "workload": w.name, "n": int(w.X.shape[0]), "m": int(w.Z.shape[0]), "k": w.k,
+        "noise_var": w.noise, "build_ms": round(t["build_total_ms"], 3),
+        "build_search_ms": round(t["build_prep_ms"] + t["build_screen_ms"], 3),
+        "build_precompute_ms": round(t["build_precompute_ms"], 3),
+        "predict_ms": round(t["predict_total_ms"], 3),
+        "predictions_per_s": round(w.Z.shape[0] / (t["predict_total_ms"] / 1e3), 1),
+        "rmse": rm, "single_query_p50_ms": round(float(np.percentile(lat, 50)), 4),
+        "single_query_p99_ms": round(float(np.percentile(lat, 99)), 4), "mcmc": mc}
+    log("borehole: %s" % result["borehole"])
+
+
+def borehole_mcmc(fmg, np, torch, synth, w, model, chains, steps, burn, step_sd=0.01,
+                  like_sd=1.0):
+    """Metropolis calibration of the borehole radius r_w with the emulator
+    (Section 4.2): the observed flow is the borehole function at r_w = 0.09
+    (unit coordinate 0.4) with the other parameters at mid-range, the
+    likelihood Gaussian with standard deviation 1 on the flow, the prior
+    uniform on the r_w range, random-walk proposals in the unit coordinate.
+    `chains` independent chains advance together, each step one batched
+    prediction of all their proposals."""
+    truth = np.full(8, synth.BOREHOLE_FIXED_U)
+    truth[0] = 0.4
+    y_obs = float(synth.borehole_flow(synth.BOREHOLE_LO + truth * (
+        synth.BOREHOLE_HI - synth.BOREHOLE_LO))) - w.extra["response_mean"]
+    base = torch.from_numpy(synth.borehole_inputs(truth)).cuda()
+    g = torch.Generator(device="cuda")
+    g.manual_seed(42)
+    u = torch.rand(chains, generator=g, dtype=torch.float64, device="cuda")
+    Zc = base.repeat(chains, 1)
+    Zc[:, 0] = u / synth.BOREHOLE_SCALE[0]
+    mu = model.predict(Zc)[:, 0]
+    acc = torch.zeros((), dtype=torch.float64, device="cuda")
+    tot = torch.zeros((), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    c0 = time.perf_counter()
+    for s in range(burn + steps):
+        up = u + step_sd * torch.randn(chains, generator=g, dtype=torch.float64, device="cuda")
+        inside = (up >= 0.0) & (up <= 1.0)
+        Zc[:, 0] = up.clamp(0.0, 1.0) / synth.BOREHOLE_SCALE[0]
+        mup = model.predict(Zc)[:, 0]
+        logr = ((mu - y_obs) ** 2 - (mup - y_obs) ** 2) / (2.0 * like_sd * like_sd)
+        lu = torch.log(torch.rand(chains, generator=g, dtype=torch.float64, device="cuda"))
+        take = inside & (lu < logr)
+        u = torch.where(take, up, u)
+        mu = torch.where(take, mup, mu)
+        if s >= burn:
+            acc += take.sum()
+            tot += u.sum()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - c0
+    n_s = chains * steps
+    return {"chains": chains, "steps": steps, "burn_in": burn, "samples": n_s,
+            "posterior_mean_rw_unit": float(tot) / n_s, "truth_rw_unit": 0.4,
+            "acceptance": float(acc) / n_s, "seconds": round(el, 3),
+            "samples_per_s": round(chains * (burn + steps) / el, 1)}
 
 
 def screen_traffic(n):

@@ -188,6 +188,7 @@ uint64_t predict_ws_bytes(int64_t max_m) {
     b += (uint64_t)rows * SCREEN_CMAX * 8;               // cand (c' <= SCREEN_CMAX)
     b += (uint64_t)rows * 4;                             // tq
     b += (uint64_t)max_m * 8 + 16;                       // fbl, nn, fbc
+    b += (uint64_t)NN_SPLIT_ENTRIES * 12;                // nn_key, nn_idx
     return b;
 }
 
@@ -209,6 +210,8 @@ fmg_status predict_ws_alloc(PredictWs *ws, int64_t max_m) {
         {(void **)&ws->fbl, (size_t)max_m * 4},
         {(void **)&ws->nn, (size_t)max_m * 4},
         {(void **)&ws->fbc, 16},
+        {(void **)&ws->nn_key, (size_t)NN_SPLIT_ENTRIES * 8},
+        {(void **)&ws->nn_idx, (size_t)NN_SPLIT_ENTRIES * 4},
     };
     for (auto &it : items) {
         hipError_t e = hipMalloc(it.p, it.bytes);
@@ -230,7 +233,8 @@ fmg_status predict_ws_alloc(PredictWs *ws, int64_t max_m) {
 }
 
 void predict_ws_free(PredictWs *ws) {
-    void *ptrs[] = {ws->Zq, ws->ez, ws->nzz, ws->pool, ws->cand, ws->tq, ws->fbl, ws->nn, ws->fbc};
+    void *ptrs[] = {ws->Zq,  ws->ez, ws->nzz, ws->pool,   ws->cand,  ws->tq,
+                    ws->fbl, ws->nn, ws->fbc, ws->nn_key, ws->nn_idx};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     *ws = PredictWs{};
@@ -267,6 +271,13 @@ fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_
         ea.k = 1;
         ea.out = nn;
         ea.out_stride = 1;
+        if (ws) {
+            ea.nn_key = ws->nn_key;
+            ea.nn_idx = ws->nn_idx;
+        } else {
+            HIPCHK(tmp.alloc((void **)&ea.nn_key, (size_t)NN_SPLIT_ENTRIES * 8), "scratch");
+            HIPCHK(tmp.alloc((void **)&ea.nn_idx, (size_t)NN_SPLIT_ENTRIES * 4), "scratch");
+        }
         HIPCHK(launch_exact_topk(true, ea, m, s), "exact search");
         for (int e = EV_SCREEN; e <= EV_FALLBACK; ++e) record(M, M->evp, e, s);
     } else {
@@ -570,6 +581,8 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
         ea.self_first = self_inc;
         ea.out = M->N;
         ea.out_stride = k;
+        HCHK(tmp.alloc((void **)&ea.nn_key, (size_t)NN_SPLIT_ENTRIES * 8), "scratch");
+        HCHK(tmp.alloc((void **)&ea.nn_idx, (size_t)NN_SPLIT_ENTRIES * 4), "scratch");
         HCHK(launch_exact_topk(true, ea, n, s), "exact search");
         for (int e = EV_SCREEN; e <= EV_FALLBACK; ++e) record(M, M->evb, e, s);
     } else {

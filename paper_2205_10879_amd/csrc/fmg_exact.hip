@@ -9,6 +9,12 @@
 // Used as the whole search in FP64 mode, and as the rescan of rows whose
 // screened candidate list could not be certified exact.
 //
+// The nearest point of a batch of queries (k = 1, the prediction's lookup)
+// runs one query per lane instead: a wave takes 64 queries and one chunk of
+// candidates, whose coordinates every lane reads at the same address; the
+// chunks are sized so that about 2048 waves fill the device, and a merge
+// takes the smallest (distance, index) over the chunks.
+//
 // Neighbourhoods wider than a wavefront (64 < k <= 256) use a pool instead:
 // each wave appends the keys that beat its current k-th to a 512-entry LDS
 // pool; when the pool nears capacity it is sorted (wave bitonic sort, eight
@@ -208,11 +214,105 @@ __global__ __launch_bounds__(256) void exact_wide_kernel(ExactArgs a) {
     }
 }
 
+constexpr int64_t NN_WAVES = 2048;
+
+template <typename T, int DMAX>
+__global__ __launch_bounds__(64) void nn_split_kernel(ExactArgs a, int64_t chunk, int splits) {
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x;
+    const int64_t q = (int64_t)blockIdx.x * 64 + lane;
+    const int y = blockIdx.y;
+    const int64_t m = a.nq;
+    const int d = a.d;
+    const T *__restrict__ X = (const T *)a.X;
+    const T *__restrict__ Qc = (const T *)a.Qc;
+    double z[DMAX];
+#pragma unroll
+    for (int c = 0; c < DMAX; ++c) z[c] = (q < m && c < d) ? (double)Qc[q * d + c] : 0.0;
+    const int64_t self = (a.loo && q < m) ? q : -1;
+    const int64_t p0 = (int64_t)y * chunk;
+    const int64_t p1 = (p0 + chunk < a.n) ? p0 + chunk : a.n;
+    uint64_t bk = ~0ull;
+    uint32_t bp = 0xffffffffu;
+    for (int64_t p = p0; p < p1; ++p) {
+        const T *__restrict__ xp = X + p * d;  // the same row for every lane
+        double s = 0.0;
+#pragma unroll
+        for (int c = 0; c < DMAX; ++c) {
+            if (c < d) {
+                const double t = z[c] - (double)xp[c];
+                const double t2 = t * t;
+                s = s + t2;
+            }
+        }
+        const uint64_t key = dkey(s);
+        if (key < bk && p != self) {  // ascending p: ties keep the smaller index
+            bk = key;
+            bp = (uint32_t)p;
+        }
+    }
+    if (q < m) {
+        if (splits == 1) {
+            a.out[q * (int64_t)a.out_stride] = (int32_t)bp;
+        } else {
+            a.nn_key[(int64_t)y * m + q] = bk;
+            a.nn_idx[(int64_t)y * m + q] = (int32_t)bp;
+        }
+    }
+}
+
+// Smallest (distance, index) over the chunks; one wave per query.
+__global__ __launch_bounds__(256) void nn_merge_kernel(ExactArgs a, int splits) {
+    const int lane = lane_id();
+    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (q >= a.nq) return;
+    const int64_t m = a.nq;
+    XKey key = xkey_empty();
+    for (int y = lane; y < splits; y += 64) {
+        const XKey o{a.nn_key[(int64_t)y * m + q], (uint32_t)a.nn_idx[(int64_t)y * m + q]};
+        if (xless(o, key)) key = o;
+    }
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const XKey o = shfl_x(key, lane ^ w);
+        if (xless(o, key)) key = o;
+    }
+    if (lane == 0) a.out[q * (int64_t)a.out_stride] = (int32_t)key.p;
+}
+
+template <typename T, int DMAX>
+hipError_t launch_nn_t(const ExactArgs &a, hipStream_t s) {
+    const int64_t qb = (a.nq + 63) / 64;
+    int64_t splits = a.nn_key && a.nn_idx ? NN_WAVES / qb : 1;
+    const int64_t most = (a.n + 63) / 64;  // at least 64 candidates per chunk
+    if (splits > most) splits = most;
+    if (splits < 1) splits = 1;
+    const int64_t chunk = (a.n + splits - 1) / splits;
+    splits = (a.n + chunk - 1) / chunk;  // splits * nq <= NN_SPLIT_ENTRIES
+    hipLaunchKernelGGL((nn_split_kernel<T, DMAX>), dim3((unsigned)qb, (unsigned)splits), dim3(64),
+                       0, s, a, chunk, (int)splits);
+    if (splits > 1)
+        hipLaunchKernelGGL(nn_merge_kernel, dim3((unsigned)((a.nq + 3) / 4)), dim3(256), 0, s, a,
+                           (int)splits);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_nn(const ExactArgs &a, hipStream_t s) {
+    if (a.d <= 4) return launch_nn_t<T, 4>(a, s);
+    if (a.d <= 8) return launch_nn_t<T, 8>(a, s);
+    if (a.d <= 16) return launch_nn_t<T, 16>(a, s);
+    if (a.d <= 32) return launch_nn_t<T, 32>(a, s);
+    return launch_nn_t<T, 64>(a, s);
+}
+
 }  // namespace
 
 hipError_t launch_exact_topk(bool f64, const ExactArgs &a, int64_t max_items, hipStream_t s) {
     if (max_items <= 0) return hipSuccess;
     if (a.k < 1 || a.k > 256) return hipErrorInvalidValue;
+    if (a.k == 1 && !a.self_first && !a.list && !a.count && a.d <= 64)
+        return f64 ? launch_nn<double>(a, s) : launch_nn<float>(a, s);
     int64_t blocks = (max_items + EXACT_WAVES - 1) / EXACT_WAVES;
     if (blocks > 8192) blocks = 8192;
     if (a.k > 64) {

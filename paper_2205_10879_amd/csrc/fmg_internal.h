@@ -72,6 +72,8 @@ struct PredictWs {
     uint64_t *pool = nullptr, *cand = nullptr;
     float *tq = nullptr;
     int32_t *fbl = nullptr, *fbc = nullptr, *nn = nullptr;
+    uint64_t *nn_key = nullptr;  // split nearest-point search (FP64 models)
+    int32_t *nn_idx = nullptr;
     uint64_t bytes = 0;
 };
 

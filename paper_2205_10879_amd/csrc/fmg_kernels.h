@@ -77,7 +77,16 @@ struct ExactArgs {
     int self_first;
     int32_t *out;
     int out_stride;
+    // Optional scratch for the nearest-point search (k = 1, query batches):
+    // partial minima of a scan split over candidate chunks, NN_SPLIT_ENTRIES
+    // each.  Without it every query is scanned by one lane over all points.
+    uint64_t *nn_key;
+    int32_t *nn_idx;
 };
+
+// Split nearest-point search: chunks x queries stays within this many
+// partial minima (2048 waves of 64 queries).
+constexpr int64_t NN_SPLIT_ENTRIES = 2048 * 64;
 
 struct PrecomputeArgs {
     const void *X;   // [n, d]

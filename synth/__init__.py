@@ -20,6 +20,8 @@ shapes):
          RBF, mixed precision (stands in for the star/galaxy classifier,
          Section 4.3).
   cfg 5a: 3-D uniform inputs with a random-Fourier response, Matern nu=1/2.
+  cfg 6: the borehole flow-rate function (Section 4.2) on Latin-hypercube
+         inputs, anisotropically scaled, RBF with k = 150, FP64.
 """
 from __future__ import annotations
 
@@ -130,6 +132,62 @@ def cfg5a(n: int = 5_000_000, m: int = 100_000) -> Workload:
     X, Y = draw(1, n)
     Z, Yz = draw(2, m)
     return Workload("cfg5a-fourier3d", X, Y, Z, Yz, 30, "matern", 0.5, 0.2, 4e-4, "fp32")
+
+
+# Borehole function (Section 4.2): parameter order, bounds, and the divisors
+# that make the inputs anisotropic.
+BOREHOLE_NAMES = ("r_w", "r", "T_u", "H_u", "T_l", "H_l", "L", "K_w")
+BOREHOLE_LO = np.array([0.05, 100.0, 63070.0, 990.0, 63.1, 700.0, 1120.0, 9855.0])
+BOREHOLE_HI = np.array([0.15, 50000.0, 115600.0, 1110.0, 116.0, 820.0, 1680.0, 12045.0])
+BOREHOLE_SCALE = np.array([0.0625, 0.25, 1.0, 0.25, 0.5, 0.25, 0.125, 0.5])
+BOREHOLE_VARY = (0, 1, 2, 4)  # r_w, r, T_u, T_l vary; H_u, H_l, L, K_w are held fixed
+BOREHOLE_FIXED_U = 0.5        # reading: the fixed parameters sit at their mid-range
+
+
+def borehole_flow(P):
+    """Water flow rate (m^3/yr) through a borehole for physical parameters
+    P [..., 8] in the order of BOREHOLE_NAMES (Section 4.2, borehole
+    equation)."""
+    P = np.asarray(P, dtype=np.float64)
+    rw, r, tu, hu, tl, hl, L, kw = (P[..., j] for j in range(8))
+    lg = np.log(r / rw)
+    return 2.0 * np.pi * tu * (hu - hl) / (lg * (1.0 + 2.0 * L * tu / (lg * rw * rw * kw) + tu / tl))
+
+
+def borehole_inputs(U):
+    """GP inputs from unit-cube coordinates U [..., 8]: each coordinate divided
+    by its anisotropy divisor."""
+    return np.asarray(U, dtype=np.float64) / BOREHOLE_SCALE
+
+
+def borehole_unit(cnt: int, rs: np.random.Generator):
+    """Latin-hypercube sample of the four varying parameters in unit-cube
+    coordinates (one point per stratum of each axis, independent random
+    permutations, uniform within the stratum); the fixed ones at mid-range."""
+    U = np.full((cnt, 8), BOREHOLE_FIXED_U)
+    for j in BOREHOLE_VARY:
+        U[:, j] = (rs.permutation(cnt) + rs.uniform(0.0, 1.0, size=cnt)) / cnt
+    return U
+
+
+def borehole(n: int = 100_000, m: int = 20_000, noise: float = 1e-6) -> Workload:
+    """Borehole emulator (Section 4.2): n training and m test points, each a
+    Latin-hypercube sample of (r_w, r, T_u, T_l) mapped affinely to its bounds
+    with H_u, H_l, L, K_w fixed at mid-range; inputs are the unit-cube
+    coordinates divided by [0.0625, 0.25, 1, 0.25, 0.5, 0.25, 0.125, 0.5]; the
+    response is the flow rate minus the training mean.  RBF kernel, length
+    scale 43.27, k = 150 (the paper's values); the nugget is not given and is
+    a reading; FP64."""
+    def draw(role, cnt):
+        U = borehole_unit(cnt, rng(6, role))
+        f = borehole_flow(BOREHOLE_LO + U * (BOREHOLE_HI - BOREHOLE_LO))
+        return borehole_inputs(U), f, U
+    X, fx, Ux = draw(1, n)
+    Z, fz, Uz = draw(2, m)
+    mean = float(np.mean(fx))
+    return Workload("borehole-emulator8d", X, (fx - mean)[:, None], Z, (fz - mean)[:, None], 150,
+                    "rbf", 0.0, 43.27, noise, "fp64",
+                    extra={"response_mean": mean, "unit_train": Ux, "unit_test": Uz})
 
 
 def cfg3_queries(m: int, role: int = 3, d: int = 40, classes: int = 10):
