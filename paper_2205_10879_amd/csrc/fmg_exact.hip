@@ -234,21 +234,35 @@ __global__ __launch_bounds__(64) void nn_split_kernel(ExactArgs a, int64_t chunk
     const int64_t p1 = (p0 + chunk < a.n) ? p0 + chunk : a.n;
     uint64_t bk = ~0ull;
     uint32_t bp = 0xffffffffu;
-    for (int64_t p = p0; p < p1; ++p) {
-        const T *__restrict__ xp = X + p * d;  // the same row for every lane
-        double s = 0.0;
+    // G candidates per iteration, their DMAX coordinates loaded unmasked (the
+    // same rows for every lane, so scalar loads; X carries 64 elements of
+    // padding past its last row) before any arithmetic; coordinates past d
+    // contribute an exact +0 to the sum.
+    constexpr int G = DMAX <= 4 ? 4 : (DMAX <= 8 ? 2 : 1);
+    for (int64_t p = p0; p < p1; p += G) {
+        double xv[G][DMAX];
 #pragma unroll
-        for (int c = 0; c < DMAX; ++c) {
-            if (c < d) {
-                const double t = z[c] - (double)xp[c];
+        for (int g = 0; g < G; ++g) {
+            const int64_t pr = (p + g < p1) ? p + g : p1 - 1;
+            const T *__restrict__ xp = X + pr * d;
+#pragma unroll
+            for (int c = 0; c < DMAX; ++c) xv[g][c] = (double)xp[c];
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            double s = 0.0;
+#pragma unroll
+            for (int c = 0; c < DMAX; ++c) {
+                const double t = (c < d) ? z[c] - xv[g][c] : 0.0;
                 const double t2 = t * t;
                 s = s + t2;
             }
-        }
-        const uint64_t key = dkey(s);
-        if (key < bk && p != self) {  // ascending p: ties keep the smaller index
-            bk = key;
-            bp = (uint32_t)p;
+            const uint64_t key = dkey(s);
+            const int64_t pg = p + g;
+            if (pg < p1 && key < bk && pg != self) {  // ascending p: ties keep the smaller index
+                bk = key;
+                bp = (uint32_t)pg;
+            }
         }
     }
     if (q < m) {

@@ -65,7 +65,8 @@ struct RerankArgs {
 };
 
 struct ExactArgs {
-    const void *X;        // [n, d] training coordinates (float or double)
+    const void *X;        // [n, d] training coordinates (float or double), followed by
+                          // 64 readable elements (the model's padded copy)
     int64_t n;
     int d;
     const void *Qc;       // [*, d] query coordinates

@@ -3,15 +3,17 @@
 // equation): for every training point i
 //     K_ab = phi(||x_{N(i)_a} - x_{N(i)_b}||)  (a != b),   K_aa = amp + sigma^2,
 //     C[i] = K^{-1} Y(X_{N(i)}),
-// in the model's precision T (FP64 or FP32).  One workgroup of 256 threads
-// per training point; K lives in LDS as a packed lower triangle (row a at
+// in the model's precision T (FP64 or FP32).  One workgroup of 1024 threads
+// per training point (the packed factor leaves room for one or two
+// workgroups per CU, so the workgroup itself supplies the waves that hide
+// LDS latency); K lives in LDS as a packed lower triangle (row a at
 // a (a + 1) / 2), so k = 150 in FP64 takes 90 KB:
 //   1. the k neighbour rows are staged in LDS;
-//   2. assembly over a 16 x 16 thread grid (thread (ty, tx) takes rows
-//      ty + 16 r and columns tx + 16 s of the lower triangle);
+//   2. assembly over a 32 x 32 thread grid (thread (ty, tx) takes rows
+//      ty + 32 r and columns tx + 32 s of the lower triangle);
 //   3. right-looking Cholesky: at step j every thread reads the pivot,
 //      thread a > j scales its entry of column j, and the trailing update
-//      is spread over the same 16 x 16 grid (two barriers per step);
+//      is spread over the same 32 x 32 grid (two barriers per step);
 //   4. forward and back substitution, thread a owning row a of all ell
 //      right-hand sides, the solved entry broadcast through LDS (double
 //      buffered, one barrier per step).
@@ -24,7 +26,9 @@ namespace fmg {
 
 namespace {
 
-constexpr int WIDE_THREADS = 256;
+constexpr int WIDE_THREADS = 1024;
+constexpr int WIDE_KMAX = 256;  // rows of the column and diagonal buffers
+constexpr int GRID = 32;        // the thread grid is GRID x GRID
 
 template <typename T>
 __device__ __forceinline__ T sqdist_rows(const T *__restrict__ u, const T *__restrict__ v, int d) {
@@ -37,7 +41,7 @@ __device__ __forceinline__ T sqdist_rows(const T *__restrict__ u, const T *__res
 }
 
 __host__ __device__ __forceinline__ size_t wide_lds_elems(int k, int d, int ellmax) {
-    return (size_t)k * (d + 1) + (size_t)k * (k + 1) / 2 + 2 * WIDE_THREADS + 2 * (size_t)ellmax;
+    return (size_t)k * (d + 1) + (size_t)k * (k + 1) / 2 + 2 * WIDE_KMAX + 2 * (size_t)ellmax;
 }
 
 template <typename T, int ELLMAX>
@@ -46,14 +50,14 @@ __global__ __launch_bounds__(WIDE_THREADS) void precompute_wide_kernel(Precomput
     const int64_t i = blockIdx.x;
     if (i >= P.n) return;
     const int a = threadIdx.x;  // row owned in the column steps and the solves
-    const int ty = a >> 4, tx = a & 15;
+    const int ty = a / GRID, tx = a % GRID;
     const int k = P.k, d = P.d, ell = P.ell;
     const int xs_ld = d + 1;
     T *xs = (T *)smem;                          // [k, d + 1]
     T *A = xs + (size_t)k * xs_ld;              // packed lower triangle
     T *col = A + (size_t)k * (k + 1) / 2;       // [256] column j of L
-    T *dg = col + WIDE_THREADS;                 // [256] L_jj
-    T *bc = dg + WIDE_THREADS;                  // [2][ELLMAX] solve broadcast
+    T *dg = col + WIDE_KMAX;                    // [256] L_jj
+    T *bc = dg + WIDE_KMAX;                     // [2][ELLMAX] solve broadcast
     const T *__restrict__ X = (const T *)P.X;
     const T *__restrict__ Y = (const T *)P.Y;
 
@@ -65,9 +69,9 @@ __global__ __launch_bounds__(WIDE_THREADS) void precompute_wide_kernel(Precomput
     __syncthreads();
 
     const T inv_rho = (T)P.inv_rho, amp = (T)P.amp, diag = (T)(P.amp + P.noise);
-    for (int r = ty; r < k; r += 16) {
+    for (int r = ty; r < k; r += GRID) {
         const size_t row = (size_t)r * (r + 1) / 2;
-        for (int b = tx; b <= r; b += 16)
+        for (int b = tx; b <= r; b += GRID)
             A[row + b] = (b == r) ? diag
                                   : phi_t<T>(sqdist_rows(xs + r * xs_ld, xs + b * xs_ld, d), P.kc,
                                              inv_rho, amp);
@@ -88,10 +92,10 @@ __global__ __launch_bounds__(WIDE_THREADS) void precompute_wide_kernel(Precomput
             col[a] = l;
         }
         __syncthreads();
-        for (int r = j + 1 + ty; r < k; r += 16) {
+        for (int r = j + 1 + ty; r < k; r += GRID) {
             const T lr = col[r];
             const size_t row = (size_t)r * (r + 1) / 2;
-            for (int b = j + 1 + tx; b <= r; b += 16) A[row + b] -= lr * col[b];
+            for (int b = j + 1 + tx; b <= r; b += GRID) A[row + b] -= lr * col[b];
         }
         __syncthreads();
     }
@@ -170,7 +174,7 @@ size_t precompute_wide_lds_bytes(bool f64, int k, int d) {
 
 hipError_t launch_precompute_wide(bool f64, const PrecomputeArgs &a, hipStream_t s) {
     if (a.n <= 0) return hipSuccess;
-    if (a.k < 1 || a.k > WIDE_THREADS || a.ell < 1 || a.ell > 16 ||
+    if (a.k < 1 || a.k > WIDE_KMAX || a.ell < 1 || a.ell > 16 ||
         precompute_wide_lds_bytes(f64, a.k, a.d) > PRECOMPUTE_WIDE_LDS_MAX)
         return hipErrorInvalidValue;
     return f64 ? launch_wide_e<double>(a, s) : launch_wide_e<float>(a, s);
