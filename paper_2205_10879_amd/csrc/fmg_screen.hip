@@ -334,14 +334,23 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
                 for (int mt = 0; mt < 4; ++mt) acc[t][mt] = Op::mfma(af[mt], bq[t][s], acc[t][mt]);
         }
 
-        // Candidate selection: the minimum of each lane's four values of a
-        // 16x16 tile is tested first (v_min3 + one compare); a tile whose
-        // minima fail in every lane costs one wave-wide test, otherwise each
-        // passing lane compares its four values and appends to its own
-        // sub-pool.  The query's own index and padding candidates may be
+        // Candidate selection.  For each query tile t a lane holds 16 values
+        // of its query (4 candidate tiles x 4 rows); their minimum (a chain of
+        // v_min3, no canonicalisation: the file is built without IEEE mode,
+        // every screened value being finite) is tested against the query's
+        // threshold, so a query tile whose candidates all fail costs one
+        // wave-wide branch.  Otherwise each candidate tile is tested the same
+        // way, and a passing lane compares its four values and appends to its
+        // own sub-pool.  The query's own index and padding candidates may be
         // appended here; the selection drops them.
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
+            float m16 = acc[t][0][0];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int i = (mt == 0 ? 1 : 0); i < 4; ++i) m16 = fminf(m16, acc[t][mt][i]);
+            if (__ballot(m16 <= thr[t]) == 0) continue;
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
                 const f32x4 v = acc[t][mt];
