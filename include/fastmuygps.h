@@ -81,6 +81,11 @@ typedef struct {
 #define FMG_FLAG_TIMING 0x8u         /* record per-phase HIP-event timings (build and the
                                         most recent predict); makes predict on this
                                         model unsafe to call from several threads */
+#define FMG_FLAG_NO_PRUNE 0x10u      /* MIXED: screen every candidate tile in the build
+                                        (by default the training points are ordered by
+                                        nearest pivot and tiles that no query of a
+                                        wavefront can take are skipped; results are
+                                        identical either way) */
 
 typedef struct fmg_model fmg_model;
 

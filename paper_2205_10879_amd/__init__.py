@@ -38,6 +38,7 @@ FLAG_SELF_INCLUSIVE = 0x1
 FLAG_NO_CENTER = 0x2
 FLAG_NO_REFINE = 0x4
 FLAG_TIMING = 0x8
+FLAG_NO_PRUNE = 0x10
 
 # Public C entry points (checked by the CPU tests against include/fastmuygps.h).
 EXPORTS = ("fastmuygps_build", "fastmuygps_predict", "fastmuygps_info", "fastmuygps_neighbors",

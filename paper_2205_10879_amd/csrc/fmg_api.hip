@@ -659,7 +659,51 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
         sa.pool = pool;
         sa.cand = cand;
         sa.tq = tq;
+        // Tile pruning: screen the self-join in nearest-pivot order, skipping
+        // tiles whose bounding balls no query of a wavefront can reach, then
+        // map the candidate lists back to the original order.
+        const bool prune = geom.mode == SCREEN_BF16 && !(flags & FMG_FLAG_NO_PRUNE) &&
+                           prune_pivots(n) > 1 && d <= 64;
+        uint32_t *perm = nullptr;
+        uint64_t *cand_p = nullptr;
+        float *tq_p = nullptr;
+        if (prune) {
+            uint32_t *asg = nullptr, *asg2 = nullptr, *idx = nullptr;
+            void *sort_tmp = nullptr, *Xq2 = nullptr, *Xp2 = nullptr, *tile_c = nullptr;
+            float *tile_r = nullptr, *nzq = nullptr;
+            size_t sort_bytes = 0;
+            HCHK(prune_sort_bytes(n, &sort_bytes), "sort size");
+            HCHK(tmp.alloc((void **)&perm, (size_t)n * 4), "scratch");
+            HCHK(tmp.alloc((void **)&asg, (size_t)n * 4), "scratch");
+            HCHK(tmp.alloc((void **)&asg2, (size_t)n * 4), "scratch");
+            HCHK(tmp.alloc((void **)&idx, (size_t)n * 4), "scratch");
+            HCHK(tmp.alloc(&sort_tmp, sort_bytes), "scratch");
+            HCHK(tmp.alloc(&Xq2, (size_t)n_pad * geom.row_bytes), "scratch");
+            HCHK(tmp.alloc(&Xp2, (size_t)n_pad * geom.row_bytes), "scratch");
+            HCHK(tmp.alloc(&tile_c, (size_t)(n_pad / SCREEN_TILE) * geom.row_bytes), "scratch");
+            HCHK(tmp.alloc((void **)&tile_r, (size_t)(n_pad / SCREEN_TILE) * 4), "scratch");
+            HCHK(tmp.alloc((void **)&nzq, (size_t)n_pad * 4), "scratch");
+            HCHK(tmp.alloc((void **)&cand_p, (size_t)n * c * 8), "scratch");
+            HCHK(tmp.alloc((void **)&tq_p, (size_t)n * 4), "scratch");
+            HCHK(launch_prune_order((const float *)M->X, n, d, M->mu, sort_tmp, sort_bytes, asg,
+                                    asg2, idx, perm, s),
+                 "pivot order");
+            HCHK(launch_prune_rows(geom, Xq, M->Xp, nzx, perm, n, n_pad, d, Xq2, Xp2, nzq, tile_c,
+                                   tile_r, s),
+                 "pruning rows");
+            sa.Q = Xq2;
+            sa.P = Xp2;
+            sa.cand = cand_p;
+            sa.tq = tq_p;
+            sa.prune = 1;
+            sa.tile_c = tile_c;
+            sa.tile_r = tile_r;
+            sa.nzq = nzq;
+            sa.acc_coef = M->acc_coef;
+            sa.nx_max = M->nx_max;
+        }
         HCHK(launch_screen(geom, sa, s), "screen");
+        if (prune) HCHK(launch_unpermute_cand(cand_p, tq_p, perm, n, c, cand, tq, s), "unpermute");
         record(M, M->evb, EV_SCREEN, s);
         RerankArgs ra{};
         ra.cand = cand;

@@ -37,6 +37,16 @@ __device__ __forceinline__ double dkey_inv(uint64_t k) {
     return __longlong_as_double((long long)u);
 }
 
+// BF16 from FP32, round to nearest even (finite inputs), and back.
+__device__ __forceinline__ uint16_t f32_to_bf16_rn(float f) {
+    uint32_t u = __float_as_uint(f);
+    uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(r >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+    return __uint_as_float((uint32_t)h << 16);
+}
+
 // Screen key: (screened value, candidate index) packed in 64 bits so that one
 // unsigned compare orders by value, then by index.
 __device__ __forceinline__ uint64_t skey(float s, uint32_t p) {

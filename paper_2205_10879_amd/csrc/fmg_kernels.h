@@ -41,6 +41,16 @@ struct ScreenArgs {
     uint64_t *pool;     // [splits, m_pad, SCREEN_CAP] scratch
     uint64_t *cand;     // [splits, m, c] sorted screen keys (value, index)
     float *tq;          // [splits, m] c-th kept value, +inf when fewer than c
+    // Tile pruning (BF16 screen of a self-join whose rows are ordered so that
+    // 64-row tiles are compact; prune != 0): per candidate tile a centroid row
+    // in the candidate-row format and a radius bounding its rows, the query
+    // rows' squared norms, and the accumulation-error coefficients of the
+    // certificate.  Each workgroup then starts its scan at its own rows.
+    int prune;
+    const void *tile_c;  // [n_pad / SCREEN_TILE, kp]
+    const float *tile_r; // [n_pad / SCREEN_TILE]
+    const float *nzq;    // [m_pad] ||z~||^2 of the query rows
+    double acc_coef, nx_max;
 };
 
 struct RerankArgs {
@@ -181,6 +191,23 @@ size_t loo_grad_lds_bytes(int k, int d);
 int loo_grad_blocks(int64_t b);
 hipError_t launch_loo_grad(bool f64, const GradArgs &a, double *part, double *out,
                            hipStream_t s);
+
+// Tile pruning of the build screen (fmg_prune.hip): the order of the training
+// points by nearest pivot (perm), the screening rows and query norms gathered
+// into it with the per-tile centroid rows and radii, and the screen's output
+// mapped back to the original order.
+int prune_pivots(int64_t n);
+hipError_t prune_sort_bytes(int64_t n, size_t *bytes);
+hipError_t launch_prune_order(const float *X, int64_t n, int d, const float *mu, void *sort_tmp,
+                              size_t sort_bytes, uint32_t *asg, uint32_t *asg_sorted,
+                              uint32_t *idx, uint32_t *perm, hipStream_t s);
+hipError_t launch_prune_rows(const ScreenGeom &g, const void *Qrows, const void *Prows,
+                             const double *nz, const uint32_t *perm, int64_t n, int64_t n_pad,
+                             int d, void *Qout, void *Pout, float *nzq, void *tile_c,
+                             float *tile_r, hipStream_t s);
+hipError_t launch_unpermute_cand(const uint64_t *cand, const float *tq, const uint32_t *perm,
+                                 int64_t n, int c, uint64_t *cand_out, float *tq_out,
+                                 hipStream_t s);
 
 // *dst += *src
 hipError_t launch_accum(const int32_t *src, unsigned long long *dst, hipStream_t s);

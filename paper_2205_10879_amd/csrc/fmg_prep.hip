@@ -17,15 +17,6 @@ namespace fmg {
 
 namespace {
 
-__device__ __forceinline__ uint16_t f32_to_bf16_rn(float f) {
-    uint32_t u = __float_as_uint(f);
-    uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(r >> 16);
-}
-__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
-    return __uint_as_float((uint32_t)h << 16);
-}
-
 // Column mean in two deterministic passes.  Pass 1: block b sums a fixed
 // chunk of rows; thread (rl, c) of the block adds rows rl, rl + RL, ... of
 // column c (RL = 256 / d row lanes, so a wavefront reads whole rows), and

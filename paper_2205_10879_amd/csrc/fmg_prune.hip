@@ -1,0 +1,213 @@
+// Tile pruning for the build's neighbour screen (Algorithm 2, the
+// training-point neighbour lookups): an order of the training points in which
+// 64-row candidate tiles are compact, and per tile a ball that bounds its
+// rows, so that the screen can skip tiles no query of a wave can take.
+//
+//   1. P pivots (evenly spaced training points) and the nearest pivot of
+//      every point (FP32 distances of the centred coordinates; any assignment
+//      is correct, a good one makes tiles compact);
+//   2. a stable sort by pivot (hipCUB radix sort over (pivot, index)), giving
+//      the permutation perm: position i of the screen holds point perm[i];
+//   3. the screening rows gathered into that order, with the query norms;
+//   4. per tile of 64 rows: the centroid of its BF16 rows, itself rounded to
+//      BF16 (so it is an exact point of the screened space) and written as a
+//      candidate row, and the FP64 radius max ||x~ - c~|| over the tile's real
+//      rows, rounded up;
+//   5. after the screen, candidate indices and rows mapped back to the
+//      original order, so that the re-rank and certificate run unchanged.
+#include <hipcub/hipcub.hpp>
+
+#include "fmg_device.h"
+#include "fmg_kernels.h"
+
+namespace fmg {
+
+namespace {
+
+__global__ __launch_bounds__(256) void pivot_assign_kernel(const float *__restrict__ X, int64_t n,
+                                                           int d, const float *__restrict__ mu,
+                                                           int P, int64_t stride,
+                                                           uint32_t *__restrict__ asg,
+                                                           uint32_t *__restrict__ idx) {
+    extern __shared__ float piv[];  // [P, 64] centred pivot coordinates, zero past d
+    for (int e = threadIdx.x; e < P * 64; e += blockDim.x) {
+        const int j = e / 64, c = e % 64;
+        piv[e] = c < d ? X[(int64_t)j * stride * d + c] - mu[c] : 0.0f;
+    }
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float x[64];
+#pragma unroll
+    for (int c = 0; c < 64; ++c) x[c] = c < d ? X[i * d + c] - mu[c] : 0.0f;
+    float best = INFINITY;
+    uint32_t bj = 0;
+    for (int j = 0; j < P; ++j) {
+        float s = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 64; ++c) {
+            if (c < d) {
+                const float t = x[c] - piv[j * 64 + c];
+                s = fmaf(t, t, s);
+            }
+        }
+        if (s < best) {
+            best = s;
+            bj = (uint32_t)j;
+        }
+    }
+    asg[i] = bj;
+    idx[i] = (uint32_t)i;
+}
+
+// Rows i < n come from point perm[i]; padding rows stay in place.
+__global__ __launch_bounds__(256) void gather_rows_kernel(const uint4 *__restrict__ Qrows,
+                                                          const uint4 *__restrict__ Prows,
+                                                          const double *__restrict__ nz,
+                                                          const uint32_t *__restrict__ perm,
+                                                          int64_t n, int64_t n_pad, int chunks,
+                                                          uint4 *__restrict__ Qout,
+                                                          uint4 *__restrict__ Pout,
+                                                          float *__restrict__ nzq) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_pad * chunks) return;
+    const int64_t i = e / chunks;
+    const int ch = (int)(e % chunks);
+    const int64_t src = i < n ? (int64_t)perm[i] : i;
+    Qout[i * chunks + ch] = Qrows[src * chunks + ch];
+    Pout[i * chunks + ch] = Prows[src * chunks + ch];
+    if (ch == 0) nzq[i] = i < n ? (float)nz[src] : 0.0f;
+}
+
+// One wave per tile of 64 BF16 candidate rows [-2 x~, norm parts, 0 ...].
+__global__ __launch_bounds__(64) void tile_bounds_kernel(const uint16_t *__restrict__ Prows,
+                                                         int64_t n, int d, int kp,
+                                                         uint16_t *__restrict__ cen,
+                                                         float *__restrict__ rad) {
+    const int64_t tile = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t row = tile * SCREEN_TILE + lane;
+    const bool real = row < n;
+    const uint16_t *pr = Prows + row * kp;
+    const int cnt = (int)__popcll(__ballot(real));
+    uint16_t *crow = cen + tile * kp;
+    if (cnt == 0) {  // padding only: never skipped
+        for (int c = lane; c < kp; c += 64) crow[c] = 0;
+        if (lane == 0) {
+            crow[d] = f32_to_bf16_rn(1.0e30f);
+            rad[tile] = INFINITY;
+        }
+        return;
+    }
+    // centroid of the rows' x~ = -(row) / 2 (exact), rounded to BF16
+    double r2 = 0.0, nc = 0.0;
+    for (int c = 0; c < d; ++c) {
+        const double x = real ? -0.5 * (double)bf16_to_f32(pr[c]) : 0.0;
+        const double m = wave_sum_f64(x) / cnt;
+        const uint16_t h = f32_to_bf16_rn((float)m);
+        const double ct = (double)bf16_to_f32(h);
+        const double t = x - ct;
+        if (real) r2 += t * t;
+        nc += ct * ct;
+        if (lane == 0) crow[c] = f32_to_bf16_rn(-2.0f * bf16_to_f32(h));  // exact scale
+    }
+    double mx = r2;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const double o = __shfl_xor(mx, w);
+        mx = o > mx ? o : mx;
+    }
+    if (lane == 0) {
+        const uint16_t hi = f32_to_bf16_rn((float)nc);
+        const double q1 = nc - (double)bf16_to_f32(hi);
+        const uint16_t mid = f32_to_bf16_rn((float)q1);
+        const double q2 = q1 - (double)bf16_to_f32(mid);
+        const uint16_t lo = f32_to_bf16_rn((float)q2);
+        for (int c = d; c < kp; ++c) crow[c] = (c == d) ? hi : (c == d + 1) ? mid : (c == d + 2) ? lo : 0;
+        rad[tile] = (float)(sqrt(mx) * (1.0 + 1.0e-6)) * (1.0f + 1.0e-6f);
+    }
+}
+
+// Screen output of permuted query row q' (candidate keys with permuted
+// indices) -> row perm[q'] with original indices.
+__global__ __launch_bounds__(256) void unpermute_cand_kernel(const uint64_t *__restrict__ cand,
+                                                             const float *__restrict__ tq,
+                                                             const uint32_t *__restrict__ perm,
+                                                             int64_t n, int c,
+                                                             uint64_t *__restrict__ cand_out,
+                                                             float *__restrict__ tq_out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * c) return;
+    const int64_t q = e / c;
+    const int s = (int)(e % c);
+    const int64_t o = perm[q];
+    const uint64_t key = cand[e];
+    const uint32_t p = (uint32_t)key;
+    const uint64_t mapped = (p < (uint64_t)n) ? ((key & 0xffffffff00000000ull) | perm[p]) : key;
+    cand_out[o * c + s] = mapped;
+    if (s == 0) tq_out[o] = tq[q];
+}
+
+}  // namespace
+
+int prune_pivots(int64_t n) {
+    const int64_t p = n / 2048;
+    return (int)(p < 1 ? 1 : (p > 256 ? 256 : p));
+}
+
+static int pivot_bits(int64_t n) {
+    int bits = 1;
+    while ((1 << bits) < prune_pivots(n)) ++bits;
+    return bits;
+}
+
+hipError_t prune_sort_bytes(int64_t n, size_t *bytes) {
+    *bytes = 0;
+    return hipcub::DeviceRadixSort::SortPairs(nullptr, *bytes, (const uint32_t *)nullptr,
+                                              (uint32_t *)nullptr, (const uint32_t *)nullptr,
+                                              (uint32_t *)nullptr, (int)n, 0, pivot_bits(n));
+}
+
+hipError_t launch_prune_order(const float *X, int64_t n, int d, const float *mu, void *sort_tmp,
+                              size_t sort_bytes, uint32_t *asg, uint32_t *asg_sorted,
+                              uint32_t *idx, uint32_t *perm, hipStream_t s) {
+    const int P = prune_pivots(n);
+    const int64_t stride = n / P;
+    if (d > 64) return hipErrorInvalidValue;
+    const size_t shm = (size_t)P * 64 * sizeof(float);
+    hipLaunchKernelGGL(pivot_assign_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), shm, s,
+                       X, n, d, mu, P, stride, asg, idx);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return hipcub::DeviceRadixSort::SortPairs(sort_tmp, sort_bytes, asg, asg_sorted, idx, perm,
+                                              (int)n, 0, pivot_bits(n), s);
+}
+
+hipError_t launch_prune_rows(const ScreenGeom &g, const void *Qrows, const void *Prows,
+                             const double *nz, const uint32_t *perm, int64_t n, int64_t n_pad,
+                             int d, void *Qout, void *Pout, float *nzq, void *tile_c,
+                             float *tile_r, hipStream_t s) {
+    if (g.mode != SCREEN_BF16 || g.row_bytes % 16 != 0) return hipErrorInvalidValue;
+    const int chunks = g.row_bytes / 16;
+    const int64_t items = n_pad * chunks;
+    hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s,
+                       (const uint4 *)Qrows, (const uint4 *)Prows, nz, perm, n, n_pad, chunks,
+                       (uint4 *)Qout, (uint4 *)Pout, nzq);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(tile_bounds_kernel, dim3((unsigned)(n_pad / SCREEN_TILE)), dim3(64), 0, s,
+                       (const uint16_t *)Pout, n, d, g.kp, (uint16_t *)tile_c, tile_r);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpermute_cand(const uint64_t *cand, const float *tq, const uint32_t *perm,
+                                 int64_t n, int c, uint64_t *cand_out, float *tq_out,
+                                 hipStream_t s) {
+    const int64_t items = n * (int64_t)c;
+    if (items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(unpermute_cand_kernel, dim3((unsigned)((items + 255) / 256)), dim3(256), 0,
+                       s, cand, tq, perm, n, c, cand_out, tq_out);
+    return hipGetLastError();
+}
+
+}  // namespace fmg

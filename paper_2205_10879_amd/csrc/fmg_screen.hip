@@ -204,7 +204,7 @@ __device__ __forceinline__ int select_pool(uint64_t *__restrict__ qpool, const i
     return base;
 }
 
-template <class Op, int KSTEPS, int CAP>
+template <class Op, int KSTEPS, int CAP, bool PRUNE>
 __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
     constexpr int RB = 4 * KSTEPS * Op::BPS;  // row bytes
     constexpr int CH = RB / 16;               // 16-byte chunks per row
@@ -230,6 +230,15 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
     const int split = blockIdx.y;
     const int cb = split * (int)a.col_chunk;
     const int ce = (cb + a.col_chunk < a.n_pad) ? cb + (int)a.col_chunk : (int)a.n_pad;
+    // Columns are visited at virtual positions v = 0, TILE, ... < len; with
+    // pruning the scan starts at this workgroup's own rows (the self-join's
+    // rows and columns share one order) and wraps around.
+    const int len = ce - cb;
+    const int rot = PRUNE ? (int)(((int64_t)blockIdx.x * SCREEN_QPB) % len) : 0;
+    auto phys = [&](int v) {
+        int p = cb + v + rot;
+        return p >= ce ? p - len : p;
+    };
     const int n_real = (int)a.n, m_real = (int)a.m;
     const char *__restrict__ Pb = (const char *)a.P;
     uint32_t *hist = hist_all[wave];
@@ -279,6 +288,73 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
         frag_off[s] = r16 * RB + (((byte >> 4) ^ (r16 & SWZ)) << 4) + (byte & 15);
     }
 
+    // Tile pruning.  Every 16 tiles the wave screens their centroid rows
+    // (8 MFMAs) and marks a tile skipped when for all of its 64 queries
+    //   (||z~ - c~|| - r)^2 - ||z~||^2 - A > threshold   (with a margin),
+    // where ||z~ - c~||^2 >= S'(c, z) + ||z~||^2 - A bounds the centroid
+    // distance from below, r bounds every row of the tile around c~ (triangle
+    // inequality), and A bounds the MFMA error of a screened value (centroid
+    // norms are within 1.02 of the largest row norm).  Every row of a skipped
+    // tile would therefore have screened above the threshold, which only
+    // decreases: the kept keys, and the certificate's premise that every
+    // non-candidate screened at or above T', are unchanged.
+    float nzq[4], aq[4];
+    uint32_t skip16 = 0;
+    if constexpr (PRUNE) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int q = wq0 + t * 16 + r16;
+            nzq[t] = (q < m_real) ? a.nzq[q] : 0.0f;
+            aq[t] = (float)(a.acc_coef * (2.01 * 1.02 * a.nx_max + (double)nzq[t]) +
+                            1.0e-6 * 1.02 * a.nx_max);
+        }
+    }
+    auto prune_mask = [&](int v0) -> uint32_t {
+        // centroid row r16 of the group belongs to the tile at v0 + r16 * TILE
+        const int vr = v0 + r16 * TILE;
+        typename Op::frag_t af[KSTEPS];
+        const char *crow = (const char *)a.tile_c + (int64_t)(phys(vr < len ? vr : 0) / TILE) * RB;
+#pragma unroll
+        for (int s = 0; s < KSTEPS; ++s) af[s] = Op::load(crow + g * KSTEPS * Op::BPS + s * Op::BPS);
+        f32x4 ac[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            ac[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < KSTEPS; ++s) ac[t] = Op::mfma(af[s], bq[t][s], ac[t]);
+        }
+        // this lane holds centroid rows 4g + i of the group
+        float rad[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int vj = v0 + (4 * g + i) * TILE;
+            rad[i] = vj < len ? a.tile_r[phys(vj) / TILE] : INFINITY;
+        }
+        uint32_t skip = 0xffffu;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                bool pr;
+                if (thr[t] == -INFINITY) {
+                    pr = true;  // padding query
+                } else {
+                    const float L = ac[t][i] + nzq[t] - aq[t];
+                    const float dl = (L > 0.0f) ? sqrtf(L) - rad[i] : -1.0f;
+                    const float d2 = dl * dl;
+                    pr = dl > 0.0f &&
+                         d2 - nzq[t] - aq[t] - 1.0e-5f * (d2 + nzq[t]) - (float)(1.0e-6 * a.nx_max) >
+                             thr[t];
+                }
+                const uint64_t m = __ballot(pr);
+#pragma unroll
+                for (int gg = 0; gg < 4; ++gg)
+                    if (((m >> (16 * gg)) & 0xffffull) != 0xffffull) skip &= ~(1u << (4 * gg + i));
+            }
+        }
+        return skip;
+    };
+
     // Counts of the four sub-pools of wave query (t, rl).
     auto counts = [&](int t, int rl, int (&cg)[4]) {
         const int ct = t == 0 ? cnt[0] : t == 1 ? cnt[1] : t == 2 ? cnt[2] : cnt[3];
@@ -317,7 +393,10 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
     };
 
     // MFMA screen of one tile and candidate selection.
-    auto screen_tile = [&](int col, const char *cur) {
+    auto screen_tile = [&](int col, const char *cur, int j16) {
+        if constexpr (PRUNE) {
+            if ((skip16 >> j16) & 1u) return;
+        }
         f32x4 acc[4][4];
 #pragma unroll
         for (int t = 0; t < 4; ++t)
@@ -377,13 +456,17 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
     // while this period's tiles in `cur` are screened (a period of compute
     // covers the load latency); then pool maintenance and one workgroup
     // barrier.
-    auto period = [&](int col, char (*cur)[TILE * RB], char (*nxt)[TILE * RB]) {
+    auto period = [&](int v, char (*cur)[TILE * RB], char (*nxt)[TILE * RB]) {
 #pragma unroll
         for (int j = 0; j < TPB; ++j)
-            if (col + (TPB + j) * TILE < ce) load_tile(col + (TPB + j) * TILE, nxt[j]);
+            if (v + (TPB + j) * TILE < len) load_tile(phys(v + (TPB + j) * TILE), nxt[j]);
+        if constexpr (PRUNE) {
+            if ((v & (16 * TILE - 1)) == 0) skip16 = prune_mask(v);
+        }
 #pragma unroll 1
         for (int j = 0; j < TPB; ++j)
-            if (col + j * TILE < ce) screen_tile(col + j * TILE, cur[j]);
+            if (v + j * TILE < len)
+                screen_tile(phys(v + j * TILE), cur[j], ((v >> 6) + j) & 15);
         if (__ballot(cnt[0] > TRIG || cnt[1] > TRIG || cnt[2] > TRIG || cnt[3] > TRIG) != 0)
             flush_full();
         // the next period's tiles must have landed in LDS before any wave reads them
@@ -393,12 +476,12 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
 
 #pragma unroll
     for (int j = 0; j < TPB; ++j)
-        if (cb + j * TILE < ce) load_tile(cb + j * TILE, ringA[j]);
+        if (j * TILE < len) load_tile(phys(j * TILE), ringA[j]);
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    for (int col = cb; col < ce; col += 2 * TPB * TILE) {
-        period(col, ringA, ringB);
-        if (col + TPB * TILE < ce) period(col + TPB * TILE, ringB, ringA);
+    for (int v = 0; v < len; v += 2 * TPB * TILE) {
+        period(v, ringA, ringB);
+        if (v + TPB * TILE < len) period(v + TPB * TILE, ringB, ringA);
     }
 
     // Final selection, sort and output of every real query of this wave.
@@ -438,11 +521,18 @@ hipError_t launch_screen(const ScreenGeom &g, const ScreenArgs &a, hipStream_t s
     dim3 grid((unsigned)(a.m_pad / SCREEN_QPB), (unsigned)a.splits);
     if (a.c < 1 || a.c > SCREEN_CMAX) return hipErrorInvalidValue;
 #define FMG_SCREEN_LAUNCH(OP, KS) \
-    hipLaunchKernelGGL((screen_kernel<OP, KS, SCREEN_CAP>), grid, dim3(256), 0, s, a)
+    hipLaunchKernelGGL((screen_kernel<OP, KS, SCREEN_CAP, false>), grid, dim3(256), 0, s, a)
     if (g.mode == SCREEN_BF16) {
         if (g.ksteps != 2) return hipErrorInvalidValue;
-        FMG_SCREEN_LAUNCH(OpBF16, 2);
+        if (a.prune) {
+            if (a.splits != 1 || !a.tile_c || !a.tile_r || !a.nzq) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((screen_kernel<OpBF16, 2, SCREEN_CAP, true>), grid, dim3(256), 0, s,
+                               a);
+        } else {
+            FMG_SCREEN_LAUNCH(OpBF16, 2);
+        }
     } else {
+        if (a.prune) return hipErrorInvalidValue;
         switch (g.ksteps) {
         case 4: FMG_SCREEN_LAUNCH(OpF32, 4); break;
         case 8: FMG_SCREEN_LAUNCH(OpF32, 8); break;
