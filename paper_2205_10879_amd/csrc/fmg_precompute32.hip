@@ -17,11 +17,13 @@
 //      one v_readlane and one FMA per right-hand side: the unit diagonal
 //      leaves nothing to scale inside the loop.
 //   4. MIXED only: one refinement step.  The rows, centred on x_i, are exact
-//      in FP64; their Gram matrix on FP64 MFMA (v_mfma_f64_16x16x4f64) gives
-//      FP64 distances and kernel values, a second FP64 MFMA product gives
-//      r = Y_N - (K64 + sigma^2 I) C, and C += solve(U D U^T, r).
-// U is kept in LDS packed by rows.  LDS per wavefront is about 15 KB (FP32)
-// or 27 KB (MIXED) for d = 40, k = 50, ell = 10.
+//      in FP64 (each operand is formed as (double) x_b - (double) x_i from the
+//      raw FP32 rows staged in LDS); their Gram matrix on FP64 MFMA
+//      (v_mfma_f64_16x16x4f64) gives FP64 distances and kernel values, a
+//      second FP64 MFMA product gives r = Y_N - (K64 + sigma^2 I) C, and
+//      C += solve(U D U^T, r).
+// U is kept in LDS packed by rows.  LDS per wavefront is about 14 KB (FP32)
+// or 17 KB (MIXED) for d = 40, k = 50, ell = 10, so eight wavefronts fit a CU.
 // A non-positive or non-finite pivot marks the point: its C row is NaN and
 // its status is 1.
 #include "fmg_device.h"
@@ -45,16 +47,11 @@ __device__ __forceinline__ void lds_sync() {
 // over the LDS banks).
 __host__ __device__ __forceinline__ int xs_stride(int d) { return ((d + 3) / 4) * 4 + 1; }
 
-// Row stride (doubles) of the FP64 rows used by the refinement: d rounded up
-// to the MFMA k-step, plus one.
-__host__ __device__ __forceinline__ int x64_stride(int d) { return ((d + 3) / 4) * 4 + 1; }
-
 // LDS layout (bytes), one wavefront per block.
 struct PcLayout {
     int xs_ld;      // floats per staged FP32 row
-    int x64_ld;     // doubles per staged FP64 row (refinement)
     int g_ld;       // floats per Gram column (column-major, 32 columns at a time)
-    int off_r1;     // staged rows, then Gram halves, then FP64 rows
+    int off_r1;     // staged rows, then Gram halves, then the refinement's raw rows
     int off_l;      // U, strictly lower part packed by rows (row a at a(a-1)/2)
     int off_bc;     // column broadcast [64] floats; with refinement the
                     // coefficients [64][ELLMAX] floats
@@ -72,11 +69,10 @@ __host__ __device__ __forceinline__ PcLayout pc_layout(int k, int d, int kmax, i
                                                        bool refine) {
     PcLayout L;
     L.xs_ld = xs_stride(d);
-    L.x64_ld = x64_stride(d);
     L.g_ld = kmax + 4;
-    // The FP64 rows (refinement) reuse the staging space; K64 C reuses
-    // theirs once the product is done.
-    const int r64 = refine ? imax3(k * L.x64_ld * 8, 64 * ellmax * 8, 0) : 0;
+    // The refinement's raw rows and centre reuse the staging space; K64 C
+    // reuses theirs once the product is done.
+    const int r64 = refine ? imax3(k * L.xs_ld * 4 + 64 * 4, 64 * ellmax * 8, 0) : 0;
     const int r1 = imax3(k * L.xs_ld * 4, 32 * L.g_ld * 4, r64);
     L.off_r1 = 0;
     L.off_l = (r1 + 15) & ~15;
@@ -114,14 +110,20 @@ __device__ __forceinline__ void stage_rows(const float *__restrict__ X, int d, i
     }
 }
 
-// The same rows exactly in FP64 (refinement); returns |x_a - x_i|^2.
-__device__ __forceinline__ double stage_rows64(const float *__restrict__ X, int d, int k,
-                                               const float *__restrict__ xi, int64_t p,
-                                               double *__restrict__ x64, int ld, int a) {
+// The refinement's rows: the raw FP32 coordinates of rows N(i)_b staged in
+// xr[b][0..d) (zero padded to a multiple of 4) and the centre in xc[0..64)
+// (zero past d), so that every FP64 MFMA operand is formed as the exact
+// difference (double) x_b - (double) x_i when it is loaded.  Returns
+// |x_a - x_i|^2 in FP64 for lane a's row.
+__device__ __forceinline__ double stage_rows_raw(const float *__restrict__ X, int d, int k,
+                                                 const float *__restrict__ xi, int64_t p,
+                                                 float *__restrict__ xr, int ld,
+                                                 float *__restrict__ xc, int a) {
+    xc[a] = a < d ? xi[a] : 0.0f;
     const float *__restrict__ xp = X + p * d;
     double n64 = 0.0;
     if (a >= k) return n64;
-    double *row = x64 + a * ld;
+    float *row = xr + a * ld;
     if ((d & 3) == 0 && (((uintptr_t)X | (uintptr_t)xi) & 15) == 0) {
 #pragma unroll 4
         for (int c = 0; c < d; c += 4) {
@@ -129,10 +131,10 @@ __device__ __forceinline__ double stage_rows64(const float *__restrict__ X, int 
             const float4 v = *(const float4 *)(xi + c);
             const double e0 = (double)u.x - (double)v.x, e1 = (double)u.y - (double)v.y;
             const double e2 = (double)u.z - (double)v.z, e3 = (double)u.w - (double)v.w;
-            row[c] = e0;
-            row[c + 1] = e1;
-            row[c + 2] = e2;
-            row[c + 3] = e3;
+            row[c] = u.x;
+            row[c + 1] = u.y;
+            row[c + 2] = u.z;
+            row[c + 3] = u.w;
             n64 = fma(e0, e0, n64);
             n64 = fma(e1, e1, n64);
             n64 = fma(e2, e2, n64);
@@ -142,10 +144,10 @@ __device__ __forceinline__ double stage_rows64(const float *__restrict__ X, int 
 #pragma unroll 4
         for (int c = 0; c < d; ++c) {
             const double e = (double)xp[c] - (double)xi[c];
-            row[c] = e;
+            row[c] = xp[c];
             n64 = fma(e, e, n64);
         }
-        for (int c = d; c < ((d + 3) & ~3); ++c) row[c] = 0.0;
+        for (int c = d; c < ((d + 3) & ~3); ++c) row[c] = 0.0f;
     }
     return n64;
 }
@@ -249,7 +251,6 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
     const PcLayout L = pc_layout(k, d, KMAX, ELLMAX, REFINE);
     float *xs = (float *)(smem + L.off_r1);
     float *G = (float *)(smem + L.off_r1);
-    double *x64 = (double *)(smem + L.off_r1);
     float *U = (float *)(smem + L.off_l);
     float *bc = (float *)(smem + L.off_bc);
     float *nrm = (float *)(smem + L.off_nrm);
@@ -370,9 +371,11 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
         // lane l holds entries (4g + l/16, l%16), g = 0..3, of a tile, which
         // (K being symmetric) is exactly the A operand of the product for
         // the transposed tile, so K never leaves registers.
-        const int ld = L.x64_ld, d4 = (d + 3) & ~3;
+        const int ld = L.xs_ld, d4 = (d + 3) & ~3;
+        float *xr = (float *)(smem + L.off_r1);
+        float *xc = xr + k * ld;
         lds_sync();  // the Gram staging area is dead
-        nrm64[a] = stage_rows64(X, d, k, xi, p, x64, ld, a);
+        nrm64[a] = stage_rows_raw(X, d, k, xi, p, xr, ld, xc, a);
         float *cb = bc;  // [64][ELLMAX] current coefficients, zero past k / ell
 #pragma unroll
         for (int c = 0; c < ELLMAX; ++c) cb[a * ELLMAX + c] = (a < k && c < ell) ? y[c] : 0.0f;
@@ -389,10 +392,11 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
             if (ct * 16 < k) {
                 for (int s = 0; s < d4; s += 4) {
                     double f[NT];
+                    const double cc = (double)xc[s + fk];
 #pragma unroll
                     for (int r = 0; r < NT; ++r) {
                         const int row = r * 16 + fr;
-                        f[r] = (row < k) ? x64[row * ld + s + fk] : 0.0;
+                        f[r] = (row < k) ? (double)xr[row * ld + s + fk] - cc : 0.0;
                     }
 #pragma unroll
                     for (int r = 0; r < NT; ++r)
@@ -418,8 +422,8 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
             }
             R[ct] = acc64;
         }
-        lds_sync();  // the FP64 rows are dead; their space takes K64 C
-        double *KC = x64;  // [64][ELLMAX]
+        lds_sync();  // the raw rows are dead; their space takes K64 C
+        double *KC = (double *)(smem + L.off_r1);  // [64][ELLMAX]
         if (fr < ell) {
 #pragma unroll
             for (int ct = 0; ct < NT; ++ct)
