@@ -73,7 +73,8 @@ namespace {
 
 void free_model(fmg_model *M) {
     if (!M) return;
-    void *ptrs[] = {M->X, M->N, M->C, M->Xp, M->mu, M->Y, M->pred_fb};
+    void *ptrs[] = {M->X,      M->N,      M->C,      M->Xp,     M->mu, M->Y,
+                    M->pred_fb, M->perm, M->Xpp, M->tile_c, M->tile_r, M->cell};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     for (void *h : M->host)
@@ -117,6 +118,11 @@ void **model_array(fmg_model *M, int idx) {
     case MA_C: return &M->C;
     case MA_XP: return &M->Xp;
     case MA_Y: return &M->Y;
+    case MA_PERM: return (void **)&M->perm;
+    case MA_XPP: return &M->Xpp;
+    case MA_TC: return &M->tile_c;
+    case MA_TR: return (void **)&M->tile_r;
+    case MA_CELL: return (void **)&M->cell;
     default: return (void **)&M->mu;
     }
 }
@@ -283,7 +289,10 @@ fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_
     } else {
         const ScreenGeom &g = M->geom;
         const int64_t m_pad = round_up(m, SCREEN_QPB);
-        int64_t splits = predict_splits(M, m_pad, ws);
+        // Large direct batches on a model with a pivot order take the pruned
+        // screen: queries sorted by nearest pivot, one column range.
+        const bool prune = !ws && M->perm && m >= PREDICT_PRUNE_MIN;
+        int64_t splits = prune ? 1 : predict_splits(M, m_pad, ws);
         int64_t chunk = round_up((M->n_pad + splits - 1) / splits, SCREEN_TILE);
         splits = (M->n_pad + chunk - 1) / chunk;
         const int c = M->c_query;
@@ -331,7 +340,46 @@ fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_
         sa.pool = pool;
         sa.cand = cand;
         sa.tq = tq;
+        uint32_t *qperm = nullptr;
+        uint64_t *cand_p = nullptr;
+        float *tq_p = nullptr;
+        if (prune) {
+            uint32_t *asg = nullptr, *asg2 = nullptr, *idx = nullptr;
+            void *sort_tmp = nullptr, *Zq2 = nullptr;
+            float *nzq = nullptr;
+            int32_t *rot = nullptr;
+            size_t sort_bytes = 0;
+            HIPCHK(prune_query_sort_bytes(M->n, m, &sort_bytes), "sort size");
+            HIPCHK(tmp.alloc((void **)&qperm, (size_t)m * 4), "scratch");
+            HIPCHK(tmp.alloc((void **)&asg, (size_t)m * 4), "scratch");
+            HIPCHK(tmp.alloc((void **)&asg2, (size_t)m * 4), "scratch");
+            HIPCHK(tmp.alloc((void **)&idx, (size_t)m * 4), "scratch");
+            HIPCHK(tmp.alloc(&sort_tmp, sort_bytes), "scratch");
+            HIPCHK(tmp.alloc(&Zq2, (size_t)m_pad * g.row_bytes), "scratch");
+            HIPCHK(tmp.alloc((void **)&nzq, (size_t)m_pad * 4), "scratch");
+            HIPCHK(tmp.alloc((void **)&rot, (size_t)(m_pad / SCREEN_QPB) * 4), "scratch");
+            HIPCHK(tmp.alloc((void **)&cand_p, (size_t)m * c * 8), "scratch");
+            HIPCHK(tmp.alloc((void **)&tq_p, (size_t)m * 4), "scratch");
+            HIPCHK(launch_prune_queries((const float *)M->X, M->n, (const float *)Z, m, M->d, M->mu,
+                                        sort_tmp, sort_bytes, asg, asg2, idx, qperm, g, Zq, nzz,
+                                        m_pad, Zq2, nzq, M->cell, rot, s),
+                   "query order");
+            sa.Q = Zq2;
+            sa.P = M->Xpp;
+            sa.cand = cand_p;
+            sa.tq = tq_p;
+            sa.prune = 1;
+            sa.tile_c = M->tile_c;
+            sa.tile_r = M->tile_r;
+            sa.nzq = nzq;
+            sa.acc_coef = M->acc_coef;
+            sa.nx_max = M->nx_max;
+            sa.rot_tab = rot;
+        }
         HIPCHK(launch_screen(g, sa, s), "screen");
+        if (prune)
+            HIPCHK(launch_unpermute_cand(cand_p, tq_p, qperm, M->perm, m, M->n, c, cand, tq, s),
+                   "unpermute");
         record(M, M->evp, EV_SCREEN, s);
         RerankArgs ra{};
         ra.cand = cand;
@@ -669,41 +717,47 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
         float *tq_p = nullptr;
         if (prune) {
             uint32_t *asg = nullptr, *asg2 = nullptr, *idx = nullptr;
-            void *sort_tmp = nullptr, *Xq2 = nullptr, *Xp2 = nullptr, *tile_c = nullptr;
-            float *tile_r = nullptr, *nzq = nullptr;
+            void *sort_tmp = nullptr, *Xq2 = nullptr;
+            float *nzq = nullptr;
             size_t sort_bytes = 0;
+            const int npiv = prune_pivots(n);
+            const size_t tiles = (size_t)(n_pad / SCREEN_TILE);
             HCHK(prune_sort_bytes(n, &sort_bytes), "sort size");
-            HCHK(tmp.alloc((void **)&perm, (size_t)n * 4), "scratch");
+            MCHK(model_alloc(M, MA_PERM, (void **)&M->perm, (size_t)n * 4, "model order"));
+            MCHK(model_alloc(M, MA_XPP, &M->Xpp, (size_t)n_pad * geom.row_bytes, "model rows"));
+            MCHK(model_alloc(M, MA_TC, &M->tile_c, tiles * geom.row_bytes, "model tiles"));
+            MCHK(model_alloc(M, MA_TR, (void **)&M->tile_r, tiles * 4, "model tiles"));
+            MCHK(model_alloc(M, MA_CELL, (void **)&M->cell, (size_t)(npiv + 1) * 4, "model cells"));
+            perm = M->perm;
             HCHK(tmp.alloc((void **)&asg, (size_t)n * 4), "scratch");
             HCHK(tmp.alloc((void **)&asg2, (size_t)n * 4), "scratch");
             HCHK(tmp.alloc((void **)&idx, (size_t)n * 4), "scratch");
             HCHK(tmp.alloc(&sort_tmp, sort_bytes), "scratch");
             HCHK(tmp.alloc(&Xq2, (size_t)n_pad * geom.row_bytes), "scratch");
-            HCHK(tmp.alloc(&Xp2, (size_t)n_pad * geom.row_bytes), "scratch");
-            HCHK(tmp.alloc(&tile_c, (size_t)(n_pad / SCREEN_TILE) * geom.row_bytes), "scratch");
-            HCHK(tmp.alloc((void **)&tile_r, (size_t)(n_pad / SCREEN_TILE) * 4), "scratch");
             HCHK(tmp.alloc((void **)&nzq, (size_t)n_pad * 4), "scratch");
             HCHK(tmp.alloc((void **)&cand_p, (size_t)n * c * 8), "scratch");
             HCHK(tmp.alloc((void **)&tq_p, (size_t)n * 4), "scratch");
             HCHK(launch_prune_order((const float *)M->X, n, d, M->mu, sort_tmp, sort_bytes, asg,
                                     asg2, idx, perm, s),
                  "pivot order");
-            HCHK(launch_prune_rows(geom, Xq, M->Xp, nzx, perm, n, n_pad, d, Xq2, Xp2, nzq, tile_c,
-                                   tile_r, s),
+            HCHK(launch_cell_starts(asg2, n, npiv, M->cell, s), "cell starts");
+            HCHK(launch_prune_rows(geom, Xq, M->Xp, nzx, perm, n, n_pad, d, Xq2, M->Xpp, nzq,
+                                   M->tile_c, M->tile_r, s),
                  "pruning rows");
             sa.Q = Xq2;
-            sa.P = Xp2;
+            sa.P = M->Xpp;
             sa.cand = cand_p;
             sa.tq = tq_p;
             sa.prune = 1;
-            sa.tile_c = tile_c;
-            sa.tile_r = tile_r;
+            sa.tile_c = M->tile_c;
+            sa.tile_r = M->tile_r;
             sa.nzq = nzq;
             sa.acc_coef = M->acc_coef;
             sa.nx_max = M->nx_max;
         }
         HCHK(launch_screen(geom, sa, s), "screen");
-        if (prune) HCHK(launch_unpermute_cand(cand_p, tq_p, perm, n, c, cand, tq, s), "unpermute");
+        if (prune)
+            HCHK(launch_unpermute_cand(cand_p, tq_p, perm, perm, n, n, c, cand, tq, s), "unpermute");
         record(M, M->evb, EV_SCREEN, s);
         RerankArgs ra{};
         ra.cand = cand;

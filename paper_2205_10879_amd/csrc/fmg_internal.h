@@ -16,7 +16,7 @@ enum { EV_START = 0, EV_PREP, EV_SCREEN, EV_RERANK, EV_FALLBACK, EV_LAST, EV_COU
 
 // Device arrays of a model, in the order they are moved between device and
 // host memory by model_offload / model_restore.
-enum { MA_X = 0, MA_N, MA_C, MA_XP, MA_MU, MA_Y, MA_COUNT };
+enum { MA_X = 0, MA_N, MA_C, MA_XP, MA_MU, MA_Y, MA_PERM, MA_XPP, MA_TC, MA_TR, MA_CELL, MA_COUNT };
 
 }  // namespace fmg
 
@@ -40,6 +40,14 @@ struct fmg_model {
     int64_t n_pad = 0;
     void *Xp = nullptr;   // [n_pad, kp] candidate-side screening rows
     float *mu = nullptr;  // [d]
+    // Tile pruning (MIXED): the pivot order of the training points
+    // (perm[position] = point), the candidate rows in that order, per-tile
+    // centroid rows and radii, and the first position of each pivot's cell.
+    uint32_t *perm = nullptr;  // [n]
+    void *Xpp = nullptr;       // [n_pad, kp]
+    void *tile_c = nullptr;    // [n_pad / 64, kp]
+    float *tile_r = nullptr;   // [n_pad / 64]
+    int32_t *cell = nullptr;   // [pivots + 1]
     double e_max = 0.0, nx_max = 0.0, acc_coef = 0.0;
     int c_build = 0, c_query = 0;
     int64_t nonpd = 0, build_fb = 0;
@@ -78,6 +86,10 @@ struct PredictWs {
 };
 
 constexpr int PREDICT_MAX_SPLITS = 32;
+// Direct predictions of at least this many queries on a model with a pivot
+// order use the pruned screen (enough workgroups to fill the device from one
+// column range).
+constexpr int64_t PREDICT_PRUNE_MIN = 65536;
 
 fmg_status set_error(fmg_status st, const char *fmt, ...);
 // Bytes of a workspace for max_m queries.

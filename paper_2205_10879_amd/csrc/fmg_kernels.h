@@ -51,6 +51,9 @@ struct ScreenArgs {
     const float *tile_r; // [n_pad / SCREEN_TILE]
     const float *nzq;    // [m_pad] ||z~||^2 of the query rows
     double acc_coef, nx_max;
+    // Optional start column of each workgroup (a multiple of SCREEN_TILE);
+    // without it a pruned self-join starts at the workgroup's own rows.
+    const int32_t *rot_tab;
 };
 
 struct RerankArgs {
@@ -205,9 +208,23 @@ hipError_t launch_prune_rows(const ScreenGeom &g, const void *Qrows, const void 
                              const double *nz, const uint32_t *perm, int64_t n, int64_t n_pad,
                              int d, void *Qout, void *Pout, float *nzq, void *tile_c,
                              float *tile_r, hipStream_t s);
-hipError_t launch_unpermute_cand(const uint64_t *cand, const float *tq, const uint32_t *perm,
-                                 int64_t n, int c, uint64_t *cand_out, float *tq_out,
-                                 hipStream_t s);
+hipError_t launch_unpermute_cand(const uint64_t *cand, const float *tq, const uint32_t *qperm,
+                                 const uint32_t *cperm, int64_t m, int64_t n, int c,
+                                 uint64_t *cand_out, float *tq_out, hipStream_t s);
+// cell[j], j <= P: first position of pivot j in the pivot order.
+hipError_t launch_cell_starts(const uint32_t *asg_sorted, int64_t n, int P, int32_t *cell,
+                              hipStream_t s);
+// Queries of a prediction in pivot order: their nearest pivots (the model's),
+// the stable sort (qperm: position -> query), the query rows and norms
+// gathered into that order, and each workgroup's start column (the cell of
+// its first query's pivot).
+hipError_t prune_query_sort_bytes(int64_t n, int64_t m, size_t *bytes);
+hipError_t launch_prune_queries(const float *X, int64_t n, const float *Z, int64_t m, int d,
+                                const float *mu, void *sort_tmp, size_t sort_bytes,
+                                uint32_t *asg, uint32_t *asg_sorted, uint32_t *idx,
+                                uint32_t *qperm, const ScreenGeom &g, const void *Zq,
+                                const double *nzz, int64_t m_pad, void *Zq_out, float *nzq,
+                                const int32_t *cell, int32_t *rot, hipStream_t s);
 
 // *dst += *src
 hipError_t launch_accum(const int32_t *src, unsigned long long *dst, hipStream_t s);

@@ -24,9 +24,12 @@ namespace fmg {
 
 namespace {
 
-__global__ __launch_bounds__(256) void pivot_assign_kernel(const float *__restrict__ X, int64_t n,
-                                                           int d, const float *__restrict__ mu,
-                                                           int P, int64_t stride,
+// Nearest pivot of points Pts [n, d]; pivot j is training row j * stride of X.
+__global__ __launch_bounds__(256) void pivot_assign_kernel(const float *__restrict__ X,
+                                                           const float *__restrict__ Pts,
+                                                           int64_t n, int d,
+                                                           const float *__restrict__ mu, int P,
+                                                           int64_t stride,
                                                            uint32_t *__restrict__ asg,
                                                            uint32_t *__restrict__ idx) {
     extern __shared__ float piv[];  // [P, 64] centred pivot coordinates, zero past d
@@ -39,7 +42,7 @@ __global__ __launch_bounds__(256) void pivot_assign_kernel(const float *__restri
     if (i >= n) return;
     float x[64];
 #pragma unroll
-    for (int c = 0; c < 64; ++c) x[c] = c < d ? X[i * d + c] - mu[c] : 0.0f;
+    for (int c = 0; c < 64; ++c) x[c] = c < d ? Pts[i * d + c] - mu[c] : 0.0f;
     float best = INFINITY;
     uint32_t bj = 0;
     for (int j = 0; j < P; ++j) {
@@ -75,7 +78,7 @@ __global__ __launch_bounds__(256) void gather_rows_kernel(const uint4 *__restric
     const int ch = (int)(e % chunks);
     const int64_t src = i < n ? (int64_t)perm[i] : i;
     Qout[i * chunks + ch] = Qrows[src * chunks + ch];
-    Pout[i * chunks + ch] = Prows[src * chunks + ch];
+    if (Pout) Pout[i * chunks + ch] = Prows[src * chunks + ch];
     if (ch == 0) nzq[i] = i < n ? (float)nz[src] : 0.0f;
 }
 
@@ -132,20 +135,48 @@ __global__ __launch_bounds__(64) void tile_bounds_kernel(const uint16_t *__restr
 // indices) -> row perm[q'] with original indices.
 __global__ __launch_bounds__(256) void unpermute_cand_kernel(const uint64_t *__restrict__ cand,
                                                              const float *__restrict__ tq,
-                                                             const uint32_t *__restrict__ perm,
-                                                             int64_t n, int c,
+                                                             const uint32_t *__restrict__ qperm,
+                                                             const uint32_t *__restrict__ cperm,
+                                                             int64_t m, int64_t n, int c,
                                                              uint64_t *__restrict__ cand_out,
                                                              float *__restrict__ tq_out) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n * c) return;
+    if (e >= m * c) return;
     const int64_t q = e / c;
     const int s = (int)(e % c);
-    const int64_t o = perm[q];
+    const int64_t o = qperm[q];
     const uint64_t key = cand[e];
     const uint32_t p = (uint32_t)key;
-    const uint64_t mapped = (p < (uint64_t)n) ? ((key & 0xffffffff00000000ull) | perm[p]) : key;
+    const uint64_t mapped = (p < (uint64_t)n) ? ((key & 0xffffffff00000000ull) | cperm[p]) : key;
     cand_out[o * c + s] = mapped;
     if (s == 0) tq_out[o] = tq[q];
+}
+
+// cell[j] = first position of pivot j in the sorted assignment (j <= P).
+__global__ __launch_bounds__(256) void cell_start_kernel(const uint32_t *__restrict__ asg_sorted,
+                                                         int64_t n, int P,
+                                                         int32_t *__restrict__ cell) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > P) return;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if (asg_sorted[mid] < (uint32_t)j) lo = mid + 1;
+        else hi = mid;
+    }
+    cell[j] = (int32_t)lo;
+}
+
+// Start column of query block b: the cell of the block's first query's pivot,
+// rounded down to a tile.
+__global__ __launch_bounds__(256) void block_start_kernel(const uint32_t *__restrict__ qasg_sorted,
+                                                          int64_t m, int64_t blocks,
+                                                          const int32_t *__restrict__ cell,
+                                                          int32_t *__restrict__ rot) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= blocks) return;
+    const int64_t q = b * SCREEN_QPB < m ? b * SCREEN_QPB : m - 1;
+    rot[b] = cell[qasg_sorted[q]] & ~(SCREEN_TILE - 1);
 }
 
 }  // namespace
@@ -176,7 +207,7 @@ hipError_t launch_prune_order(const float *X, int64_t n, int d, const float *mu,
     if (d > 64) return hipErrorInvalidValue;
     const size_t shm = (size_t)P * 64 * sizeof(float);
     hipLaunchKernelGGL(pivot_assign_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), shm, s,
-                       X, n, d, mu, P, stride, asg, idx);
+                       X, X, n, d, mu, P, stride, asg, idx);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return hipcub::DeviceRadixSort::SortPairs(sort_tmp, sort_bytes, asg, asg_sorted, idx, perm,
@@ -200,14 +231,56 @@ hipError_t launch_prune_rows(const ScreenGeom &g, const void *Qrows, const void 
     return hipGetLastError();
 }
 
-hipError_t launch_unpermute_cand(const uint64_t *cand, const float *tq, const uint32_t *perm,
-                                 int64_t n, int c, uint64_t *cand_out, float *tq_out,
-                                 hipStream_t s) {
-    const int64_t items = n * (int64_t)c;
+hipError_t launch_unpermute_cand(const uint64_t *cand, const float *tq, const uint32_t *qperm,
+                                 const uint32_t *cperm, int64_t m, int64_t n, int c,
+                                 uint64_t *cand_out, float *tq_out, hipStream_t s) {
+    const int64_t items = m * (int64_t)c;
     if (items <= 0) return hipSuccess;
     hipLaunchKernelGGL(unpermute_cand_kernel, dim3((unsigned)((items + 255) / 256)), dim3(256), 0,
-                       s, cand, tq, perm, n, c, cand_out, tq_out);
+                       s, cand, tq, qperm, cperm, m, n, c, cand_out, tq_out);
     return hipGetLastError();
+}
+
+hipError_t launch_cell_starts(const uint32_t *asg_sorted, int64_t n, int P, int32_t *cell,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(cell_start_kernel, dim3((unsigned)((P + 1 + 255) / 256)), dim3(256), 0, s,
+                       asg_sorted, n, P, cell);
+    return hipGetLastError();
+}
+
+hipError_t launch_prune_queries(const float *X, int64_t n, const float *Z, int64_t m, int d,
+                                const float *mu, void *sort_tmp, size_t sort_bytes,
+                                uint32_t *asg, uint32_t *asg_sorted, uint32_t *idx,
+                                uint32_t *qperm, const ScreenGeom &g, const void *Zq,
+                                const double *nzz, int64_t m_pad, void *Zq_out, float *nzq,
+                                const int32_t *cell, int32_t *rot, hipStream_t s) {
+    if (d > 64 || g.mode != SCREEN_BF16 || g.row_bytes % 16 != 0) return hipErrorInvalidValue;
+    const int P = prune_pivots(n);
+    const int64_t stride = n / P;
+    const size_t shm = (size_t)P * 64 * sizeof(float);
+    hipLaunchKernelGGL(pivot_assign_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), shm, s,
+                       X, Z, m, d, mu, P, stride, asg, idx);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipcub::DeviceRadixSort::SortPairs(sort_tmp, sort_bytes, asg, asg_sorted, idx, qperm,
+                                           (int)m, 0, pivot_bits(n), s);
+    if (e != hipSuccess) return e;
+    const int chunks = g.row_bytes / 16;
+    const int64_t items = m_pad * chunks;
+    hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s,
+                       (const uint4 *)Zq, (const uint4 *)nullptr, nzz, qperm, m, m_pad, chunks,
+                       (uint4 *)Zq_out, (uint4 *)nullptr, nzq);
+    const int64_t blocks = m_pad / SCREEN_QPB;
+    hipLaunchKernelGGL(block_start_kernel, dim3((unsigned)((blocks + 255) / 256)), dim3(256), 0, s,
+                       asg_sorted, m, blocks, cell, rot);
+    return hipGetLastError();
+}
+
+hipError_t prune_query_sort_bytes(int64_t n, int64_t m, size_t *bytes) {
+    *bytes = 0;
+    return hipcub::DeviceRadixSort::SortPairs(nullptr, *bytes, (const uint32_t *)nullptr,
+                                              (uint32_t *)nullptr, (const uint32_t *)nullptr,
+                                              (uint32_t *)nullptr, (int)m, 0, pivot_bits(n));
 }
 
 }  // namespace fmg

@@ -234,7 +234,9 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
     // pruning the scan starts at this workgroup's own rows (the self-join's
     // rows and columns share one order) and wraps around.
     const int len = ce - cb;
-    const int rot = PRUNE ? (int)(((int64_t)blockIdx.x * SCREEN_QPB) % len) : 0;
+    const int rot = !PRUNE ? 0
+                    : a.rot_tab ? (int)(a.rot_tab[blockIdx.x] % len)
+                                : (int)(((int64_t)blockIdx.x * SCREEN_QPB) % len);
     auto phys = [&](int v) {
         int p = cb + v + rot;
         return p >= ce ? p - len : p;

@@ -70,3 +70,28 @@ def test_pruned_build_with_duplicates_and_self_inclusive_sets():
     Nr, _, _ = oracle.build_model(X.astype(np.float64), Y.astype(np.float64), 24, "matern", 1.5,
                                   2.0, 1e-2, 1.0, oracle.MODE_SELF, rows=rows)
     assert np.array_equal(got[0][rows], Nr)
+
+
+def test_pruned_prediction_equals_chunked_unpruned_prediction():
+    # 70,000 queries in one call take the pruned screen (queries sorted by
+    # nearest pivot); chunks of 20,000 take the full screen
+    f = fmg()
+    X, Y = clustered(50_000, 24, 8, 11)
+    Z, _ = clustered(70_000, 24, 8, 11)  # same cluster means (same seed), fresh points
+    Z = Z + np.float32(0.01)
+    m = f.fastmuygps_build(torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda(), 30, "rbf",
+                           0.0, 3.0, 1e-2, precision="mixed")
+    Zd = torch.from_numpy(Z).cuda()
+    nn_all = torch.empty(70_000, dtype=torch.int32, device="cuda")
+    mu_all = m.predict(Zd, nn_out=nn_all).cpu().numpy()
+    parts_nn, parts_mu = [], []
+    for lo in range(0, 70_000, 20_000):
+        nn = torch.empty(min(20_000, 70_000 - lo), dtype=torch.int32, device="cuda")
+        parts_mu.append(m.predict(Zd[lo:lo + 20_000], nn_out=nn).cpu().numpy())
+        parts_nn.append(nn.cpu().numpy())
+    m.free()
+    assert np.array_equal(nn_all.cpu().numpy(), np.concatenate(parts_nn))
+    assert np.array_equal(mu_all, np.concatenate(parts_mu))
+    take = np.random.default_rng(4).choice(70_000, 300, replace=False)
+    ref, _ = oracle.nearest(X.astype(np.float64), Z[take].astype(np.float64))
+    assert np.array_equal(nn_all.cpu().numpy()[take], ref)
