@@ -376,11 +376,12 @@ fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_
             sa.nx_max = M->nx_max;
             sa.rot_tab = rot;
         }
+        if (prune) record(M, M->evp, EV_PREP, s);  // the query order counts as ingest
         HIPCHK(launch_screen(g, sa, s), "screen");
+        record(M, M->evp, EV_SCREEN, s);
         if (prune)
             HIPCHK(launch_unpermute_cand(cand_p, tq_p, qperm, M->perm, m, M->n, c, cand, tq, s),
                    "unpermute");
-        record(M, M->evp, EV_SCREEN, s);
         RerankArgs ra{};
         ra.cand = cand;
         ra.tq = tq;
@@ -755,10 +756,11 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
             sa.acc_coef = M->acc_coef;
             sa.nx_max = M->nx_max;
         }
+        if (prune) record(M, M->evb, EV_PREP, s);  // the pivot order counts as ingest
         HCHK(launch_screen(geom, sa, s), "screen");
+        record(M, M->evb, EV_SCREEN, s);
         if (prune)
             HCHK(launch_unpermute_cand(cand_p, tq_p, perm, perm, n, n, c, cand, tq, s), "unpermute");
-        record(M, M->evb, EV_SCREEN, s);
         RerankArgs ra{};
         ra.cand = cand;
         ra.tq = tq;
