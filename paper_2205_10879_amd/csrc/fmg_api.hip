@@ -361,7 +361,8 @@ fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_
             HIPCHK(tmp.alloc((void **)&cand_p, (size_t)m * c * 8), "scratch");
             HIPCHK(tmp.alloc((void **)&tq_p, (size_t)m * 4), "scratch");
             HIPCHK(launch_prune_queries((const float *)M->X, M->n, (const float *)Z, m, M->d, M->mu,
-                                        sort_tmp, sort_bytes, asg, asg2, idx, qperm, g, Zq, nzz,
+                                        sort_tmp, sort_bytes, M->cell + prune_pivots(M->n) + 1,
+                                        asg, asg2, idx, qperm, g, Zq, nzz,
                                         m_pad, Zq2, nzq, M->cell, rot, s),
                    "query order");
             sa.Q = Zq2;
@@ -728,7 +729,8 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
             MCHK(model_alloc(M, MA_XPP, &M->Xpp, (size_t)n_pad * geom.row_bytes, "model rows"));
             MCHK(model_alloc(M, MA_TC, &M->tile_c, tiles * geom.row_bytes, "model tiles"));
             MCHK(model_alloc(M, MA_TR, (void **)&M->tile_r, tiles * 4, "model tiles"));
-            MCHK(model_alloc(M, MA_CELL, (void **)&M->cell, (size_t)(npiv + 1) * 4, "model cells"));
+            MCHK(model_alloc(M, MA_CELL, (void **)&M->cell, (size_t)(2 * npiv + 1) * 4,
+                             "model cells"));
             perm = M->perm;
             HCHK(tmp.alloc((void **)&asg, (size_t)n * 4), "scratch");
             HCHK(tmp.alloc((void **)&asg2, (size_t)n * 4), "scratch");
@@ -738,8 +740,8 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
             HCHK(tmp.alloc((void **)&nzq, (size_t)n_pad * 4), "scratch");
             HCHK(tmp.alloc((void **)&cand_p, (size_t)n * c * 8), "scratch");
             HCHK(tmp.alloc((void **)&tq_p, (size_t)n * 4), "scratch");
-            HCHK(launch_prune_order((const float *)M->X, n, d, M->mu, sort_tmp, sort_bytes, asg,
-                                    asg2, idx, perm, s),
+            HCHK(launch_prune_order((const float *)M->X, n, d, M->mu, sort_tmp, sort_bytes,
+                                    M->cell + npiv + 1, asg, asg2, idx, perm, s),
                  "pivot order");
             HCHK(launch_cell_starts(asg2, n, npiv, M->cell, s), "cell starts");
             HCHK(launch_prune_rows(geom, Xq, M->Xp, nzx, perm, n, n_pad, d, Xq2, M->Xpp, nzq,

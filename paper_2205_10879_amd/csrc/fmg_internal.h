@@ -47,7 +47,7 @@ struct fmg_model {
     void *Xpp = nullptr;       // [n_pad, kp]
     void *tile_c = nullptr;    // [n_pad / 64, kp]
     float *tile_r = nullptr;   // [n_pad / 64]
-    int32_t *cell = nullptr;   // [pivots + 1]
+    int32_t *cell = nullptr;   // [pivots + 1] cell starts, then [pivots] pivot labels
     double e_max = 0.0, nx_max = 0.0, acc_coef = 0.0;
     int c_build = 0, c_query = 0;
     int64_t nonpd = 0, build_fb = 0;

@@ -201,9 +201,12 @@ hipError_t launch_loo_grad(bool f64, const GradArgs &a, double *part, double *ou
 // mapped back to the original order.
 int prune_pivots(int64_t n);
 hipError_t prune_sort_bytes(int64_t n, size_t *bytes);
+// label [P]: pivot labels along a nearest-neighbour chain (written here,
+// reused for the queries of predictions).
 hipError_t launch_prune_order(const float *X, int64_t n, int d, const float *mu, void *sort_tmp,
-                              size_t sort_bytes, uint32_t *asg, uint32_t *asg_sorted,
-                              uint32_t *idx, uint32_t *perm, hipStream_t s);
+                              size_t sort_bytes, int32_t *label, uint32_t *asg,
+                              uint32_t *asg_sorted, uint32_t *idx, uint32_t *perm,
+                              hipStream_t s);
 hipError_t launch_prune_rows(const ScreenGeom &g, const void *Qrows, const void *Prows,
                              const double *nz, const uint32_t *perm, int64_t n, int64_t n_pad,
                              int d, void *Qout, void *Pout, float *nzq, void *tile_c,
@@ -221,7 +224,8 @@ hipError_t launch_cell_starts(const uint32_t *asg_sorted, int64_t n, int P, int3
 hipError_t prune_query_sort_bytes(int64_t n, int64_t m, size_t *bytes);
 hipError_t launch_prune_queries(const float *X, int64_t n, const float *Z, int64_t m, int d,
                                 const float *mu, void *sort_tmp, size_t sort_bytes,
-                                uint32_t *asg, uint32_t *asg_sorted, uint32_t *idx,
+                                const int32_t *label, uint32_t *asg, uint32_t *asg_sorted,
+                                uint32_t *idx,
                                 uint32_t *qperm, const ScreenGeom &g, const void *Zq,
                                 const double *nzz, int64_t m_pad, void *Zq_out, float *nzq,
                                 const int32_t *cell, int32_t *rot, hipStream_t s);

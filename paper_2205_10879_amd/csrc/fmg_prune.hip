@@ -3,11 +3,14 @@
 // 64-row candidate tiles are compact, and per tile a ball that bounds its
 // rows, so that the screen can skip tiles no query of a wave can take.
 //
-//   1. P pivots (evenly spaced training points) and the nearest pivot of
-//      every point (FP32 distances of the centred coordinates; any assignment
-//      is correct, a good one makes tiles compact);
-//   2. a stable sort by pivot (hipCUB radix sort over (pivot, index)), giving
-//      the permutation perm: position i of the screen holds point perm[i];
+//   1. P pivots (evenly spaced training points), labelled along a greedy
+//      nearest-neighbour chain so that consecutive labels are close, and the
+//      nearest pivot of every point (FP32 distances of the centred
+//      coordinates; any assignment is correct, a good one makes tiles
+//      compact);
+//   2. a stable sort by pivot label (hipCUB radix sort over (label, index)),
+//      giving the permutation perm: position i of the screen holds point
+//      perm[i]; the cells of one cluster form a run;
 //   3. the screening rows gathered into that order, with the query norms;
 //   4. per tile of 64 rows: the centroid of its BF16 rows, itself rounded to
 //      BF16 (so it is an exact point of the screened space) and written as a
@@ -25,42 +28,122 @@ namespace fmg {
 namespace {
 
 // Nearest pivot of points Pts [n, d]; pivot j is training row j * stride of X.
+// Coordinates are zero padded to DP (a multiple of 16 covering d), so the
+// distance loop has no guards and reads each pivot row as 16-byte vectors.
+template <int DP>
 __global__ __launch_bounds__(256) void pivot_assign_kernel(const float *__restrict__ X,
                                                            const float *__restrict__ Pts,
                                                            int64_t n, int d,
                                                            const float *__restrict__ mu, int P,
                                                            int64_t stride,
+                                                           const int32_t *__restrict__ label,
                                                            uint32_t *__restrict__ asg,
                                                            uint32_t *__restrict__ idx) {
-    extern __shared__ float piv[];  // [P, 64] centred pivot coordinates, zero past d
-    for (int e = threadIdx.x; e < P * 64; e += blockDim.x) {
-        const int j = e / 64, c = e % 64;
+    extern __shared__ __align__(16) float piv[];  // [P, DP] centred pivots, zero past d
+    for (int e = threadIdx.x; e < P * DP; e += blockDim.x) {
+        const int j = e / DP, c = e % DP;
         piv[e] = c < d ? X[(int64_t)j * stride * d + c] - mu[c] : 0.0f;
     }
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    float x[64];
+    float x[DP];
 #pragma unroll
-    for (int c = 0; c < 64; ++c) x[c] = c < d ? Pts[i * d + c] - mu[c] : 0.0f;
+    for (int c = 0; c < DP; ++c) x[c] = c < d ? Pts[i * d + c] - mu[c] : 0.0f;
     float best = INFINITY;
     uint32_t bj = 0;
     for (int j = 0; j < P; ++j) {
-        float s = 0.0f;
+        const float4 *pj = (const float4 *)(piv + j * DP);
+        float s0 = 0.0f, s1 = 0.0f;
 #pragma unroll
-        for (int c = 0; c < 64; ++c) {
-            if (c < d) {
-                const float t = x[c] - piv[j * 64 + c];
-                s = fmaf(t, t, s);
-            }
+        for (int c4 = 0; c4 < DP / 4; ++c4) {
+            const float4 v = pj[c4];
+            const float t0 = x[4 * c4] - v.x, t1 = x[4 * c4 + 1] - v.y;
+            const float t2 = x[4 * c4 + 2] - v.z, t3 = x[4 * c4 + 3] - v.w;
+            s0 = fmaf(t0, t0, s0);
+            s1 = fmaf(t1, t1, s1);
+            s0 = fmaf(t2, t2, s0);
+            s1 = fmaf(t3, t3, s1);
         }
-        if (s < best) {
-            best = s;
+        const float sj = s0 + s1;
+        if (sj < best) {
+            best = sj;
             bj = (uint32_t)j;
         }
     }
-    asg[i] = bj;
+    asg[i] = (uint32_t)label[bj];
     idx[i] = (uint32_t)i;
+}
+
+// Pivot labels along a greedy nearest-neighbour chain (pivot 0 first, then
+// repeatedly the nearest unlabelled pivot, ties to the smaller pivot), so
+// that pivots with consecutive labels are close and the cells of one cluster
+// form a run of the order.  One workgroup of 256 threads, thread j holding
+// pivot j (P <= 256).
+__global__ __launch_bounds__(256) void pivot_chain_kernel(const float *__restrict__ X, int d,
+                                                          const float *__restrict__ mu, int P,
+                                                          int64_t stride,
+                                                          int32_t *__restrict__ label) {
+    __shared__ float piv[256 * 64];
+    __shared__ uint64_t best[4];
+    __shared__ int cur_sh;
+    const int j = threadIdx.x;
+    for (int e = j; e < P * 64; e += 256) {
+        const int q = e / 64, c = e % 64;
+        piv[e] = c < d ? X[(int64_t)q * stride * d + c] - mu[c] : 0.0f;
+    }
+    bool used = j >= P;
+    if (j == 0) {
+        label[0] = 0;
+        cur_sh = 0;
+    }
+    if (j == 0) used = true;
+    __syncthreads();
+    for (int step = 1; step < P; ++step) {
+        const int cur = cur_sh;
+        float s = 0.0f;
+        for (int c = 0; c < d; ++c) {
+            const float t = piv[j * 64 + c] - piv[cur * 64 + c];
+            s = fmaf(t, t, s);
+        }
+        // key: distance bits, then pivot index (non-negative floats order as integers)
+        uint64_t key = used ? ~0ull : (((uint64_t)__float_as_uint(s)) << 32) | (uint32_t)j;
+#pragma unroll
+        for (int w = 32; w >= 1; w >>= 1) {
+            const uint64_t o = ((uint64_t)(uint32_t)__shfl_xor((int)(key >> 32), w) << 32) |
+                               (uint32_t)__shfl_xor((int)(uint32_t)key, w);
+            key = o < key ? o : key;
+        }
+        if ((j & 63) == 0) best[j >> 6] = key;
+        __syncthreads();
+        if (j == 0) {
+            uint64_t b = best[0];
+            for (int w = 1; w < 4; ++w) b = best[w] < b ? best[w] : b;
+            const int nxt = (int)(uint32_t)b;
+            label[nxt] = step;
+            cur_sh = nxt;
+        }
+        __syncthreads();
+        if (j == cur_sh) used = true;
+    }
+}
+
+template <int DP>
+void launch_assign_t(const float *X, const float *Pts, int64_t n, int d, const float *mu, int P,
+                     int64_t stride, const int32_t *label, uint32_t *asg, uint32_t *idx,
+                     hipStream_t s) {
+    const size_t shm = (size_t)P * DP * sizeof(float);
+    hipLaunchKernelGGL((pivot_assign_kernel<DP>), dim3((unsigned)((n + 255) / 256)), dim3(256), shm,
+                       s, X, Pts, n, d, mu, P, stride, label, asg, idx);
+}
+
+void launch_assign(const float *X, const float *Pts, int64_t n, int d, const float *mu, int P,
+                   int64_t stride, const int32_t *label, uint32_t *asg, uint32_t *idx,
+                   hipStream_t s) {
+    if (d <= 16) launch_assign_t<16>(X, Pts, n, d, mu, P, stride, label, asg, idx, s);
+    else if (d <= 32) launch_assign_t<32>(X, Pts, n, d, mu, P, stride, label, asg, idx, s);
+    else if (d <= 48) launch_assign_t<48>(X, Pts, n, d, mu, P, stride, label, asg, idx, s);
+    else launch_assign_t<64>(X, Pts, n, d, mu, P, stride, label, asg, idx, s);
 }
 
 // Rows i < n come from point perm[i]; padding rows stay in place.
@@ -200,14 +283,14 @@ hipError_t prune_sort_bytes(int64_t n, size_t *bytes) {
 }
 
 hipError_t launch_prune_order(const float *X, int64_t n, int d, const float *mu, void *sort_tmp,
-                              size_t sort_bytes, uint32_t *asg, uint32_t *asg_sorted,
-                              uint32_t *idx, uint32_t *perm, hipStream_t s) {
+                              size_t sort_bytes, int32_t *label, uint32_t *asg,
+                              uint32_t *asg_sorted, uint32_t *idx, uint32_t *perm,
+                              hipStream_t s) {
     const int P = prune_pivots(n);
     const int64_t stride = n / P;
-    if (d > 64) return hipErrorInvalidValue;
-    const size_t shm = (size_t)P * 64 * sizeof(float);
-    hipLaunchKernelGGL(pivot_assign_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), shm, s,
-                       X, X, n, d, mu, P, stride, asg, idx);
+    if (d > 64 || P > 256) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(pivot_chain_kernel, dim3(1), dim3(256), 0, s, X, d, mu, P, stride, label);
+    launch_assign(X, X, n, d, mu, P, stride, label, asg, idx, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return hipcub::DeviceRadixSort::SortPairs(sort_tmp, sort_bytes, asg, asg_sorted, idx, perm,
@@ -250,16 +333,15 @@ hipError_t launch_cell_starts(const uint32_t *asg_sorted, int64_t n, int P, int3
 
 hipError_t launch_prune_queries(const float *X, int64_t n, const float *Z, int64_t m, int d,
                                 const float *mu, void *sort_tmp, size_t sort_bytes,
-                                uint32_t *asg, uint32_t *asg_sorted, uint32_t *idx,
+                                const int32_t *label, uint32_t *asg, uint32_t *asg_sorted,
+                                uint32_t *idx,
                                 uint32_t *qperm, const ScreenGeom &g, const void *Zq,
                                 const double *nzz, int64_t m_pad, void *Zq_out, float *nzq,
                                 const int32_t *cell, int32_t *rot, hipStream_t s) {
     if (d > 64 || g.mode != SCREEN_BF16 || g.row_bytes % 16 != 0) return hipErrorInvalidValue;
     const int P = prune_pivots(n);
     const int64_t stride = n / P;
-    const size_t shm = (size_t)P * 64 * sizeof(float);
-    hipLaunchKernelGGL(pivot_assign_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), shm, s,
-                       X, Z, m, d, mu, P, stride, asg, idx);
+    launch_assign(X, Z, m, d, mu, P, stride, label, asg, idx, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = hipcub::DeviceRadixSort::SortPairs(sort_tmp, sort_bytes, asg, asg_sorted, idx, qperm,
