@@ -77,7 +77,8 @@ __host__ __device__ __forceinline__ PcLayout pc_layout(int k, int d, int kmax, i
     L.off_r1 = 0;
     L.off_l = (r1 + 15) & ~15;
     L.off_bc = (L.off_l + (k * (k - 1) / 2) * 4 + 15) & ~15;
-    L.off_nrm = L.off_bc + 64 * (refine ? ellmax : 1) * 4;
+    // two buffers of 64 float4 for the blocked Cholesky steps
+    L.off_nrm = L.off_bc + (refine && ellmax >= 8 ? 64 * ellmax * 4 : 2048);
     L.off_nrm64 = L.off_nrm + 64 * 4;
     L.bytes = L.off_nrm64 + 64 * 8;
     return L;
@@ -179,9 +180,17 @@ __device__ __forceinline__ double exp_nonpos64(double x) {
     return ldexp(q, e);
 }
 
-// phi in FP64 for the refinement residual, through exp_nonpos64.
-__device__ __forceinline__ double phi_eval64(const PhiForm<double> &f, double D) {
-    const double s = f.scale * (f.root ? sqrt(D) : D);
+// phi from its argument t (the distance for the Matern forms, the squared
+// distance for RBF: the caller takes the square root under a uniform branch,
+// so that RBF runs no square roots), in FP32 and in FP64 through
+// exp_nonpos64 for the refinement residual.
+__device__ __forceinline__ float phi_arg32(const PhiForm<float> &f, float t) {
+    const float s = f.scale * t;
+    return f.amp * fmaf(fmaf(f.c2, s, f.c1), s, 1.0f) * expf(-s);
+}
+
+__device__ __forceinline__ double phi_arg64(const PhiForm<double> &f, double t) {
+    const double s = f.scale * t;
     return f.amp * fma(fma(f.c2, s, f.c1), s, 1.0) * exp_nonpos64(-s);
 }
 
@@ -211,13 +220,69 @@ __device__ __forceinline__ void solve_unit_backward(const float *__restrict__ U,
     }
 }
 
-// Cholesky steps j in [j0, j1) with a register window of W columns.
+// Four Cholesky steps j .. j + 3 at once (register window of W columns).
+// The panel, columns j .. j + 3 held in K[0..3], is factored with values
+// read across lanes (the entry of row j + t2 in column j + t comes from lane
+// j + t2); every lane then publishes its four panel entries in LDS, and the
+// trailing columns take the four rank-one updates in step order, so each
+// entry sees exactly the operations of four single steps, with one LDS
+// round trip instead of four.  bc holds two buffers of 64 float4, used
+// alternately.
+template <int KMAX, int ELLMAX, int W>
+__device__ __forceinline__ void chol_block4(float (&K)[KMAX], float (&y)[ELLMAX], int j, int k,
+                                            int a, float *__restrict__ U,
+                                            float *__restrict__ bc, float &dinv, bool &bad) {
+    const int arow = a * (a - 1) / 2;
+    float u[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        float piv = readlane_f32(K[t], j + t);
+        if (!(piv > 0.0f) || !isfinite(piv)) {
+            bad = true;
+            piv = 1.0f;
+        }
+        const float rp = 1.0f / piv;
+        const bool below = a > j + t && a < k;
+        u[t] = below ? K[t] * rp : 0.0f;
+        if (a == j + t) dinv = rp;
+        if (below) U[arow + j + t] = u[t];
+#pragma unroll
+        for (int c = 0; c < ELLMAX; ++c) y[c] = fmaf(-u[t], readlane_f32(y[c], j + t), y[c]);
+#pragma unroll
+        for (int t2 = t + 1; t2 < 4; ++t2)
+            K[t2] = fmaf(-u[t], readlane_f32(K[t], j + t2), K[t2]);
+    }
+    // Entry b of the buffer: the panel row of lane j + 4 + b; positions past
+    // the last row are zero.
+    float4 *buf = (float4 *)bc + ((j >> 2) & 1) * 64;
+    buf[(a - j - 4) & 63] =
+        (a >= j + 4) ? make_float4(K[0], K[1], K[2], K[3]) : make_float4(0.f, 0.f, 0.f, 0.f);
+    lds_sync();
+#pragma unroll
+    for (int b = 4; b < W; ++b) {
+        const float4 v = buf[b - 4];
+        float x = fmaf(-u[0], v.x, K[b]);
+        x = fmaf(-u[1], v.y, x);
+        x = fmaf(-u[2], v.z, x);
+        K[b - 4] = fmaf(-u[3], v.w, x);
+    }
+#pragma unroll
+    for (int b = W - 4; b < W; ++b) K[b] = 0.0f;
+}
+
+// Cholesky steps j in [j0, j1) with a register window of W columns: blocks
+// of four steps, then single steps.
 template <int KMAX, int ELLMAX, int W>
 __device__ __forceinline__ void chol_steps(float (&K)[KMAX], float (&y)[ELLMAX], int j0, int j1,
                                            int k, int ell, int a, float *__restrict__ U,
                                            float *__restrict__ bc, float &dinv, bool &bad) {
     const int arow = a * (a - 1) / 2;
-    for (int j = j0; j < j1; ++j) {
+    int j = j0;
+    if (j + 4 <= j1) {
+        for (; j + 4 <= j1; j += 4) chol_block4<KMAX, ELLMAX, W>(K, y, j, k, a, U, bc, dinv, bad);
+        lds_sync();  // the last block's readers are done before bc is written again
+    }
+    for (; j < j1; ++j) {
         float piv = readlane_f32(K[0], j);
         if (!(piv > 0.0f) || !isfinite(piv)) {
             bad = true;
@@ -324,12 +389,15 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
     const PhiForm<float> pf = phi_form<float>(P.kc, P.inv_rho, P.amp);
     const float diag = (float)(P.amp + P.noise);
 #pragma unroll
+    for (int b = 0; b < KMAX; ++b) K[b] = fmaxf(na + nrm[b] - 2.0f * K[b], 0.0f);
+    if (pf.root) {
+#pragma unroll
+        for (int b = 0; b < KMAX; ++b) K[b] = sqrtf(K[b]);
+    }
+#pragma unroll
     for (int b = 0; b < KMAX; ++b) {
         float v = 0.0f;
-        if (b < k) {
-            const float D = fmaxf(na + nrm[b] - 2.0f * K[b], 0.0f);
-            v = (a == b) ? diag : phi_eval(pf, D);
-        }
+        if (b < k) v = (a == b) ? diag : phi_arg32(pf, K[b]);
         K[b] = (a < k) ? v : ((a == b) ? 1.0f : 0.0f);
     }
 
@@ -404,6 +472,20 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
                 }
             }
             const double ncol = nrm64[rb];
+#pragma unroll
+            for (int r = 0; r < NT; ++r) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const double D = nrm64[r * 16 + 4 * q + fk] + ncol - 2.0 * g[r][q];
+                    g[r][q] = D > 0.0 ? D : 0.0;
+                }
+            }
+            if (pf64.root) {
+#pragma unroll
+                for (int r = 0; r < NT; ++r)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) g[r][q] = sqrt(g[r][q]);
+            }
             f64x4 acc64 = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int r = 0; r < NT; ++r) {
@@ -411,11 +493,7 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
                 for (int q = 0; q < 4; ++q) {
                     const int row = r * 16 + 4 * q + fk;
                     double kab = 0.0;
-                    if (row < k && rb < k) {
-                        double D = nrm64[row] + ncol - 2.0 * g[r][q];
-                        D = D > 0.0 ? D : 0.0;
-                        kab = (row == rb) ? diag64 : phi_eval64(pf64, D);
-                    }
+                    if (row < k && rb < k) kab = (row == rb) ? diag64 : phi_arg64(pf64, g[r][q]);
                     const double cv = (fr < ell) ? (double)cb[row * ELLMAX + fr] : 0.0;
                     acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(kab, cv, acc64, 0, 0, 0);
                 }
