@@ -340,9 +340,7 @@ fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_
         sa.pool = pool;
         sa.cand = cand;
         sa.tq = tq;
-        uint32_t *qperm = nullptr;
-        uint64_t *cand_p = nullptr;
-        float *tq_p = nullptr;
+        uint32_t *qperm = nullptr, *qinv = nullptr;
         if (prune) {
             uint32_t *asg = nullptr, *asg2 = nullptr, *idx = nullptr;
             void *sort_tmp = nullptr, *Zq2 = nullptr;
@@ -358,17 +356,15 @@ fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_
             HIPCHK(tmp.alloc(&Zq2, (size_t)m_pad * g.row_bytes), "scratch");
             HIPCHK(tmp.alloc((void **)&nzq, (size_t)m_pad * 4), "scratch");
             HIPCHK(tmp.alloc((void **)&rot, (size_t)(m_pad / SCREEN_QPB) * 4), "scratch");
-            HIPCHK(tmp.alloc((void **)&cand_p, (size_t)m * c * 8), "scratch");
-            HIPCHK(tmp.alloc((void **)&tq_p, (size_t)m * 4), "scratch");
+            HIPCHK(tmp.alloc((void **)&qinv, (size_t)m * 4), "scratch");
             HIPCHK(launch_prune_queries((const float *)M->X, M->n, (const float *)Z, m, M->d, M->mu,
                                         sort_tmp, sort_bytes, M->cell + prune_pivots(M->n) + 1,
                                         asg, asg2, idx, qperm, g, Zq, nzz,
                                         m_pad, Zq2, nzq, M->cell, rot, s),
                    "query order");
+            HIPCHK(launch_inverse_perm(qperm, m, qinv, s), "query order");
             sa.Q = Zq2;
             sa.P = M->Xpp;
-            sa.cand = cand_p;
-            sa.tq = tq_p;
             sa.prune = 1;
             sa.tile_c = M->tile_c;
             sa.tile_r = M->tile_r;
@@ -380,10 +376,12 @@ fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_
         if (prune) record(M, M->evp, EV_PREP, s);  // the query order counts as ingest
         HIPCHK(launch_screen(g, sa, s), "screen");
         record(M, M->evp, EV_SCREEN, s);
-        if (prune)
-            HIPCHK(launch_unpermute_cand(cand_p, tq_p, qperm, M->perm, m, M->n, c, cand, tq, s),
-                   "unpermute");
         RerankArgs ra{};
+        if (prune) {  // screen rows and indices are in pivot order
+            ra.row_of = qinv;
+            ra.cand_idx = M->perm;
+            ra.n_idx = M->n;
+        }
         ra.cand = cand;
         ra.tq = tq;
         ra.splits = (int)splits;
@@ -710,13 +708,12 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
         sa.cand = cand;
         sa.tq = tq;
         // Tile pruning: screen the self-join in nearest-pivot order, skipping
-        // tiles whose bounding balls no query of a wavefront can reach, then
-        // map the candidate lists back to the original order.
+        // tiles whose bounding balls no query of a wavefront can reach; the
+        // re-rank reads each row's candidates through the inverse order and
+        // maps their indices back.
         const bool prune = geom.mode == SCREEN_BF16 && !(flags & FMG_FLAG_NO_PRUNE) &&
                            prune_pivots(n) > 1 && d <= 64;
-        uint32_t *perm = nullptr;
-        uint64_t *cand_p = nullptr;
-        float *tq_p = nullptr;
+        uint32_t *perm = nullptr, *pinv = nullptr;
         if (prune) {
             uint32_t *asg = nullptr, *asg2 = nullptr, *idx = nullptr;
             void *sort_tmp = nullptr, *Xq2 = nullptr;
@@ -738,8 +735,7 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
             HCHK(tmp.alloc(&sort_tmp, sort_bytes), "scratch");
             HCHK(tmp.alloc(&Xq2, (size_t)n_pad * geom.row_bytes), "scratch");
             HCHK(tmp.alloc((void **)&nzq, (size_t)n_pad * 4), "scratch");
-            HCHK(tmp.alloc((void **)&cand_p, (size_t)n * c * 8), "scratch");
-            HCHK(tmp.alloc((void **)&tq_p, (size_t)n * 4), "scratch");
+            HCHK(tmp.alloc((void **)&pinv, (size_t)n * 4), "scratch");
             HCHK(launch_prune_order((const float *)M->X, n, d, M->mu, sort_tmp, sort_bytes,
                                     M->cell + npiv + 1, asg, asg2, idx, perm, s),
                  "pivot order");
@@ -747,10 +743,9 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
             HCHK(launch_prune_rows(geom, Xq, M->Xp, nzx, perm, n, n_pad, d, Xq2, M->Xpp, nzq,
                                    M->tile_c, M->tile_r, s),
                  "pruning rows");
+            HCHK(launch_inverse_perm(perm, n, pinv, s), "pivot order");
             sa.Q = Xq2;
             sa.P = M->Xpp;
-            sa.cand = cand_p;
-            sa.tq = tq_p;
             sa.prune = 1;
             sa.tile_c = M->tile_c;
             sa.tile_r = M->tile_r;
@@ -761,9 +756,12 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
         if (prune) record(M, M->evb, EV_PREP, s);  // the pivot order counts as ingest
         HCHK(launch_screen(geom, sa, s), "screen");
         record(M, M->evb, EV_SCREEN, s);
-        if (prune)
-            HCHK(launch_unpermute_cand(cand_p, tq_p, perm, perm, n, n, c, cand, tq, s), "unpermute");
         RerankArgs ra{};
+        if (prune) {  // screen rows and indices are in pivot order
+            ra.row_of = pinv;
+            ra.cand_idx = perm;
+            ra.n_idx = n;
+        }
         ra.cand = cand;
         ra.tq = tq;
         ra.splits = 1;

@@ -71,25 +71,40 @@ __global__ __launch_bounds__(256) void finite_kernel(const T *__restrict__ A, in
     if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(flag, 1);
 }
 
+// Running maxima of non-negative doubles as their bit patterns (which order
+// like the values): one atomic per wavefront, after a wave-wide maximum.
+__device__ __forceinline__ void wave_atomic_max_bits(unsigned long long *dst, double v) {
+    unsigned long long b = (unsigned long long)__double_as_longlong(v);
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const unsigned long long o =
+            ((unsigned long long)(uint32_t)__shfl_xor((int)(b >> 32), w) << 32) |
+            (uint32_t)__shfl_xor((int)(uint32_t)b, w);
+        b = o > b ? o : b;
+    }
+    if (lane_id() == 0) atomicMax(dst, b);
+}
+
 __global__ __launch_bounds__(256) void prep_bf16_kernel(
     const float *__restrict__ X, int64_t n, int64_t n_pad, int d, const float *__restrict__ mu,
     int kp, uint16_t *__restrict__ Q, uint16_t *__restrict__ P, double *__restrict__ e_out,
     double *__restrict__ nz_out, unsigned long long *emax_bits,
     unsigned long long *nxmax_bits) {
     const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (r >= n_pad) return;
-    uint16_t *q = Q ? Q + r * kp : nullptr;
-    uint16_t *p = P ? P + r * kp : nullptr;
-    if (r >= n) {
+    // lanes past n_pad write nothing but still take part in the wave maxima
+    uint16_t *q = (Q && r < n_pad) ? Q + r * kp : nullptr;
+    uint16_t *p = (P && r < n_pad) ? P + r * kp : nullptr;
+    double e = 0.0, nz = 0.0;
+    if (r >= n_pad) {
+    } else if (r >= n) {
         // Padding candidate: a huge norm part keeps it out of every selection.
         for (int c = 0; c < kp; ++c) {
             if (q) q[c] = 0;
             if (p) p[c] = 0;
         }
         if (p) p[d] = f32_to_bf16_rn(1.0e30f);
-        return;
-    }
-    double e2 = 0.0, nz = 0.0;
+    } else {
+    double e2 = 0.0;
     for (int c = 0; c < d; ++c) {
         const double xc = (double)X[r * d + c] - (double)mu[c];
         const uint16_t h = f32_to_bf16_rn((float)xc);
@@ -111,11 +126,12 @@ __global__ __launch_bounds__(256) void prep_bf16_kernel(
         if (q) q[c] = (c < d + 3) ? one : 0;
         if (p) p[c] = (c == d) ? hi : (c == d + 1) ? mid : (c == d + 2) ? lo : 0;
     }
-    const double e = sqrt(e2) * (1.0 + 1.0e-12);
+    e = sqrt(e2) * (1.0 + 1.0e-12);
     if (e_out) e_out[r] = e;
     if (nz_out) nz_out[r] = nz;
-    if (emax_bits) atomicMax(emax_bits, (unsigned long long)__double_as_longlong(e));
-    if (nxmax_bits) atomicMax(nxmax_bits, (unsigned long long)__double_as_longlong(nz));
+    }
+    if (emax_bits) wave_atomic_max_bits(emax_bits, e);
+    if (nxmax_bits) wave_atomic_max_bits(nxmax_bits, nz);
 }
 
 __global__ __launch_bounds__(256) void prep_f32_kernel(
@@ -124,18 +140,19 @@ __global__ __launch_bounds__(256) void prep_f32_kernel(
     double *__restrict__ nz_out, unsigned long long *emax_bits,
     unsigned long long *nxmax_bits) {
     const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (r >= n_pad) return;
-    float *q = Q ? Q + r * kp : nullptr;
-    float *p = P ? P + r * kp : nullptr;
-    if (r >= n) {
+    // lanes past n_pad write nothing but still take part in the wave maxima
+    float *q = (Q && r < n_pad) ? Q + r * kp : nullptr;
+    float *p = (P && r < n_pad) ? P + r * kp : nullptr;
+    double e = 0.0, nz = 0.0;
+    if (r >= n_pad) {
+    } else if (r >= n) {
         for (int c = 0; c < kp; ++c) {
             if (q) q[c] = 0.0f;
             if (p) p[c] = 0.0f;
         }
         if (p) p[d] = 1.0e30f;
-        return;
-    }
-    double e2 = 0.0, nz = 0.0;
+    } else {
+    double e2 = 0.0;
     for (int c = 0; c < d; ++c) {
         const double xc = (double)X[r * d + c] - (double)mu[c];
         const float xt = (float)xc;
@@ -149,11 +166,12 @@ __global__ __launch_bounds__(256) void prep_f32_kernel(
         if (q) q[c] = (c == d) ? 1.0f : 0.0f;
         if (p) p[c] = (c == d) ? (float)nz : 0.0f;
     }
-    const double e = (e2 > 0.0) ? sqrt(e2) * (1.0 + 1.0e-12) : 0.0;
+    e = (e2 > 0.0) ? sqrt(e2) * (1.0 + 1.0e-12) : 0.0;
     if (e_out) e_out[r] = e;
     if (nz_out) nz_out[r] = nz;
-    if (emax_bits) atomicMax(emax_bits, (unsigned long long)__double_as_longlong(e));
-    if (nxmax_bits) atomicMax(nxmax_bits, (unsigned long long)__double_as_longlong(nz));
+    }
+    if (emax_bits) wave_atomic_max_bits(emax_bits, e);
+    if (nxmax_bits) wave_atomic_max_bits(nxmax_bits, nz);
 }
 
 __global__ __launch_bounds__(256) void count_nonzero_kernel(const int32_t *__restrict__ a,

@@ -16,8 +16,9 @@
 //      BF16 (so it is an exact point of the screened space) and written as a
 //      candidate row, and the FP64 radius max ||x~ - c~|| over the tile's real
 //      rows, rounded up;
-//   5. after the screen, candidate indices and rows mapped back to the
-//      original order, so that the re-rank and certificate run unchanged.
+//   5. the inverse order, through which the re-rank reads each row's
+//      candidates and maps their indices back to training indices, so that
+//      the certificate runs unchanged.
 #include <hipcub/hipcub.hpp>
 
 #include "fmg_device.h"
@@ -214,25 +215,10 @@ __global__ __launch_bounds__(64) void tile_bounds_kernel(const uint16_t *__restr
     }
 }
 
-// Screen output of permuted query row q' (candidate keys with permuted
-// indices) -> row perm[q'] with original indices.
-__global__ __launch_bounds__(256) void unpermute_cand_kernel(const uint64_t *__restrict__ cand,
-                                                             const float *__restrict__ tq,
-                                                             const uint32_t *__restrict__ qperm,
-                                                             const uint32_t *__restrict__ cperm,
-                                                             int64_t m, int64_t n, int c,
-                                                             uint64_t *__restrict__ cand_out,
-                                                             float *__restrict__ tq_out) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m * c) return;
-    const int64_t q = e / c;
-    const int s = (int)(e % c);
-    const int64_t o = qperm[q];
-    const uint64_t key = cand[e];
-    const uint32_t p = (uint32_t)key;
-    const uint64_t mapped = (p < (uint64_t)n) ? ((key & 0xffffffff00000000ull) | cperm[p]) : key;
-    cand_out[o * c + s] = mapped;
-    if (s == 0) tq_out[o] = tq[q];
+__global__ __launch_bounds__(256) void inverse_perm_kernel(const uint32_t *__restrict__ perm,
+                                                           int64_t n, uint32_t *__restrict__ inv) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) inv[perm[i]] = (uint32_t)i;
 }
 
 // cell[j] = first position of pivot j in the sorted assignment (j <= P).
@@ -314,13 +300,10 @@ hipError_t launch_prune_rows(const ScreenGeom &g, const void *Qrows, const void 
     return hipGetLastError();
 }
 
-hipError_t launch_unpermute_cand(const uint64_t *cand, const float *tq, const uint32_t *qperm,
-                                 const uint32_t *cperm, int64_t m, int64_t n, int c,
-                                 uint64_t *cand_out, float *tq_out, hipStream_t s) {
-    const int64_t items = m * (int64_t)c;
-    if (items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(unpermute_cand_kernel, dim3((unsigned)((items + 255) / 256)), dim3(256), 0,
-                       s, cand, tq, qperm, cperm, m, n, c, cand_out, tq_out);
+hipError_t launch_inverse_perm(const uint32_t *perm, int64_t n, uint32_t *inv, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(inverse_perm_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, perm,
+                       n, inv);
     return hipGetLastError();
 }
 

@@ -39,6 +39,9 @@ __global__ __launch_bounds__(256) void rerank_kernel(RerankArgs a) {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 
+    // row of this query in the screen's output (queries screened in a pivot
+    // order), and screened indices mapped to training indices
+    const int64_t cq = a.row_of ? (int64_t)a.row_of[q] : q;
     const int total = a.splits * a.c;
     XKey list = xkey_empty();
     for (int base = 0; base < total; base += 64) {
@@ -46,9 +49,10 @@ __global__ __launch_bounds__(256) void rerank_kernel(RerankArgs a) {
         XKey key = xkey_empty();
         if (slot < total) {
             const int sp = slot / a.c, r = slot % a.c;
-            const uint64_t sk = a.cand[((int64_t)sp * a.m + q) * a.c + r];
+            const uint64_t sk = a.cand[((int64_t)sp * a.m + cq) * a.c + r];
             if (sk != SKEY_EMPTY) {
-                const uint32_t p = skey_idx(sk);
+                uint32_t p = skey_idx(sk);
+                if (a.cand_idx && p < (uint64_t)a.n_idx) p = a.cand_idx[p];
                 const float *__restrict__ xp = X + (int64_t)p * a.d;
                 double s = 0.0;
                 for (int c = 0; c < a.d; ++c) {
@@ -65,7 +69,7 @@ __global__ __launch_bounds__(256) void rerank_kernel(RerankArgs a) {
     // certificate
     double tmin = INFINITY;
     for (int sp = 0; sp < a.splits; ++sp) {
-        const double t = (double)a.tq[(int64_t)sp * a.m + q];
+        const double t = (double)a.tq[(int64_t)sp * a.m + cq];
         tmin = t < tmin ? t : tmin;
     }
     const XKey kk = readlane_x(list, a.k - 1);
