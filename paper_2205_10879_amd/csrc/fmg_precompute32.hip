@@ -450,14 +450,19 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
         lds_sync();
         const double diag64 = P.amp + P.noise;
         const PhiForm<double> pf64 = phi_form<double>(P.kc, P.inv_rho, P.amp);
+        // Column tiles go in groups of PG: each MFMA operand formed from the
+        // raw rows serves every tile of the group.
+        constexpr int PG = 2;
+        static_assert(NT % PG == 0, "column tile groups");
         f64x4 R[NT];
 #pragma unroll
-        for (int ct = 0; ct < NT; ++ct) {
-            f64x4 g[NT];
+        for (int c0 = 0; c0 < NT; c0 += PG) {
+            f64x4 g[PG][NT];
 #pragma unroll
-            for (int r = 0; r < NT; ++r) g[r] = f64x4{0.0, 0.0, 0.0, 0.0};
-            const int rb = ct * 16 + fr;
-            if (ct * 16 < k) {
+            for (int h = 0; h < PG; ++h)
+#pragma unroll
+                for (int r = 0; r < NT; ++r) g[h][r] = f64x4{0.0, 0.0, 0.0, 0.0};
+            if (c0 * 16 < k) {
                 for (int s = 0; s < d4; s += 4) {
                     double f[NT];
                     const double cc = (double)xc[s + fk];
@@ -467,38 +472,50 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
                         f[r] = (row < k) ? (double)xr[row * ld + s + fk] - cc : 0.0;
                     }
 #pragma unroll
+                    for (int h = 0; h < PG; ++h) {
+                        if (h == 0 || (c0 + h) * 16 < k) {
+#pragma unroll
+                            for (int r = 0; r < NT; ++r)
+                                g[h][r] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[r], f[c0 + h],
+                                                                               g[h][r], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < PG; ++h) {
+                const int ct = c0 + h;
+                const int rb = ct * 16 + fr;
+                const double ncol = nrm64[rb];
+#pragma unroll
+                for (int r = 0; r < NT; ++r) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const double D = nrm64[r * 16 + 4 * q + fk] + ncol - 2.0 * g[h][r][q];
+                        g[h][r][q] = D > 0.0 ? D : 0.0;
+                    }
+                }
+                if (pf64.root) {
+#pragma unroll
                     for (int r = 0; r < NT; ++r)
-                        g[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[r], f[ct], g[r], 0, 0, 0);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) g[h][r][q] = sqrt(g[h][r][q]);
                 }
-            }
-            const double ncol = nrm64[rb];
+                f64x4 acc64 = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int r = 0; r < NT; ++r) {
+                for (int r = 0; r < NT; ++r) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const double D = nrm64[r * 16 + 4 * q + fk] + ncol - 2.0 * g[r][q];
-                    g[r][q] = D > 0.0 ? D : 0.0;
+                    for (int q = 0; q < 4; ++q) {
+                        const int row = r * 16 + 4 * q + fk;
+                        double kab = 0.0;
+                        if (row < k && rb < k)
+                            kab = (row == rb) ? diag64 : phi_arg64(pf64, g[h][r][q]);
+                        const double cv = (fr < ell) ? (double)cb[row * ELLMAX + fr] : 0.0;
+                        acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(kab, cv, acc64, 0, 0, 0);
+                    }
                 }
+                R[ct] = acc64;
             }
-            if (pf64.root) {
-#pragma unroll
-                for (int r = 0; r < NT; ++r)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) g[r][q] = sqrt(g[r][q]);
-            }
-            f64x4 acc64 = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int r = 0; r < NT; ++r) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int row = r * 16 + 4 * q + fk;
-                    double kab = 0.0;
-                    if (row < k && rb < k) kab = (row == rb) ? diag64 : phi_arg64(pf64, g[r][q]);
-                    const double cv = (fr < ell) ? (double)cb[row * ELLMAX + fr] : 0.0;
-                    acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(kab, cv, acc64, 0, 0, 0);
-                }
-            }
-            R[ct] = acc64;
         }
         lds_sync();  // the raw rows are dead; their space takes K64 C
         double *KC = (double *)(smem + L.off_r1);  // [64][ELLMAX]
