@@ -5,8 +5,10 @@
 
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -45,23 +47,59 @@ fmg_status hip_fail(hipError_t e, const char *what) {
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
-// Device scratch owned by one call: freed when the holder goes out of scope,
-// stream-ordered when a stream is given.
+// Stream-ordered memory pool of the current device for call scratch.  Freed
+// scratch stays cached in the pool up to SCRATCH_POOL_KEEP bytes, so repeated
+// builds and predictions reuse it without mapping memory again; beyond that
+// it returns to the device at the next synchronisation.  A failed allocation
+// trims the cache and tries once more.
+constexpr uint64_t SCRATCH_POOL_KEEP = 16ull << 30;
+constexpr int MAX_DEVICES = 64;
+
+hipMemPool_t scratch_pool() {
+    static std::mutex mu;
+    static hipMemPool_t pools[MAX_DEVICES] = {};
+    static bool failed[MAX_DEVICES] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!pools[dev] && !failed[dev]) {
+        hipMemPoolProps props;
+        memset(&props, 0, sizeof props);
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = dev;
+        hipMemPool_t pool = nullptr;
+        if (hipMemPoolCreate(&pool, &props) != hipSuccess) {
+            failed[dev] = true;  // fall back to the device's default pool
+            return nullptr;
+        }
+        uint64_t keep = SCRATCH_POOL_KEEP;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        pools[dev] = pool;
+    }
+    return pools[dev];
+}
+
+// Device scratch owned by one call: freed (stream-ordered, on the call's
+// stream) when the holder goes out of scope.
 struct Scratch {
     hipStream_t stream = nullptr;
-    bool async = false;
     std::vector<void *> ptrs;
     ~Scratch() {
-        for (void *p : ptrs) {
-            if (async)
-                (void)hipFreeAsync(p, stream);
-            else
-                (void)hipFree(p);
-        }
+        for (void *p : ptrs) (void)hipFreeAsync(p, stream);
     }
     hipError_t alloc(void **p, size_t bytes) {
         if (bytes == 0) bytes = 16;
-        hipError_t e = async ? hipMallocAsync(p, bytes, stream) : hipMalloc(p, bytes);
+        hipMemPool_t pool = scratch_pool();
+        hipError_t e = pool ? hipMallocFromPoolAsync(p, bytes, pool, stream)
+                            : hipMallocAsync(p, bytes, stream);
+        if ((e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) && pool) {
+            (void)hipGetLastError();
+            (void)hipStreamSynchronize(stream);
+            (void)hipMemPoolTrimTo(pool, 0);
+            e = hipMallocFromPoolAsync(p, bytes, pool, stream);
+        }
         if (e == hipSuccess) ptrs.push_back(*p);
         return e;
     }
@@ -256,7 +294,6 @@ fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_
     const bool f64 = M->prec == FMG_PREC_FP64;
     Scratch tmp;
     tmp.stream = s;
-    tmp.async = true;
     record(M, M->evp, EV_START, s);
     int32_t *nn = nn_out;
     if (!nn) {
@@ -554,6 +591,7 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
     const size_t esz = f64 ? 8 : 4;
     fmg_status st;
     Scratch tmp;
+    tmp.stream = s;
 
 #define MCHK(expr)                  \
     do {                            \
@@ -879,7 +917,6 @@ fmg_status fastmuygps_predict_muygps(const fmg_model *model, const void *Z, int6
     const size_t esz = f64 ? 8 : 4;
     Scratch tmp;
     tmp.stream = s;
-    tmp.async = true;
     int32_t *nb = nbr_out;
     if (!nb) HIPCHK(tmp.alloc((void **)&nb, (size_t)m * k * 4), "scratch");
 
@@ -1069,7 +1106,6 @@ fmg_status fastmuygps_loo_loss(const fmg_model *model, const int32_t *rows, int6
     const double amp = hyper->amplitude > 0.0 ? hyper->amplitude : 1.0;
     Scratch tmp;
     tmp.stream = s;
-    tmp.async = true;
     void *Xb = nullptr, *Yb = nullptr, *Cb = nullptr, *mu = nullptr;
     int32_t *Nb = nullptr, *st = nullptr;
     int *bad = nullptr;
@@ -1158,7 +1194,6 @@ fmg_status fastmuygps_loo_loss_grad(const fmg_model *model, const int32_t *rows,
     hipStream_t s = (hipStream_t)stream;
     Scratch tmp;
     tmp.stream = s;
-    tmp.async = true;
     double *terms = nullptr, *part = nullptr, *sums = nullptr;
     int *bad = nullptr;
     HIPCHK(tmp.alloc((void **)&terms, (size_t)b * 3 * 8), "scratch");
