@@ -20,7 +20,12 @@
  *     stream); work is enqueued on it;
  *   - no call throws; every call returns an fmg_status and, on failure,
  *     leaves a message for fastmuygps_last_error() (thread-local);
- *   - indices are int32, so n <= 2^31 - 1.
+ *   - indices are int32, so n <= 2^31 - 1;
+ *   - device scratch of a call (candidate pools, orders, staging) comes from
+ *     a stream-ordered memory pool of the device that the library creates on
+ *     first use; freed scratch stays cached there, up to 16 GiB per device,
+ *     until the process ends (larger peaks return to the device at the next
+ *     synchronisation, and a failed allocation trims the cache and retries).
  */
 #ifndef FASTMUYGPS_H
 #define FASTMUYGPS_H
