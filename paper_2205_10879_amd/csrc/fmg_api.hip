@@ -636,15 +636,38 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
     HCHK(hipMemsetAsync(flag, 0, 4, s), "hipMemsetAsync");
     HCHK(launch_finite_check(X, f64, n * (int64_t)d, flag, s), "finite check");
     HCHK(launch_finite_check(Y, f64, n * (int64_t)ell, flag, s), "finite check");
-    int hflag = 0;
-    HCHK(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s), "copy flag");
-    HCHK(hipStreamSynchronize(s), "sync");
-    if (hflag) {
-        free_model(M);
-        return fail(FMG_E_INVALID_ARG, "X or Y holds a non-finite value");
-    }
-
     const int kk = self_inc ? k - 1 : k;  // neighbours found by search
+    // The screened paths read the flag with the screening rows' maxima (one
+    // synchronisation, after the pivot order has been enqueued); the others
+    // read it now.
+    const bool screened = !f64 && kk > 0;
+    int hflag = 0;
+    if (!screened) {
+        HCHK(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s), "copy flag");
+        HCHK(hipStreamSynchronize(s), "sync");
+        if (hflag) {
+            free_model(M);
+            return fail(FMG_E_INVALID_ARG, "X or Y holds a non-finite value");
+        }
+    }
+    unsigned long long *mx = nullptr;  // maxima of the rounding radii and squared norms
+    // Reads the input flag and the maxima, and sets the certificate's
+    // constants (FP32 and MIXED).
+    auto read_maxima = [&]() -> fmg_status {
+        unsigned long long hmx[2] = {0, 0};
+        hipError_t e = hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(hmx, mx, 16, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "copy maxima");
+        if (hflag) return fail(FMG_E_INVALID_ARG, "X or Y holds a non-finite value");
+        memcpy(&M->e_max, &hmx[0], 8);
+        memcpy(&M->nx_max, &hmx[1], 8);
+        const double u = std::ldexp(1.0, -23);
+        const double nt = 2.0 * geom.kp;
+        M->acc_coef = nt * u / (1.0 - nt * u);
+        M->c_query = 16;
+        return FMG_OK;
+    };
     // Screening rows (FP32 and MIXED): the candidate side is kept by the
     // model for the queries' search, the query side serves the build.
     int64_t n_pad = 0;
@@ -683,7 +706,6 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
             HCHK(launch_col_mean(M->X, false, n, d, M->mu, part, s), "column mean");
         }
         MCHK(model_alloc(M, MA_XP, &M->Xp, (size_t)n_pad * geom.row_bytes, "model screen rows"));
-        unsigned long long *mx = nullptr;
         HCHK(tmp.alloc(&Xq, (size_t)n_pad * geom.row_bytes), "scratch");
         HCHK(tmp.alloc((void **)&ex, (size_t)n * 8), "scratch");
         HCHK(tmp.alloc((void **)&nzx, (size_t)n * 8), "scratch");
@@ -692,20 +714,12 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
         HCHK(launch_prep_rows(geom, (const float *)M->X, n, n_pad, d, M->mu, Xq, M->Xp, ex, nzx,
                               mx, mx + 1, s),
              "screen rows");
-        unsigned long long hmx[2] = {0, 0};
-        HCHK(hipMemcpyAsync(hmx, mx, 16, hipMemcpyDeviceToHost, s), "copy maxima");
         record(M, M->evb, EV_PREP, s);
-        HCHK(hipStreamSynchronize(s), "sync");
-        memcpy(&M->e_max, &hmx[0], 8);
-        memcpy(&M->nx_max, &hmx[1], 8);
-        const double u = std::ldexp(1.0, -23);
-        const double nt = 2.0 * geom.kp;
-        M->acc_coef = nt * u / (1.0 - nt * u);
-        M->c_query = 16;
     }
     if (kk > 64 && !f64) {
         // Neighbourhoods wider than a wavefront: pooled exact search (the
         // screening rows above still serve the queries' nearest-point search).
+        MCHK(read_maxima());
         ExactArgs ea{};
         ea.X = M->X;
         ea.n = n;
@@ -782,6 +796,7 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
                                    M->tile_c, M->tile_r, s),
                  "pruning rows");
             HCHK(launch_inverse_perm(perm, n, pinv, s), "pivot order");
+            MCHK(read_maxima());
             sa.Q = Xq2;
             sa.P = M->Xpp;
             sa.prune = 1;
@@ -791,7 +806,10 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
             sa.acc_coef = M->acc_coef;
             sa.nx_max = M->nx_max;
         }
-        if (prune) record(M, M->evb, EV_PREP, s);  // the pivot order counts as ingest
+        if (prune)
+            record(M, M->evb, EV_PREP, s);  // the pivot order counts as ingest
+        else
+            MCHK(read_maxima());
         HCHK(launch_screen(geom, sa, s), "screen");
         record(M, M->evb, EV_SCREEN, s);
         RerankArgs ra{};

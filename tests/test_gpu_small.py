@@ -186,6 +186,17 @@ def test_invalid_arguments_are_rejected():
     with pytest.raises(f.FmgError) as e:
         f.fastmuygps_build(Xn, Y, 3, "matern", 1.5, 1.0, 0.1, precision="mixed")
     assert e.value.status == f.FMG_E_INVALID_ARG
+    # non-finite values on the pruned, wide and FP64 paths (the flag is read
+    # at different points of the build)
+    Xb, Yb, _ = synth.small(5000, 1, 3, ell=2, seed=21)
+    for prec, k, where in (("mixed", 8, "Y"), ("fp32", 70, "X"), ("fp64", 5, "X")):
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        Xt = torch.from_numpy(Xb).to(dt).cuda()
+        Yt = torch.from_numpy(Yb).to(dt).cuda()
+        (Yt if where == "Y" else Xt)[4321, 1] = float("inf")
+        with pytest.raises(f.FmgError) as e:
+            f.fastmuygps_build(Xt, Yt, k, "matern", 1.5, 1.0, 0.1, precision=prec)
+        assert e.value.status == f.FMG_E_INVALID_ARG
     with pytest.raises(f.FmgError) as e:
         f.fastmuygps_build(torch.zeros((10, 70), dtype=torch.float32, device="cuda"), Y, 3,
                            precision="mixed")
