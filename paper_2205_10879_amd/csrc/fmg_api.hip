@@ -295,6 +295,7 @@ fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_
     Scratch tmp;
     tmp.stream = s;
     record(M, M->evp, EV_START, s);
+    uint32_t *qperm = nullptr;  // pruned screens: queries in pivot order (also the gather's order)
     int32_t *nn = nn_out;
     if (!nn) {
         if (ws)
@@ -377,7 +378,7 @@ fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_
         sa.pool = pool;
         sa.cand = cand;
         sa.tq = tq;
-        uint32_t *qperm = nullptr, *qinv = nullptr;
+        uint32_t *qinv = nullptr;
         if (prune) {
             uint32_t *asg = nullptr, *asg2 = nullptr, *idx = nullptr;
             void *sort_tmp = nullptr, *Zq2 = nullptr;
@@ -456,6 +457,7 @@ fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_
         record(M, M->evp, EV_FALLBACK, s);
     }
     GatherArgs ga{};
+    ga.order = qperm;
     ga.X = M->X;
     ga.Z = Z;
     ga.nn = nn;

@@ -124,6 +124,7 @@ struct PrecomputeArgs {
 struct GatherArgs {
     const void *X;
     const void *Z;         // query coordinates
+    const uint32_t *order; // optional: wave w handles query order[w] (a permutation of [0, m))
     const int32_t *zrow;   // optional: query q is row zrow[q] of Z (else row q)
     const int32_t *nn;     // optional: coefficient row of query q (else q)
     const int32_t *N;      // neighbourhood rows [*, k]

@@ -6,7 +6,8 @@
 // contiguous values, so the wave reads C[j] as one contiguous k*ell block)
 // and the ell sums are DPP wave reductions.  Neighbourhoods wider than the
 // wave (k <= 256) give lane s the rows s + 64 r as well.  The
-// cross-covariance carries no nugget.
+// cross-covariance carries no nugget.  Queries may be taken in a given order
+// (nearby queries in consecutive waves share neighbour rows in the caches).
 #include "fmg_device.h"
 #include "fmg_kernels.h"
 
@@ -55,8 +56,9 @@ __device__ __forceinline__ T row_sqdist(const T *__restrict__ z, const T *__rest
 template <typename T, bool VEC, int ELLMAX, int KR>
 __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
     const int lane = lane_id();
-    const int64_t q = (int64_t)blockIdx.x * G_WAVES + (threadIdx.x >> 6);
-    if (q >= a.m) return;
+    const int64_t wq = (int64_t)blockIdx.x * G_WAVES + (threadIdx.x >> 6);
+    if (wq >= a.m) return;
+    const int64_t q = a.order ? (int64_t)a.order[wq] : wq;
     const T *__restrict__ X = (const T *)a.X;
     const T *__restrict__ Z = (const T *)a.Z;
     const T *__restrict__ C = (const T *)a.C;
