@@ -378,7 +378,6 @@ fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_
         sa.pool = pool;
         sa.cand = cand;
         sa.tq = tq;
-        uint32_t *qinv = nullptr;
         if (prune) {
             uint32_t *asg = nullptr, *asg2 = nullptr, *idx = nullptr;
             void *sort_tmp = nullptr, *Zq2 = nullptr;
@@ -394,13 +393,11 @@ fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_
             HIPCHK(tmp.alloc(&Zq2, (size_t)m_pad * g.row_bytes), "scratch");
             HIPCHK(tmp.alloc((void **)&nzq, (size_t)m_pad * 4), "scratch");
             HIPCHK(tmp.alloc((void **)&rot, (size_t)(m_pad / SCREEN_QPB) * 4), "scratch");
-            HIPCHK(tmp.alloc((void **)&qinv, (size_t)m * 4), "scratch");
             HIPCHK(launch_prune_queries((const float *)M->X, M->n, (const float *)Z, m, M->d, M->mu,
                                         sort_tmp, sort_bytes, M->cell + prune_pivots(M->n) + 1,
                                         asg, asg2, idx, qperm, g, Zq, nzz,
                                         m_pad, Zq2, nzq, M->cell, rot, s),
                    "query order");
-            HIPCHK(launch_inverse_perm(qperm, m, qinv, s), "query order");
             sa.Q = Zq2;
             sa.P = M->Xpp;
             sa.prune = 1;
@@ -416,7 +413,7 @@ fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_
         record(M, M->evp, EV_SCREEN, s);
         RerankArgs ra{};
         if (prune) {  // screen rows and indices are in pivot order
-            ra.row_of = qinv;
+            ra.order = qperm;
             ra.cand_idx = M->perm;
             ra.n_idx = M->n;
         }
@@ -763,11 +760,11 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
         sa.tq = tq;
         // Tile pruning: screen the self-join in nearest-pivot order, skipping
         // tiles whose bounding balls no query of a wavefront can reach; the
-        // re-rank reads each row's candidates through the inverse order and
-        // maps their indices back.
+        // re-rank takes the rows in the same order and maps the candidates'
+        // indices back.
         const bool prune = geom.mode == SCREEN_BF16 && !(flags & FMG_FLAG_NO_PRUNE) &&
                            prune_pivots(n) > 1 && d <= 64;
-        uint32_t *perm = nullptr, *pinv = nullptr;
+        uint32_t *perm = nullptr;
         if (prune) {
             uint32_t *asg = nullptr, *asg2 = nullptr, *idx = nullptr;
             void *sort_tmp = nullptr, *Xq2 = nullptr;
@@ -789,7 +786,6 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
             HCHK(tmp.alloc(&sort_tmp, sort_bytes), "scratch");
             HCHK(tmp.alloc(&Xq2, (size_t)n_pad * geom.row_bytes), "scratch");
             HCHK(tmp.alloc((void **)&nzq, (size_t)n_pad * 4), "scratch");
-            HCHK(tmp.alloc((void **)&pinv, (size_t)n * 4), "scratch");
             HCHK(launch_prune_order((const float *)M->X, n, d, M->mu, sort_tmp, sort_bytes,
                                     M->cell + npiv + 1, asg, asg2, idx, perm, s),
                  "pivot order");
@@ -797,7 +793,6 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
             HCHK(launch_prune_rows(geom, Xq, M->Xp, nzx, perm, n, n_pad, d, Xq2, M->Xpp, nzq,
                                    M->tile_c, M->tile_r, s),
                  "pruning rows");
-            HCHK(launch_inverse_perm(perm, n, pinv, s), "pivot order");
             MCHK(read_maxima());
             sa.Q = Xq2;
             sa.P = M->Xpp;
@@ -816,7 +811,7 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
         record(M, M->evb, EV_SCREEN, s);
         RerankArgs ra{};
         if (prune) {  // screen rows and indices are in pivot order
-            ra.row_of = pinv;
+            ra.order = perm;
             ra.cand_idx = perm;
             ra.n_idx = n;
         }

@@ -75,9 +75,11 @@ struct RerankArgs {
     int out_stride;
     int32_t *fb_list;    // rows that failed the certificate
     int32_t *fb_count;
-    // Optional (screens run in a pivot order): the cand / tq row of query q,
-    // and the training index of a screened index below n_idx.
-    const uint32_t *row_of;
+    // Optional (screens run in a pivot order): wave w handles query order[w],
+    // whose candidates are cand / tq row w (nearby queries in consecutive
+    // waves share candidate rows in the caches), and a screened index below
+    // n_idx maps to training index cand_idx[index].
+    const uint32_t *order;
     const uint32_t *cand_idx;
     int64_t n_idx;
 };
@@ -203,8 +205,8 @@ hipError_t launch_loo_grad(bool f64, const GradArgs &a, double *part, double *ou
 
 // Tile pruning of the build screen (fmg_prune.hip): the order of the training
 // points by nearest pivot (perm), the screening rows and query norms gathered
-// into it with the per-tile centroid rows and radii, and the inverse order
-// through which the re-rank reads the screen's output.
+// into it with the per-tile centroid rows and radii (the re-rank then takes
+// the rows in the same order).
 int prune_pivots(int64_t n);
 hipError_t prune_sort_bytes(int64_t n, size_t *bytes);
 // label [P]: pivot labels along a nearest-neighbour chain (written here,
@@ -217,8 +219,6 @@ hipError_t launch_prune_rows(const ScreenGeom &g, const void *Qrows, const void 
                              const double *nz, const uint32_t *perm, int64_t n, int64_t n_pad,
                              int d, void *Qout, void *Pout, float *nzq, void *tile_c,
                              float *tile_r, hipStream_t s);
-// inv[perm[i]] = i for i < n.
-hipError_t launch_inverse_perm(const uint32_t *perm, int64_t n, uint32_t *inv, hipStream_t s);
 // cell[j], j <= P: first position of pivot j in the pivot order.
 hipError_t launch_cell_starts(const uint32_t *asg_sorted, int64_t n, int P, int32_t *cell,
                               hipStream_t s);

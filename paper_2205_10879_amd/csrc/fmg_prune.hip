@@ -16,9 +16,9 @@
 //      BF16 (so it is an exact point of the screened space) and written as a
 //      candidate row, and the FP64 radius max ||x~ - c~|| over the tile's real
 //      rows, rounded up;
-//   5. the inverse order, through which the re-rank reads each row's
-//      candidates and maps their indices back to training indices, so that
-//      the certificate runs unchanged.
+//   5. the re-rank takes the rows in the same order and maps each
+//      candidate's index back to its training index, so that the certificate
+//      runs unchanged.
 #include <hipcub/hipcub.hpp>
 
 #include "fmg_device.h"
@@ -215,12 +215,6 @@ __global__ __launch_bounds__(64) void tile_bounds_kernel(const uint16_t *__restr
     }
 }
 
-__global__ __launch_bounds__(256) void inverse_perm_kernel(const uint32_t *__restrict__ perm,
-                                                           int64_t n, uint32_t *__restrict__ inv) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) inv[perm[i]] = (uint32_t)i;
-}
-
 // cell[j] = first position of pivot j in the sorted assignment (j <= P).
 __global__ __launch_bounds__(256) void cell_start_kernel(const uint32_t *__restrict__ asg_sorted,
                                                          int64_t n, int P,
@@ -297,13 +291,6 @@ hipError_t launch_prune_rows(const ScreenGeom &g, const void *Qrows, const void 
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(tile_bounds_kernel, dim3((unsigned)(n_pad / SCREEN_TILE)), dim3(64), 0, s,
                        (const uint16_t *)Pout, n, d, g.kp, (uint16_t *)tile_c, tile_r);
-    return hipGetLastError();
-}
-
-hipError_t launch_inverse_perm(const uint32_t *perm, int64_t n, uint32_t *inv, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(inverse_perm_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, perm,
-                       n, inv);
     return hipGetLastError();
 }
 

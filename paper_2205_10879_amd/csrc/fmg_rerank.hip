@@ -30,8 +30,9 @@ __global__ __launch_bounds__(256) void rerank_kernel(RerankArgs a) {
     extern __shared__ double zsh[];
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
-    const int64_t q = (int64_t)blockIdx.x * RR_WAVES + wave;
-    if (q >= a.m) return;
+    const int64_t w = (int64_t)blockIdx.x * RR_WAVES + wave;
+    if (w >= a.m) return;
+    const int64_t q = a.order ? (int64_t)a.order[w] : w;  // query (output row)
     double *z = zsh + wave * a.d;
     const float *__restrict__ X = (const float *)a.X;
     const float *__restrict__ Zc = (const float *)a.Zc;
@@ -39,9 +40,7 @@ __global__ __launch_bounds__(256) void rerank_kernel(RerankArgs a) {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 
-    // row of this query in the screen's output (queries screened in a pivot
-    // order), and screened indices mapped to training indices
-    const int64_t cq = a.row_of ? (int64_t)a.row_of[q] : q;
+    const int64_t cq = w;  // its row of the screen's output
     const int total = a.splits * a.c;
     XKey list = xkey_empty();
     for (int base = 0; base < total; base += 64) {
