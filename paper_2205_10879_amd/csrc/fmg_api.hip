@@ -877,6 +877,7 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
     pa.inv_rho = M->inv_rho;
     pa.amp = M->amp;
     pa.noise = hyper->noise_var;
+    pa.order = M->perm;  // pivot order of a pruned screen: nearby points run together
     const bool refine = prec == FMG_PREC_MIXED && !(flags & FMG_FLAG_NO_REFINE);
     HCHK(launch_precompute(f64, refine, pa, s), "precompute");
     record(M, M->evb, EV_LAST, s);

@@ -121,6 +121,10 @@ struct PrecomputeArgs {
                        // any point works: kernel values depend on differences only
     int kc;            // kernel code (fmg_device.h)
     double inv_rho, amp, noise;
+    // optional: workgroup b factors point order[b] (a permutation of [0, n);
+    // FP32 / mixed kernel), so that nearby points run together and share
+    // neighbour rows in the caches
+    const uint32_t *order;
 };
 
 struct GatherArgs {

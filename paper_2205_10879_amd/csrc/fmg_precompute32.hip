@@ -309,8 +309,8 @@ __device__ __forceinline__ void chol_steps(float (&K)[KMAX], float (&y)[ELLMAX],
 template <int KMAX, int ELLMAX, bool REFINE>
 __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
     extern __shared__ __align__(16) char smem[];
-    const int64_t i = blockIdx.x;
-    if (i >= P.n) return;
+    if ((int64_t)blockIdx.x >= P.n) return;
+    const int64_t i = P.order ? (int64_t)P.order[blockIdx.x] : (int64_t)blockIdx.x;
     const int a = threadIdx.x;
     const int k = P.k, d = P.d, ell = P.ell;
     const PcLayout L = pc_layout(k, d, KMAX, ELLMAX, REFINE);
