@@ -346,15 +346,19 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
             const int row = t * 16 + fr;
             f[t] = (row < k) ? xs[row * L.xs_ld + s + fk] : 0.0f;
         }
+        // tiles on and below the diagonal only: G is symmetric
 #pragma unroll
         for (int r = 0; r < NT; ++r)
 #pragma unroll
-            for (int c = 0; c < NT; ++c)
+            for (int c = 0; c <= r; ++c)
                 acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(f[r], f[c], acc[r][c], 0, 0, 0);
     }
     // Transpose through LDS, 32 columns at a time: tile (r, c), lane l holds
     // rows r*16 + 4*(l/16) + 0..3 of column c*16 + l%16; lane a then reads
-    // column a, which is its row (G is symmetric).
+    // column a, which is its row.  A tile above the diagonal is the transpose
+    // of tile (c, r): its lane l holds column c*16 + 4*(l/16) + 0..3 at row
+    // r*16 + l%16 (the same products summed in the same order, so G stays
+    // exactly symmetric).
     float K[KMAX];
 #pragma unroll
     for (int h = 0; h < NT; h += 2) {
@@ -362,8 +366,15 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
 #pragma unroll
         for (int r = 0; r < NT; ++r)
 #pragma unroll
-            for (int c = h; c < h + 2 && c < NT; ++c)
-                *(f32x4 *)(G + ((c - h) * 16 + fr) * L.g_ld + r * 16 + 4 * fk) = acc[r][c];
+            for (int c = h; c < h + 2 && c < NT; ++c) {
+                if (r >= c) {
+                    *(f32x4 *)(G + ((c - h) * 16 + fr) * L.g_ld + r * 16 + 4 * fk) = acc[r][c];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        G[((c - h) * 16 + 4 * fk + q) * L.g_ld + r * 16 + fr] = acc[c][r][q];
+                }
+            }
         lds_sync();
         const bool mine = a >= h * 16 && a < (h + 2) * 16 && a < KMAX;
         const float *col = G + (a - h * 16) * L.g_ld;
