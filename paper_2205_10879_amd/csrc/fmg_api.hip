@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -81,6 +82,69 @@ hipMemPool_t scratch_pool() {
     return pools[dev];
 }
 
+// Arrays of freed models, kept per device (up to ARRAY_CACHE_KEEP bytes) for
+// later builds to take at the same size: a build-and-free cycle then neither
+// maps nor unmaps memory (hipFree after kernels have touched the memory costs
+// milliseconds).  A failed allocation returns the cache to the device first.
+constexpr size_t ARRAY_CACHE_KEEP = 16ull << 30;
+
+struct ArrayCache {
+    std::mutex mu;
+    std::multimap<size_t, void *> blocks;  // size -> block
+    size_t bytes = 0;
+};
+
+ArrayCache &array_cache(int dev) {
+    static ArrayCache caches[MAX_DEVICES];
+    return caches[dev >= 0 && dev < MAX_DEVICES ? dev : 0];
+}
+
+void array_cache_clear(int dev) {
+    ArrayCache &c = array_cache(dev);
+    std::lock_guard<std::mutex> lock(c.mu);
+    for (auto &b : c.blocks) (void)hipFree(b.second);
+    c.blocks.clear();
+    c.bytes = 0;
+}
+
+hipError_t array_alloc(void **p, size_t bytes) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (dev >= 0 && dev < MAX_DEVICES) {
+        ArrayCache &c = array_cache(dev);
+        std::lock_guard<std::mutex> lock(c.mu);
+        auto it = c.blocks.find(bytes);
+        if (it != c.blocks.end()) {
+            *p = it->second;
+            c.bytes -= bytes;
+            c.blocks.erase(it);
+            return hipSuccess;
+        }
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if ((e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) && dev >= 0 &&
+        dev < MAX_DEVICES) {
+        (void)hipGetLastError();
+        array_cache_clear(dev);
+        e = hipMalloc(p, bytes);
+    }
+    return e;
+}
+
+// p (bytes long, from array_alloc on device dev) is no longer used by any work.
+void array_release(int dev, void *p, size_t bytes) {
+    if (dev >= 0 && dev < MAX_DEVICES) {
+        ArrayCache &c = array_cache(dev);
+        std::lock_guard<std::mutex> lock(c.mu);
+        if (c.bytes + bytes <= ARRAY_CACHE_KEEP) {
+            c.blocks.emplace(bytes, p);
+            c.bytes += bytes;
+            return;
+        }
+    }
+    (void)hipFree(p);
+}
+
 // Device scratch owned by one call: freed (stream-ordered, on the call's
 // stream) when the holder goes out of scope.
 struct Scratch {
@@ -109,12 +173,24 @@ struct Scratch {
 
 namespace {
 
+void **model_array(fmg_model *M, int idx);
+
 void free_model(fmg_model *M) {
     if (!M) return;
-    void *ptrs[] = {M->X,      M->N,      M->C,      M->Xp,     M->mu, M->Y,
-                    M->pred_fb, M->perm, M->Xpp, M->tile_c, M->tile_r, M->cell};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
+    // The arrays go back to the device's cache; nothing may still read them
+    // when a later build takes them.
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (cur != M->device) (void)hipSetDevice(M->device);
+    (void)hipDeviceSynchronize();
+    for (int a = 0; a < MA_COUNT; ++a) {
+        void **p = model_array(M, a);
+        if (*p) array_release(M->device, *p, M->arr_bytes[a]);
+        *p = nullptr;
+    }
+    if (M->pred_fb) array_release(M->device, M->pred_fb, M->fb_bytes);
+    M->pred_fb = nullptr;
+    if (cur >= 0 && cur != M->device) (void)hipSetDevice(cur);
     for (void *h : M->host)
         if (h) (void)hipHostFree(h);
     if (M->timing)
@@ -142,10 +218,11 @@ void record(fmg_model *M, hipEvent_t *ev, int idx, hipStream_t s) {
 // array whose size is recorded for offloading).
 fmg_status model_alloc(fmg_model *M, int idx, void **p, size_t bytes, const char *what) {
     if (bytes == 0) bytes = 16;
-    hipError_t e = hipMalloc(p, bytes);
+    hipError_t e = array_alloc(p, bytes);
     if (e != hipSuccess) return hip_fail(e, what);
     M->bytes += bytes;
     if (idx >= 0 && idx < MA_COUNT) M->arr_bytes[idx] = bytes;
+    else M->fb_bytes = bytes;
     return FMG_OK;
 }
 
@@ -503,7 +580,7 @@ fmg_status model_restore(fmg_model *M) {
     for (int a = 0; a < MA_COUNT; ++a) {
         if (!M->host[a]) continue;
         void **p = model_array(M, a);
-        hipError_t e = hipMalloc(p, M->arr_bytes[a]);
+        hipError_t e = array_alloc(p, M->arr_bytes[a]);
         if (e != hipSuccess) {
             // undo: the model stays offloaded
             for (int b = 0; b < a; ++b) {

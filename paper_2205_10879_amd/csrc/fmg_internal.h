@@ -57,6 +57,7 @@ struct fmg_model {
     // Residency: sizes of the movable arrays, and their host copies while the
     // model is offloaded (resident == false).
     size_t arr_bytes[fmg::MA_COUNT]{};
+    size_t fb_bytes = 0;  // the prediction fallback counter
     void *host[fmg::MA_COUNT]{};
     bool resident = true;
 
