@@ -25,7 +25,10 @@
  *     a stream-ordered memory pool of the device that the library creates on
  *     first use; freed scratch stays cached there, up to 16 GiB per device,
  *     until the process ends (larger peaks return to the device at the next
- *     synchronisation, and a failed allocation trims the cache and retries).
+ *     synchronisation, and a failed allocation trims the cache and retries);
+ *   - the device arrays of a freed model are kept by the library (up to
+ *     16 GiB per device) for later builds of the same sizes; an allocation
+ *     that fails returns them to the device first.
  */
 #ifndef FASTMUYGPS_H
 #define FASTMUYGPS_H

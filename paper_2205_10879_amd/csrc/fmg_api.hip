@@ -153,6 +153,17 @@ struct Scratch {
     ~Scratch() {
         for (void *p : ptrs) (void)hipFreeAsync(p, stream);
     }
+    // Stream-ordered free of p before the holder ends (work enqueued on the
+    // stream before this call may still use it).
+    void release(void *p) {
+        for (auto &q : ptrs)
+            if (q == p) {
+                (void)hipFreeAsync(q, stream);
+                q = ptrs.back();
+                ptrs.pop_back();
+                return;
+            }
+    }
     hipError_t alloc(void **p, size_t bytes) {
         if (bytes == 0) bytes = 16;
         hipMemPool_t pool = scratch_pool();
@@ -913,6 +924,11 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
         ra.fb_count = fbc;
         HCHK(launch_rerank(ra, s), "re-rank");
         record(M, M->evb, EV_RERANK, s);
+        // the screen's pools and candidate lists are dead after the re-rank:
+        // return them while the device still works (a large free costs
+        // milliseconds of host time)
+        tmp.release(pool);
+        tmp.release(cand);
         int hfb = 0;
         HCHK(hipMemcpyAsync(&hfb, fbc, 4, hipMemcpyDeviceToHost, s), "copy count");
         HCHK(hipStreamSynchronize(s), "sync");
