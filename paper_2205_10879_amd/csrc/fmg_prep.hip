@@ -85,50 +85,78 @@ __device__ __forceinline__ void wave_atomic_max_bits(unsigned long long *dst, do
     if (lane_id() == 0) atomicMax(dst, b);
 }
 
+// One thread per row; the row (kp = 64 BF16 values, 128 bytes) is assembled
+// in registers and written with 16-byte stores.
 __global__ __launch_bounds__(256) void prep_bf16_kernel(
     const float *__restrict__ X, int64_t n, int64_t n_pad, int d, const float *__restrict__ mu,
-    int kp, uint16_t *__restrict__ Q, uint16_t *__restrict__ P, double *__restrict__ e_out,
+    uint16_t *__restrict__ Q, uint16_t *__restrict__ P, double *__restrict__ e_out,
     double *__restrict__ nz_out, unsigned long long *emax_bits,
     unsigned long long *nxmax_bits) {
+    constexpr int KP = 64;
     const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    uint32_t qw[KP / 2], pw[KP / 2];  // pairs of BF16 values
+#pragma unroll
+    for (int w = 0; w < KP / 2; ++w) {
+        qw[w] = 0u;
+        pw[w] = 0u;
+    }
     // lanes past n_pad write nothing but still take part in the wave maxima
-    uint16_t *q = (Q && r < n_pad) ? Q + r * kp : nullptr;
-    uint16_t *p = (P && r < n_pad) ? P + r * kp : nullptr;
     double e = 0.0, nz = 0.0;
-    if (r >= n_pad) {
-    } else if (r >= n) {
-        // Padding candidate: a huge norm part keeps it out of every selection.
-        for (int c = 0; c < kp; ++c) {
-            if (q) q[c] = 0;
-            if (p) p[c] = 0;
+    if (r < n) {
+        const float *__restrict__ xr = X + r * d;
+        double e2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < KP; ++c) {
+            if (c < d) {
+                const double xc = (double)xr[c] - (double)mu[c];
+                const uint16_t h = f32_to_bf16_rn((float)xc);
+                const double xt = (double)bf16_to_f32(h);
+                const double diff = xc - xt;
+                e2 += diff * diff;
+                nz += xt * xt;
+                // -2 x~ is exact: a power-of-two scale
+                const uint16_t ph = f32_to_bf16_rn(-2.0f * bf16_to_f32(h));
+                qw[c >> 1] |= (uint32_t)h << (16 * (c & 1));
+                pw[c >> 1] |= (uint32_t)ph << (16 * (c & 1));
+            }
         }
-        if (p) p[d] = f32_to_bf16_rn(1.0e30f);
-    } else {
-    double e2 = 0.0;
-    for (int c = 0; c < d; ++c) {
-        const double xc = (double)X[r * d + c] - (double)mu[c];
-        const uint16_t h = f32_to_bf16_rn((float)xc);
-        const double xt = (double)bf16_to_f32(h);
-        const double diff = xc - xt;
-        e2 += diff * diff;
-        nz += xt * xt;
-        if (q) q[c] = h;
-        if (p) p[c] = f32_to_bf16_rn(-2.0f * bf16_to_f32(h));  // exact: a power-of-two scale
+        // norm split: nz = hi + mid + lo (+ a remainder below 2^-26 nz)
+        const uint16_t hi = f32_to_bf16_rn((float)nz);
+        const double r1 = nz - (double)bf16_to_f32(hi);
+        const uint16_t mid = f32_to_bf16_rn((float)r1);
+        const double r2 = r1 - (double)bf16_to_f32(mid);
+        const uint16_t lo = f32_to_bf16_rn((float)r2);
+        const uint16_t one = f32_to_bf16_rn(1.0f);
+#pragma unroll
+        for (int c = 0; c < KP; ++c) {
+            const int sh = 16 * (c & 1);
+            if (c >= d && c < d + 3) qw[c >> 1] |= (uint32_t)one << sh;
+            const uint16_t pv = (c == d) ? hi : (c == d + 1) ? mid : (c == d + 2) ? lo : 0;
+            pw[c >> 1] |= (uint32_t)pv << sh;
+        }
+        e = sqrt(e2) * (1.0 + 1.0e-12);
+        if (e_out) e_out[r] = e;
+        if (nz_out) nz_out[r] = nz;
+    } else if (r < n_pad) {
+        // Padding candidate: a huge norm part keeps it out of every selection.
+        const uint16_t big = f32_to_bf16_rn(1.0e30f);
+#pragma unroll
+        for (int c = 0; c < KP; ++c)
+            if (c == d) pw[c >> 1] |= (uint32_t)big << (16 * (c & 1));
     }
-    // norm split: nz = hi + mid + lo (+ a remainder below 2^-26 nz)
-    const uint16_t hi = f32_to_bf16_rn((float)nz);
-    const double r1 = nz - (double)bf16_to_f32(hi);
-    const uint16_t mid = f32_to_bf16_rn((float)r1);
-    const double r2 = r1 - (double)bf16_to_f32(mid);
-    const uint16_t lo = f32_to_bf16_rn((float)r2);
-    const uint16_t one = f32_to_bf16_rn(1.0f);
-    for (int c = d; c < kp; ++c) {
-        if (q) q[c] = (c < d + 3) ? one : 0;
-        if (p) p[c] = (c == d) ? hi : (c == d + 1) ? mid : (c == d + 2) ? lo : 0;
-    }
-    e = sqrt(e2) * (1.0 + 1.0e-12);
-    if (e_out) e_out[r] = e;
-    if (nz_out) nz_out[r] = nz;
+    if (r < n_pad) {
+        if (Q) {
+            uint4 *dst = (uint4 *)(Q + r * KP);
+#pragma unroll
+            for (int w = 0; w < KP / 8; ++w)
+                dst[w] = make_uint4(qw[4 * w], qw[4 * w + 1], qw[4 * w + 2], qw[4 * w + 3]);
+        }
+        if (P) {
+            uint4 *dst = (uint4 *)(P + r * KP);
+#pragma unroll
+            for (int w = 0; w < KP / 8; ++w)
+                dst[w] = make_uint4(pw[4 * w], pw[4 * w + 1], pw[4 * w + 2], pw[4 * w + 3]);
+        }
     }
     if (emax_bits) wave_atomic_max_bits(emax_bits, e);
     if (nxmax_bits) wave_atomic_max_bits(nxmax_bits, nz);
@@ -260,14 +288,16 @@ hipError_t launch_prep_rows(const ScreenGeom &g, const float *X, int64_t n, int6
                             double *nz_out, unsigned long long *emax_bits,
                             unsigned long long *nxmax_bits, hipStream_t s) {
     const unsigned blocks = (unsigned)((n_pad + 255) / 256);
-    if (g.mode == SCREEN_BF16)
+    if (g.mode == SCREEN_BF16) {
+        if (g.kp != 64 || d + 3 > 64) return hipErrorInvalidValue;
         hipLaunchKernelGGL(prep_bf16_kernel, dim3(blocks), dim3(256), 0, s, X, n, n_pad, d, mu,
-                           g.kp, (uint16_t *)Qrows, (uint16_t *)Prows, e_out, nz_out, emax_bits,
+                           (uint16_t *)Qrows, (uint16_t *)Prows, e_out, nz_out, emax_bits,
                            nxmax_bits);
-    else
+    } else {
         hipLaunchKernelGGL(prep_f32_kernel, dim3(blocks), dim3(256), 0, s, X, n, n_pad, d, mu,
                            g.kp, (float *)Qrows, (float *)Prows, e_out, nz_out, emax_bits,
                            nxmax_bits);
+    }
     return hipGetLastError();
 }
 
