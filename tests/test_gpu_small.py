@@ -218,3 +218,17 @@ def test_not_positive_definite_rows_are_flagged():
     Cg = model.coeffs().cpu().numpy()
     assert np.array_equal(np.isnan(Cg).all(axis=(1, 2)), st != 0)
     model.free()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "mixed"])
+def test_repeated_builds_of_one_shape(prec):
+    # A freed model's arrays are reused by the next build of the same sizes:
+    # every build must still produce its own, exact result.
+    X1, Y1, Z1 = synth.small(5000, 64, 4, ell=2, seed=31)
+    X2, Y2, Z2 = synth.small(5000, 64, 4, ell=2, seed=32)
+    first = run(prec, X1, Y1, Z1, 16, "matern", 2.5, 1.0, 1e-2)[3]
+    second = run(prec, X2, Y2, Z2, 16, "matern", 2.5, 1.0, 1e-2)
+    check_against_oracle(prec, *second[:3], 16, "matern", 2.5, 1.0, 1e-2, second[3])
+    again = run(prec, X1, Y1, Z1, 16, "matern", 2.5, 1.0, 1e-2)[3]
+    for key in ("N", "C", "mu", "nn"):
+        assert np.array_equal(first[key], again[key]), key
