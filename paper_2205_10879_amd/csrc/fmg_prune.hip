@@ -30,7 +30,11 @@ namespace {
 
 // Nearest pivot of points Pts [n, d]; pivot j is training row j * stride of X.
 // Coordinates are zero padded to DP (a multiple of 16 covering d), so the
-// distance loop has no guards and reads each pivot row as 16-byte vectors.
+// loop has no guards and reads each pivot row as 16-byte vectors.  The
+// nearest pivot minimises ||p_j||^2 - 2 x.p_j (||x||^2 is common to all j):
+// one FMA per coordinate.  Any assignment serves the pruning (the tile radii
+// are measured on the tiles' actual rows), so the rounding of this form is
+// harmless.
 template <int DP>
 __global__ __launch_bounds__(256) void pivot_assign_kernel(const float *__restrict__ X,
                                                            const float *__restrict__ Pts,
@@ -40,10 +44,17 @@ __global__ __launch_bounds__(256) void pivot_assign_kernel(const float *__restri
                                                            const int32_t *__restrict__ label,
                                                            uint32_t *__restrict__ asg,
                                                            uint32_t *__restrict__ idx) {
-    extern __shared__ __align__(16) float piv[];  // [P, DP] centred pivots, zero past d
+    extern __shared__ __align__(16) float piv[];  // [P, DP] centred pivots, zero past d; [P] norms
+    float *pn = piv + P * DP;
     for (int e = threadIdx.x; e < P * DP; e += blockDim.x) {
         const int j = e / DP, c = e % DP;
         piv[e] = c < d ? X[(int64_t)j * stride * d + c] - mu[c] : 0.0f;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < P; j += blockDim.x) {
+        float s = 0.0f;
+        for (int c = 0; c < DP; ++c) s = fmaf(piv[j * DP + c], piv[j * DP + c], s);
+        pn[j] = s;
     }
     __syncthreads();
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -55,18 +66,16 @@ __global__ __launch_bounds__(256) void pivot_assign_kernel(const float *__restri
     uint32_t bj = 0;
     for (int j = 0; j < P; ++j) {
         const float4 *pj = (const float4 *)(piv + j * DP);
-        float s0 = 0.0f, s1 = 0.0f;
+        float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
 #pragma unroll
         for (int c4 = 0; c4 < DP / 4; ++c4) {
             const float4 v = pj[c4];
-            const float t0 = x[4 * c4] - v.x, t1 = x[4 * c4 + 1] - v.y;
-            const float t2 = x[4 * c4 + 2] - v.z, t3 = x[4 * c4 + 3] - v.w;
-            s0 = fmaf(t0, t0, s0);
-            s1 = fmaf(t1, t1, s1);
-            s0 = fmaf(t2, t2, s0);
-            s1 = fmaf(t3, t3, s1);
+            s0 = fmaf(x[4 * c4], v.x, s0);
+            s1 = fmaf(x[4 * c4 + 1], v.y, s1);
+            s2 = fmaf(x[4 * c4 + 2], v.z, s2);
+            s3 = fmaf(x[4 * c4 + 3], v.w, s3);
         }
-        const float sj = s0 + s1;
+        const float sj = fmaf(-2.0f, (s0 + s1) + (s2 + s3), pn[j]);
         if (sj < best) {
             best = sj;
             bj = (uint32_t)j;
@@ -133,7 +142,9 @@ template <int DP>
 void launch_assign_t(const float *X, const float *Pts, int64_t n, int d, const float *mu, int P,
                      int64_t stride, const int32_t *label, uint32_t *asg, uint32_t *idx,
                      hipStream_t s) {
-    const size_t shm = (size_t)P * DP * sizeof(float);
+    const size_t shm = (size_t)P * (DP + 1) * sizeof(float);
+    (void)hipFuncSetAttribute((const void *)pivot_assign_kernel<DP>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL((pivot_assign_kernel<DP>), dim3((unsigned)((n + 255) / 256)), dim3(256), shm,
                        s, X, Pts, n, d, mu, P, stride, label, asg, idx);
 }
@@ -166,37 +177,52 @@ __global__ __launch_bounds__(256) void gather_rows_kernel(const uint4 *__restric
     if (ch == 0) nzq[i] = i < n ? (float)nz[src] : 0.0f;
 }
 
-// One wave per tile of 64 BF16 candidate rows [-2 x~, norm parts, 0 ...].
+// One wave per tile of 64 BF16 candidate rows [-2 x~, norm parts, 0 ...]
+// (kp = 64).  The rows go through LDS so that lane c sums column c; then
+// every lane measures its own row against the centroid.
 __global__ __launch_bounds__(64) void tile_bounds_kernel(const uint16_t *__restrict__ Prows,
-                                                         int64_t n, int d, int kp,
+                                                         int64_t n, int d,
                                                          uint16_t *__restrict__ cen,
                                                          float *__restrict__ rad) {
+    constexpr int KP = 64;
+    __shared__ __align__(16) uint16_t rows[SCREEN_TILE * KP];
+    __shared__ float ctr[KP];
     const int64_t tile = blockIdx.x;
     const int lane = threadIdx.x;
     const int64_t row = tile * SCREEN_TILE + lane;
     const bool real = row < n;
-    const uint16_t *pr = Prows + row * kp;
     const int cnt = (int)__popcll(__ballot(real));
-    uint16_t *crow = cen + tile * kp;
+    uint16_t *crow = cen + tile * KP;
     if (cnt == 0) {  // padding only: never skipped
-        for (int c = lane; c < kp; c += 64) crow[c] = 0;
-        if (lane == 0) {
-            crow[d] = f32_to_bf16_rn(1.0e30f);
-            rad[tile] = INFINITY;
-        }
+        crow[lane] = lane == d ? f32_to_bf16_rn(1.0e30f) : (uint16_t)0;
+        if (lane == 0) rad[tile] = INFINITY;
         return;
     }
+    {
+        const uint4 *src = (const uint4 *)(Prows + row * KP);
+        uint4 *dst = (uint4 *)(rows + lane * KP);
+#pragma unroll
+        for (int w = 0; w < KP / 8; ++w) dst[w] = real ? src[w] : make_uint4(0u, 0u, 0u, 0u);
+    }
+    __syncthreads();
     // centroid of the rows' x~ = -(row) / 2 (exact), rounded to BF16
-    double r2 = 0.0, nc = 0.0;
-    for (int c = 0; c < d; ++c) {
-        const double x = real ? -0.5 * (double)bf16_to_f32(pr[c]) : 0.0;
-        const double m = wave_sum_f64(x) / cnt;
-        const uint16_t h = f32_to_bf16_rn((float)m);
-        const double ct = (double)bf16_to_f32(h);
-        const double t = x - ct;
-        if (real) r2 += t * t;
-        nc += ct * ct;
-        if (lane == 0) crow[c] = f32_to_bf16_rn(-2.0f * bf16_to_f32(h));  // exact scale
+    double ct = 0.0;
+    if (lane < d) {
+        double sum = 0.0;
+        for (int r = 0; r < SCREEN_TILE; ++r) sum += -0.5 * (double)bf16_to_f32(rows[r * KP + lane]);
+        const uint16_t h = f32_to_bf16_rn((float)(sum / cnt));
+        ct = (double)bf16_to_f32(h);
+        crow[lane] = f32_to_bf16_rn(-2.0f * bf16_to_f32(h));  // exact scale
+    }
+    ctr[lane] = (float)ct;  // exact: a BF16 value
+    const double nc = wave_sum_f64(ct * ct);
+    __syncthreads();
+    double r2 = 0.0;
+    if (real) {
+        for (int c = 0; c < d; ++c) {
+            const double t = -0.5 * (double)bf16_to_f32(rows[lane * KP + c]) - (double)ctr[c];
+            r2 += t * t;
+        }
     }
     double mx = r2;
 #pragma unroll
@@ -204,15 +230,15 @@ __global__ __launch_bounds__(64) void tile_bounds_kernel(const uint16_t *__restr
         const double o = __shfl_xor(mx, w);
         mx = o > mx ? o : mx;
     }
-    if (lane == 0) {
-        const uint16_t hi = f32_to_bf16_rn((float)nc);
-        const double q1 = nc - (double)bf16_to_f32(hi);
-        const uint16_t mid = f32_to_bf16_rn((float)q1);
-        const double q2 = q1 - (double)bf16_to_f32(mid);
-        const uint16_t lo = f32_to_bf16_rn((float)q2);
-        for (int c = d; c < kp; ++c) crow[c] = (c == d) ? hi : (c == d + 1) ? mid : (c == d + 2) ? lo : 0;
-        rad[tile] = (float)(sqrt(mx) * (1.0 + 1.0e-6)) * (1.0f + 1.0e-6f);
-    }
+    // norm parts of the centroid row
+    const uint16_t hi = f32_to_bf16_rn((float)nc);
+    const double q1 = nc - (double)bf16_to_f32(hi);
+    const uint16_t mid = f32_to_bf16_rn((float)q1);
+    const double q2 = q1 - (double)bf16_to_f32(mid);
+    const uint16_t lo = f32_to_bf16_rn((float)q2);
+    if (lane >= d)
+        crow[lane] = (lane == d) ? hi : (lane == d + 1) ? mid : (lane == d + 2) ? lo : (uint16_t)0;
+    if (lane == 0) rad[tile] = (float)(sqrt(mx) * (1.0 + 1.0e-6)) * (1.0f + 1.0e-6f);
 }
 
 // cell[j] = first position of pivot j in the sorted assignment (j <= P).
@@ -289,8 +315,9 @@ hipError_t launch_prune_rows(const ScreenGeom &g, const void *Qrows, const void 
                        (uint4 *)Qout, (uint4 *)Pout, nzq);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (g.kp != 64) return hipErrorInvalidValue;
     hipLaunchKernelGGL(tile_bounds_kernel, dim3((unsigned)(n_pad / SCREEN_TILE)), dim3(64), 0, s,
-                       (const uint16_t *)Pout, n, d, g.kp, (uint16_t *)tile_c, tile_r);
+                       (const uint16_t *)Pout, n, d, (uint16_t *)tile_c, tile_r);
     return hipGetLastError();
 }
 
