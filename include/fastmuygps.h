@@ -28,7 +28,8 @@
  *     synchronisation, and a failed allocation trims the cache and retries);
  *   - the device arrays of a freed model are kept by the library (up to
  *     16 GiB per device) for later builds of the same sizes; an allocation
- *     that fails returns them to the device first.
+ *     that fails returns them to the device first, and
+ *     fastmuygps_release_cached() returns both caches at once.
  */
 #ifndef FASTMUYGPS_H
 #define FASTMUYGPS_H
@@ -341,6 +342,12 @@ const char *fastmuygps_last_error(void);
 
 /* Library version string, e.g. "fastmuygps-gfx950 0.1". */
 const char *fastmuygps_version(void);
+
+/* Return the device memory the library keeps cached on the current device
+ * (the arrays of freed models and the freed scratch of earlier calls) to the
+ * device.  Synchronises the device first; no call may be running on it.
+ * Later calls allocate afresh.  FMG_E_DEVICE on a HIP error. */
+fmg_status fastmuygps_release_cached(void);
 
 #ifdef __cplusplus
 }

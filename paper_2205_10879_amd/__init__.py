@@ -48,7 +48,7 @@ EXPORTS = ("fastmuygps_build", "fastmuygps_predict", "fastmuygps_info", "fastmuy
            "fastmuygps_server_create", "fastmuygps_server_add_model",
            "fastmuygps_server_remove_model", "fastmuygps_server_submit", "fastmuygps_server_wait",
            "fastmuygps_server_stats", "fastmuygps_server_reset_stats",
-           "fastmuygps_server_destroy")
+           "fastmuygps_server_destroy", "fastmuygps_release_cached")
 
 
 class FmgHyper(ctypes.Structure):
@@ -130,6 +130,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fastmuygps_last_error.restype = ctypes.c_char_p
     lib.fastmuygps_version.argtypes = []
     lib.fastmuygps_version.restype = ctypes.c_char_p
+    lib.fastmuygps_release_cached.argtypes = []
+    lib.fastmuygps_release_cached.restype = ctypes.c_int
     lib.fastmuygps_server_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(FmgServerOpts),
                                              ctypes.POINTER(P)]
     lib.fastmuygps_server_create.restype = ctypes.c_int
@@ -186,6 +188,12 @@ def _dev_ptr(t: torch.Tensor, dtype, name: str) -> ctypes.c_void_p:
 
 def version() -> str:
     return lib().fastmuygps_version().decode()
+
+
+def release_cached() -> None:
+    """Return the device memory cached by the library (freed models' arrays,
+    freed scratch) on the current device."""
+    _check(lib().fastmuygps_release_cached())
 
 
 class Model:

@@ -623,6 +623,17 @@ const char *fastmuygps_last_error(void) { return g_err.c_str(); }
 
 const char *fastmuygps_version(void) { return "fastmuygps-gfx950 0.1"; }
 
+fmg_status fastmuygps_release_cached(void) {
+    g_err.clear();
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev), "hipGetDevice");
+    HIPCHK(hipDeviceSynchronize(), "sync");
+    if (dev >= 0 && dev < MAX_DEVICES) array_cache_clear(dev);
+    hipMemPool_t pool = scratch_pool();
+    if (pool) HIPCHK(hipMemPoolTrimTo(pool, 0), "hipMemPoolTrimTo");
+    return FMG_OK;
+}
+
 void fastmuygps_free(fmg_model *model) { free_model(model); }
 
 fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, int32_t ell,

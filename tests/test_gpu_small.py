@@ -232,3 +232,13 @@ def test_repeated_builds_of_one_shape(prec):
     again = run(prec, X1, Y1, Z1, 16, "matern", 2.5, 1.0, 1e-2)[3]
     for key in ("N", "C", "mu", "nn"):
         assert np.array_equal(first[key], again[key]), key
+
+
+def test_release_cached_memory():
+    f = fmg()
+    X, Y, Z = synth.small(5000, 64, 4, ell=1, seed=41)
+    out1 = run("mixed", X, Y, Z, 8, "rbf", 0.0, 1.0, 1e-2)[3]
+    f.release_cached()  # the freed model's arrays and the scratch go back to the device
+    out2 = run("mixed", X, Y, Z, 8, "rbf", 0.0, 1.0, 1e-2)[3]
+    for key in ("N", "C", "mu", "nn"):
+        assert np.array_equal(out1[key], out2[key]), key
