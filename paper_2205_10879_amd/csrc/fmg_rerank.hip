@@ -42,8 +42,27 @@ __global__ __launch_bounds__(256) void rerank_kernel(RerankArgs a) {
 
     const int64_t cq = w;  // its row of the screen's output
     const int total = a.splits * a.c;
+    const double nz = a.nzq[q];
+    const double A = a.acc_coef * (2.01 * a.nx_max + nz) + 1.0e-6 * a.nx_max;
+    // Lower bound on the exact distance of any point whose screened value is
+    // at least S (the certificate's bound).
+    auto lower_bound = [&](double S) {
+        const double lb2 = S + nz - A;
+        return (lb2 > 0.0 ? sqrt(lb2) : 0.0) - a.e_max - a.eq[q];
+    };
     XKey list = xkey_empty();
     for (int base = 0; base < total; base += 64) {
+        if (base > 0 && a.splits == 1) {
+            // One sorted list: once the bound of the next screened value
+            // exceeds the current k-th exact distance, no later candidate
+            // can enter the k nearest.
+            const uint64_t nk = a.cand[cq * a.c + base];
+            if (nk == SKEY_EMPTY) break;
+            const XKey cur = readlane_x(list, a.k - 1);
+            if (cur.p != 0xffffffffu &&
+                lower_bound((double)skey_val(nk)) > sqrt(dkey_inv(cur.d)) * (1.0 + 1.0e-12) + 1.0e-300)
+                break;
+        }
         const int slot = base + lane;
         XKey key = xkey_empty();
         if (slot < total) {
@@ -78,12 +97,8 @@ __global__ __launch_bounds__(256) void rerank_kernel(RerankArgs a) {
     } else if (kk.p == 0xffffffffu) {
         ok = false;
     } else {
-        const double nz = a.nzq[q];
-        const double A = a.acc_coef * (2.01 * a.nx_max + nz) + 1.0e-6 * a.nx_max;
-        const double lb2 = tmin + nz - A;
-        const double lb = (lb2 > 0.0 ? sqrt(lb2) : 0.0) - a.e_max - a.eq[q];
         const double dk = sqrt(dkey_inv(kk.d));
-        ok = lb > dk * (1.0 + 1.0e-12) + 1.0e-300;
+        ok = lower_bound(tmin) > dk * (1.0 + 1.0e-12) + 1.0e-300;
     }
 
     int32_t *o = a.out + q * (int64_t)a.out_stride;
