@@ -171,6 +171,8 @@ __global__ __launch_bounds__(256) void exact_wide_kernel(ExactArgs a) {
     const T *__restrict__ X = (const T *)a.X;
     const T *__restrict__ Qc = (const T *)a.Qc;
     const uint64_t lt = (1ull << lane) - 1ull;
+    // FP64 rows of even length on a 16-byte aligned base load as double2
+    const bool vec2 = sizeof(T) == 8 && (a.d % 2) == 0 && ((uintptr_t)a.X & 15) == 0;
     const int64_t items = a.count ? (int64_t)(*a.count) : a.nq;
     for (int64_t w = (int64_t)blockIdx.x * EXACT_WAVES + wave; w < items;
          w += (int64_t)gridDim.x * EXACT_WAVES) {
@@ -186,10 +188,23 @@ __global__ __launch_bounds__(256) void exact_wide_kernel(ExactArgs a) {
             if (p < a.n && p != self) {
                 const T *__restrict__ xp = X + p * a.d;
                 double s = 0.0;
-                for (int c = 0; c < a.d; ++c) {
-                    const double t = z[c] - (double)xp[c];
-                    const double t2 = t * t;
-                    s = s + t2;
+                if (vec2) {
+                    // the row in 16-byte loads, coordinates still summed in order
+                    for (int c = 0; c < a.d; c += 2) {
+                        const double2 v = *(const double2 *)(xp + c);
+                        const double t0 = z[c] - v.x;
+                        const double u0 = t0 * t0;
+                        s = s + u0;
+                        const double t1 = z[c + 1] - v.y;
+                        const double u1 = t1 * t1;
+                        s = s + u1;
+                    }
+                } else {
+                    for (int c = 0; c < a.d; ++c) {
+                        const double t = z[c] - (double)xp[c];
+                        const double t2 = t * t;
+                        s = s + t2;
+                    }
                 }
                 key = XKey{dkey(s), (uint32_t)p};
             }
