@@ -157,74 +157,112 @@ __device__ __forceinline__ int wide_select(uint64_t *__restrict__ pd, uint32_t *
     return keep;
 }
 
+// Neighbourhoods wider than the wave (64 < k <= 256): each wave serves two
+// queries, so every candidate row it loads is measured against both; each
+// query keeps a pool of up to WIDE_POOL keys under its running k-th key.
+constexpr int WIDE_Q = 2;  // queries per wave
+
 template <typename T>
 __global__ __launch_bounds__(256) void exact_wide_kernel(ExactArgs a) {
 #pragma clang fp contract(off)
-    extern __shared__ __align__(16) char wsm[];  // z [4][d], pool keys [4][512], indices [4][512]
+    // z [4][WIDE_Q][d], pool keys [4][WIDE_Q][512], indices [4][WIDE_Q][512]
+    extern __shared__ __align__(16) char wsm[];
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
-    double *z = (double *)wsm + wave * a.d;
-    uint64_t *pd = (uint64_t *)(wsm + (size_t)EXACT_WAVES * a.d * 8) + wave * WIDE_POOL;
-    uint32_t *pp = (uint32_t *)(wsm + (size_t)EXACT_WAVES * a.d * 8 +
-                                (size_t)EXACT_WAVES * WIDE_POOL * 8) +
-                   wave * WIDE_POOL;
+    double *zw = (double *)wsm + wave * WIDE_Q * a.d;
+    uint64_t *pdw = (uint64_t *)(wsm + (size_t)EXACT_WAVES * WIDE_Q * a.d * 8) +
+                    wave * WIDE_Q * WIDE_POOL;
+    uint32_t *ppw = (uint32_t *)(wsm + (size_t)EXACT_WAVES * WIDE_Q * a.d * 8 +
+                                 (size_t)EXACT_WAVES * WIDE_Q * WIDE_POOL * 8) +
+                    wave * WIDE_Q * WIDE_POOL;
     const T *__restrict__ X = (const T *)a.X;
     const T *__restrict__ Qc = (const T *)a.Qc;
     const uint64_t lt = (1ull << lane) - 1ull;
     // FP64 rows of even length on a 16-byte aligned base load as double2
     const bool vec2 = sizeof(T) == 8 && (a.d % 2) == 0 && ((uintptr_t)a.X & 15) == 0;
     const int64_t items = a.count ? (int64_t)(*a.count) : a.nq;
-    for (int64_t w = (int64_t)blockIdx.x * EXACT_WAVES + wave; w < items;
+    for (int64_t w = (int64_t)blockIdx.x * EXACT_WAVES + wave; w * WIDE_Q < items;
          w += (int64_t)gridDim.x * EXACT_WAVES) {
-        const int64_t q = a.list ? (int64_t)a.list[w] : w;
-        for (int c = lane; c < a.d; c += 64) z[c] = (double)Qc[q * a.d + c];
+        int64_t q[WIDE_Q], self[WIDE_Q];
+        bool act[WIDE_Q];
+        int cnt[WIDE_Q];
+        XKey kth[WIDE_Q];
+#pragma unroll
+        for (int h = 0; h < WIDE_Q; ++h) {
+            const int64_t it = w * WIDE_Q + h;
+            act[h] = it < items;
+            q[h] = !act[h] ? 0 : a.list ? (int64_t)a.list[it] : it;
+            self[h] = (a.loo && act[h]) ? q[h] : -1;
+            cnt[h] = 0;
+            kth[h] = xkey_empty();
+            for (int c = lane; c < a.d; c += 64)
+                zw[h * a.d + c] = act[h] ? (double)Qc[q[h] * a.d + c] : 0.0;
+        }
         wave_lds_fence();
-        const int64_t self = a.loo ? q : -1;
-        int cnt = 0;
-        XKey kth = xkey_empty();
         for (int64_t base = 0; base < a.n; base += 64) {
             const int64_t p = base + lane;
-            XKey key = xkey_empty();
-            if (p < a.n && p != self) {
+            double sd[WIDE_Q];
+#pragma unroll
+            for (int h = 0; h < WIDE_Q; ++h) sd[h] = 0.0;
+            if (p < a.n) {
                 const T *__restrict__ xp = X + p * a.d;
-                double s = 0.0;
                 if (vec2) {
                     // the row in 16-byte loads, coordinates still summed in order
                     for (int c = 0; c < a.d; c += 2) {
                         const double2 v = *(const double2 *)(xp + c);
-                        const double t0 = z[c] - v.x;
-                        const double u0 = t0 * t0;
-                        s = s + u0;
-                        const double t1 = z[c + 1] - v.y;
-                        const double u1 = t1 * t1;
-                        s = s + u1;
+#pragma unroll
+                        for (int h = 0; h < WIDE_Q; ++h) {
+                            const double t0 = zw[h * a.d + c] - v.x;
+                            const double u0 = t0 * t0;
+                            sd[h] = sd[h] + u0;
+                            const double t1 = zw[h * a.d + c + 1] - v.y;
+                            const double u1 = t1 * t1;
+                            sd[h] = sd[h] + u1;
+                        }
                     }
                 } else {
                     for (int c = 0; c < a.d; ++c) {
-                        const double t = z[c] - (double)xp[c];
-                        const double t2 = t * t;
-                        s = s + t2;
+                        const double xv = (double)xp[c];
+#pragma unroll
+                        for (int h = 0; h < WIDE_Q; ++h) {
+                            const double t = zw[h * a.d + c] - xv;
+                            const double t2 = t * t;
+                            sd[h] = sd[h] + t2;
+                        }
                     }
                 }
-                key = XKey{dkey(s), (uint32_t)p};
             }
-            const bool pass = xless(key, kth);
-            const uint64_t m = __ballot(pass);
-            if (m != 0) {
-                if (pass) {
-                    const int pos = cnt + __popcll(m & lt);
-                    pd[pos] = key.d;
-                    pp[pos] = key.p;
+#pragma unroll
+            for (int h = 0; h < WIDE_Q; ++h) {
+                if (!act[h]) continue;  // uniform
+                XKey key = xkey_empty();
+                if (p < a.n && p != self[h]) key = XKey{dkey(sd[h]), (uint32_t)p};
+                const bool pass = xless(key, kth[h]);
+                const uint64_t m = __ballot(pass);
+                if (m != 0) {
+                    uint64_t *pd = pdw + h * WIDE_POOL;
+                    uint32_t *pp = ppw + h * WIDE_POOL;
+                    if (pass) {
+                        const int pos = cnt[h] + __popcll(m & lt);
+                        pd[pos] = key.d;
+                        pp[pos] = key.p;
+                    }
+                    cnt[h] += __popcll(m);
+                    if (cnt[h] > WIDE_POOL - 64) cnt[h] = wide_select(pd, pp, cnt[h], a.k, &kth[h]);
                 }
-                cnt += __popcll(m);
-                if (cnt > WIDE_POOL - 64) cnt = wide_select(pd, pp, cnt, a.k, &kth);
             }
         }
-        cnt = wide_select(pd, pp, cnt, a.k, &kth);
-        int32_t *o = a.out + q * (int64_t)a.out_stride;
-        const int off = a.self_first ? 1 : 0;
-        for (int s = lane; s < cnt; s += 64) o[off + s] = (int32_t)pp[s];
-        if (a.self_first && lane == 0) o[0] = (int32_t)q;
+#pragma unroll
+        for (int h = 0; h < WIDE_Q; ++h) {
+            if (!act[h]) continue;
+            uint64_t *pd = pdw + h * WIDE_POOL;
+            uint32_t *pp = ppw + h * WIDE_POOL;
+            const int kept = wide_select(pd, pp, cnt[h], a.k, &kth[h]);
+            int32_t *o = a.out + q[h] * (int64_t)a.out_stride;
+            const int off = a.self_first ? 1 : 0;
+            for (int s2 = lane; s2 < kept; s2 += 64) o[off + s2] = (int32_t)pp[s2];
+            if (a.self_first && lane == 0) o[0] = (int32_t)q[h];
+        }
         wave_lds_fence();
     }
 }
@@ -345,7 +383,9 @@ hipError_t launch_exact_topk(bool f64, const ExactArgs &a, int64_t max_items, hi
     int64_t blocks = (max_items + EXACT_WAVES - 1) / EXACT_WAVES;
     if (blocks > 8192) blocks = 8192;
     if (a.k > 64) {
-        const size_t wshm = (size_t)EXACT_WAVES * (8 * (size_t)a.d + 12 * WIDE_POOL);
+        const size_t wshm = (size_t)EXACT_WAVES * WIDE_Q * (8 * (size_t)a.d + 12 * WIDE_POOL);
+        blocks = (max_items + EXACT_WAVES * WIDE_Q - 1) / (EXACT_WAVES * WIDE_Q);
+        if (blocks > 8192) blocks = 8192;
         if (f64)
             hipLaunchKernelGGL(exact_wide_kernel<double>, dim3((unsigned)blocks), dim3(256), wshm,
                                s, a);
