@@ -132,7 +132,7 @@ typedef struct {
  *         exact FP64-distance search for every training point and one
  *         workgroup per factorisation with the packed factor in LDS, so they
  *         need FP64 or FP32 precision and
- *         esz * (k (d+1) + k (k+1)/2 + 544) <= 160 KB (esz = 8 for FP64,
+ *         esz * (k (d+1) + k (k+1)/2 + 513) <= 160 KB (esz = 8 for FP64,
  *         4 for FP32); otherwise FMG_E_UNSUPPORTED.
  * X and Y are only read during the call; the model keeps its own copies of
  * what prediction needs (X, Y, the neighbour lists N [n,k] and C [n,k,ell]).

@@ -11,12 +11,19 @@
 //   1. the k neighbour rows are staged in LDS;
 //   2. assembly over a 32 x 32 thread grid (thread (ty, tx) takes rows
 //      ty + 32 r and columns tx + 32 s of the lower triangle);
-//   3. right-looking Cholesky: at step j every thread reads the pivot,
-//      thread a > j scales its entry of column j, and the trailing update
-//      is spread over the same 32 x 32 grid (two barriers per step);
+//   3. right-looking Cholesky in blocks of NB columns: every wavefront that
+//      holds rows at or below a block factors its NB x NB diagonal block in
+//      registers (one entry per lane, cross-lane reads), and each thread
+//      below the block then derives its row's NB entries of L; the whole
+//      workgroup applies the block's NB rank-one updates to the trailing
+//      columns (two barriers per block; every entry sees the single-step
+//      updates in step order, so the factor equals the unblocked one bit for
+//      bit);
 //   4. forward and back substitution, thread a owning row a of all ell
-//      right-hand sides, the solved entry broadcast through LDS (double
-//      buffered, one barrier per step).
+//      right-hand sides: the wavefront holding a block's rows solves them in
+//      turn (cross-lane reads), publishes them in LDS (double buffered), and
+//      the other rows subtract the block's contributions in step order (one
+//      barrier per block).
 // A non-positive or non-finite pivot marks the row as not positive definite:
 // its C row is NaN and its status is 1.
 #include "fmg_device.h"
@@ -29,6 +36,28 @@ namespace {
 constexpr int WIDE_THREADS = 1024;
 constexpr int WIDE_KMAX = 256;  // rows of the column and diagonal buffers
 constexpr int GRID = 32;        // the thread grid is GRID x GRID
+constexpr int NB = 8;           // columns per block (divides 64: a block's rows share a wavefront)
+
+template <typename T>
+__device__ __forceinline__ T lane_value(T v, int lane);
+template <>
+__device__ __forceinline__ double lane_value<double>(double v, int lane) {
+    return readlane_f64(v, lane);
+}
+template <>
+__device__ __forceinline__ float lane_value<float>(float v, int lane) {
+    return readlane_f32(v, lane);
+}
+template <typename T>
+__device__ __forceinline__ T lane_shfl(T v, int src);
+template <>
+__device__ __forceinline__ double lane_shfl<double>(double v, int src) {
+    return __longlong_as_double((long long)shfl_u64((uint64_t)__double_as_longlong(v), src));
+}
+template <>
+__device__ __forceinline__ float lane_shfl<float>(float v, int src) {
+    return __int_as_float((int)shfl_u32((uint32_t)__float_as_int(v), src));
+}
 
 template <typename T>
 __device__ __forceinline__ T sqdist_rows(const T *__restrict__ u, const T *__restrict__ v, int d) {
@@ -41,7 +70,8 @@ __device__ __forceinline__ T sqdist_rows(const T *__restrict__ u, const T *__res
 }
 
 __host__ __device__ __forceinline__ size_t wide_lds_elems(int k, int d, int ellmax) {
-    return (size_t)k * (d + 1) + (size_t)k * (k + 1) / 2 + 2 * WIDE_KMAX + 2 * (size_t)ellmax;
+    // rows, packed factor, diagonal, solved blocks, flag
+    return (size_t)k * (d + 1) + (size_t)k * (k + 1) / 2 + WIDE_KMAX + 2 * (size_t)NB * ellmax + 1;
 }
 
 template <typename T, int ELLMAX>
@@ -55,17 +85,20 @@ __global__ __launch_bounds__(WIDE_THREADS) void precompute_wide_kernel(Precomput
     const int xs_ld = d + 1;
     T *xs = (T *)smem;                          // [k, d + 1]
     T *A = xs + (size_t)k * xs_ld;              // packed lower triangle
-    T *col = A + (size_t)k * (k + 1) / 2;       // [256] column j of L
-    T *dg = col + WIDE_KMAX;                    // [256] L_jj
-    T *bc = dg + WIDE_KMAX;                     // [2][ELLMAX] solve broadcast
+    T *dg = A + (size_t)k * (k + 1) / 2;        // [256] L_jj
+    T *wb = dg + WIDE_KMAX;                     // [2][NB][ELLMAX] solved block rows
+    int *badf = (int *)(wb + 2 * NB * ELLMAX);  // a pivot was not positive
     const T *__restrict__ X = (const T *)P.X;
     const T *__restrict__ Y = (const T *)P.Y;
+    const int wave = a >> 6, lane = a & 63;
+    const size_t arow = (size_t)a * (a + 1) / 2;
 
     int64_t p = 0;
     if (a < k) {
         p = (int64_t)P.N[i * k + a];
         for (int c = 0; c < d; ++c) xs[a * xs_ld + c] = X[p * d + c];
     }
+    if (a == 0) *badf = 0;
     __syncthreads();
 
     const T inv_rho = (T)P.inv_rho, amp = (T)P.amp, diag = (T)(P.amp + P.noise);
@@ -78,64 +111,143 @@ __global__ __launch_bounds__(WIDE_THREADS) void precompute_wide_kernel(Precomput
     }
     __syncthreads();
 
-    bool bad = false;
-    const size_t arow = (size_t)a * (a + 1) / 2;
-    for (int j = 0; j < k; ++j) {
-        const T piv = A[(size_t)j * (j + 1) / 2 + j];
-        const bool ok = piv > T(0) && isfinite((double)piv);
-        bad = bad || !ok;
-        const T ljj = ok ? (T)sqrt(piv) : T(1);
-        if (a == j) dg[j] = ljj;
-        if (a > j && a < k) {
-            const T l = A[arow + j] / ljj;
-            A[arow + j] = l;
-            col[a] = l;
+    const int dr = lane >> 3, dc = lane & 7;  // lane's entry of a diagonal block
+    for (int jb = 0; jb < k; jb += NB) {
+        const int je = jb + NB < k ? jb + NB : k, nb = je - jb;
+        const bool owner = wave == (jb >> 6);  // holds the block's rows
+        T v = T(0);
+        if ((wave + 1) * 64 > jb && wave * 64 < k) {
+            // the diagonal block, factored in registers by every wavefront
+            // that holds rows at or below it: entry (jb + dr, jb + dc)
+            if (dc <= dr && dr < nb) v = A[(size_t)(jb + dr) * (jb + dr + 1) / 2 + jb + dc];
+            T ljj[NB];
+            bool wbad = false;
+#pragma unroll
+            for (int t = 0; t < NB; ++t) {
+                if (t < nb) {
+                    const T piv = lane_value<T>(v, t * (NB + 1));
+                    const bool ok = piv > T(0) && isfinite((double)piv);
+                    wbad = wbad || !ok;
+                    ljj[t] = ok ? (T)sqrt(piv) : T(1);
+                    if (dc == t && dr > t && dr < nb) v = v / ljj[t];
+                    const T lr = lane_shfl<T>(v, dr * NB + t);
+                    const T lb = lane_shfl<T>(v, dc * NB + t);
+                    if (dc > t && dc <= dr && dr < nb) v -= lr * lb;
+                } else {
+                    ljj[t] = T(1);
+                }
+            }
+            if (owner && lane == 0) {
+#pragma unroll
+                for (int t = 0; t < NB; ++t)
+                    if (t < nb) dg[jb + t] = ljj[t];
+                if (wbad) *badf = 1;
+            }
+            // the rows below the block: row a takes the block's steps in
+            // order, each a division by the pivot after the earlier columns'
+            // updates (a block with rows below it is full)
+            if (je < k) {
+                const bool mine = a >= je && a < k;
+                T u[NB];
+#pragma unroll
+                for (int t = 0; t < NB; ++t) u[t] = mine ? A[arow + jb + t] : T(0);
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+#pragma unroll
+                    for (int t = 0; t < j; ++t) u[j] -= u[t] * lane_value<T>(v, j * NB + t);
+                    u[j] = u[j] / ljj[j];
+                }
+                if (mine) {
+#pragma unroll
+                    for (int t = 0; t < NB; ++t) A[arow + jb + t] = u[t];
+                }
+            }
         }
         __syncthreads();
-        for (int r = j + 1 + ty; r < k; r += GRID) {
-            const T lr = col[r];
-            const size_t row = (size_t)r * (r + 1) / 2;
-            for (int b = j + 1 + tx; b <= r; b += GRID) A[row + b] -= lr * col[b];
+        if (owner && dc <= dr && dr < nb)
+            A[(size_t)(jb + dr) * (jb + dr + 1) / 2 + jb + dc] = v;
+        // trailing columns, the block's steps in order
+        for (int r = je + ty; r < k; r += GRID) {
+            const size_t rr = (size_t)r * (r + 1) / 2;
+            T lr[NB];
+#pragma unroll
+            for (int t = 0; t < NB; ++t) lr[t] = A[rr + jb + t];
+            for (int b = je + tx; b <= r; b += GRID) {
+                const T *lb = A + (size_t)b * (b + 1) / 2 + jb;
+                T x = A[rr + b];
+#pragma unroll
+                for (int t = 0; t < NB; ++t) x -= lr[t] * lb[t];
+                A[rr + b] = x;
+            }
         }
         __syncthreads();
     }
+    const bool bad = *badf != 0;
 
     T y[ELLMAX];
 #pragma unroll
     for (int c = 0; c < ELLMAX; ++c) y[c] = (a < k && c < ell) ? Y[p * ell + c] : T(0);
-    for (int j = 0; j < k; ++j) {  // L w = y
-        T *buf = bc + (j & 1) * ELLMAX;
-        if (a == j) {
-            const T ljj = dg[j];
+    for (int jb = 0, blk = 0; jb < k; jb += NB, ++blk) {  // L w = y
+        const int je = jb + NB < k ? jb + NB : k;
+        T *w = wb + (blk & 1) * NB * ELLMAX;
+        if (wave == (jb >> 6)) {
+            for (int j = jb; j < je; ++j) {
+                if (a == j) {
+                    const T ljj = dg[j];
 #pragma unroll
-            for (int c = 0; c < ELLMAX; ++c) {
-                y[c] = y[c] / ljj;
-                buf[c] = y[c];
+                    for (int c = 0; c < ELLMAX; ++c) y[c] = y[c] / ljj;
+                }
+                const T l = (a > j && a < je) ? A[arow + j] : T(0);
+#pragma unroll
+                for (int c = 0; c < ELLMAX; ++c) {
+                    const T wj = lane_value<T>(y[c], j & 63);
+                    if (a > j && a < je) y[c] -= l * wj;
+                }
+            }
+            if (a >= jb && a < je) {
+#pragma unroll
+                for (int c = 0; c < ELLMAX; ++c) w[(a - jb) * ELLMAX + c] = y[c];
             }
         }
         __syncthreads();
-        if (a > j && a < k) {
-            const T l = A[arow + j];
+        if (a >= je && a < k) {
+            for (int j = jb; j < je; ++j) {
+                const T l = A[arow + j];
 #pragma unroll
-            for (int c = 0; c < ELLMAX; ++c) y[c] -= l * buf[c];
+                for (int c = 0; c < ELLMAX; ++c) y[c] -= l * w[(j - jb) * ELLMAX + c];
+            }
         }
     }
     __syncthreads();
-    for (int j = k - 1; j >= 0; --j) {  // L^T x = w
-        T *buf = bc + (j & 1) * ELLMAX;
-        if (a == j) {
-            const T ljj = dg[j];
+    for (int jb = ((k - 1) / NB) * NB, blk = 0; jb >= 0; jb -= NB, ++blk) {  // L^T x = w
+        const int je = jb + NB < k ? jb + NB : k;
+        T *w = wb + (blk & 1) * NB * ELLMAX;
+        if (wave == (jb >> 6)) {
+            for (int j = je - 1; j >= jb; --j) {
+                if (a == j) {
+                    const T ljj = dg[j];
 #pragma unroll
-            for (int c = 0; c < ELLMAX; ++c) {
-                y[c] = y[c] / ljj;
-                buf[c] = y[c];
+                    for (int c = 0; c < ELLMAX; ++c) y[c] = y[c] / ljj;
+                }
+                const T l = (a >= jb && a < j) ? A[(size_t)j * (j + 1) / 2 + a] : T(0);
+#pragma unroll
+                for (int c = 0; c < ELLMAX; ++c) {
+                    const T xj = lane_value<T>(y[c], j & 63);
+                    if (a >= jb && a < j) y[c] -= l * xj;
+                }
+            }
+            if (a >= jb && a < je) {
+#pragma unroll
+                for (int c = 0; c < ELLMAX; ++c) w[(a - jb) * ELLMAX + c] = y[c];
             }
         }
         __syncthreads();
-        if (a < j) {
-            const T l = A[(size_t)j * (j + 1) / 2 + a];
+        if (a < jb) {
+            for (int j = je - 1; j >= jb; --j) {
+                const T l = A[(size_t)j * (j + 1) / 2 + a];
 #pragma unroll
-            for (int c = 0; c < ELLMAX; ++c) y[c] -= l * buf[c];
+                for (int c = 0; c < ELLMAX; ++c) y[c] -= l * w[(j - jb) * ELLMAX + c];
+            }
         }
     }
 
