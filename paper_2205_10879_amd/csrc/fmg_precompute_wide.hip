@@ -20,10 +20,11 @@
 //      updates in step order, so the factor equals the unblocked one bit for
 //      bit);
 //   4. forward and back substitution, thread a owning row a of all ell
-//      right-hand sides: the wavefront holding a block's rows solves them in
-//      turn (cross-lane reads), publishes them in LDS (double buffered), and
-//      the other rows subtract the block's contributions in step order (one
-//      barrier per block).
+//      right-hand sides: a block's rows are solved in turn by one wavefront
+//      (cross-lane reads) and published in LDS, and the rows still to solve
+//      subtract the block's contributions in step order; the forward pass
+//      rides along with the factorisation, the backward pass takes one
+//      barrier per block.
 // A non-positive or non-finite pivot marks the row as not positive definite:
 // its C row is NaN and its status is 1.
 #include "fmg_device.h"
@@ -86,8 +87,9 @@ __global__ __launch_bounds__(WIDE_THREADS) void precompute_wide_kernel(Precomput
     T *xs = (T *)smem;                          // [k, d + 1]
     T *A = xs + (size_t)k * xs_ld;              // packed lower triangle
     T *dg = A + (size_t)k * (k + 1) / 2;        // [256] L_jj
-    T *wb = dg + WIDE_KMAX;                     // [2][NB][ELLMAX] solved block rows
+    T *wb = dg + WIDE_KMAX;                     // [2][NB][ELLMAX] block rows of the solves
     int *badf = (int *)(wb + 2 * NB * ELLMAX);  // a pivot was not positive
+    T *wf = wb, *yb = wb + NB * ELLMAX;         // forward solve: solved rows, rows to solve
     const T *__restrict__ X = (const T *)P.X;
     const T *__restrict__ Y = (const T *)P.Y;
     const int wave = a >> 6, lane = a & 63;
@@ -99,6 +101,13 @@ __global__ __launch_bounds__(WIDE_THREADS) void precompute_wide_kernel(Precomput
         for (int c = 0; c < d; ++c) xs[a * xs_ld + c] = X[p * d + c];
     }
     if (a == 0) *badf = 0;
+    T y[ELLMAX];
+#pragma unroll
+    for (int c = 0; c < ELLMAX; ++c) y[c] = (a < k && c < ell) ? Y[p * ell + c] : T(0);
+    if (a < NB && a < k) {
+#pragma unroll
+        for (int c = 0; c < ELLMAX; ++c) yb[a * ELLMAX + c] = y[c];
+    }
     __syncthreads();
 
     const T inv_rho = (T)P.inv_rho, amp = (T)P.amp, diag = (T)(P.amp + P.noise);
@@ -111,12 +120,21 @@ __global__ __launch_bounds__(WIDE_THREADS) void precompute_wide_kernel(Precomput
     }
     __syncthreads();
 
+    // The factorisation carries the forward substitution L w = y along: the
+    // last wavefront (it holds no rows, k <= 256) solves each block's rows as
+    // soon as the block's diagonal factor exists, and every row below takes
+    // the block's contributions after the first barrier.
     const int dr = lane >> 3, dc = lane & 7;  // lane's entry of a diagonal block
+    const bool solver = wave == WIDE_THREADS / 64 - 1;
     for (int jb = 0; jb < k; jb += NB) {
         const int je = jb + NB < k ? jb + NB : k, nb = je - jb;
         const bool owner = wave == (jb >> 6);  // holds the block's rows
+        const bool rows = (wave + 1) * 64 > jb && wave * 64 < k;
         T v = T(0);
-        if ((wave + 1) * 64 > jb && wave * 64 < k) {
+        T u[NB];  // row a's entries of L in the block's columns
+#pragma unroll
+        for (int t = 0; t < NB; ++t) u[t] = T(0);
+        if (rows || solver) {
             // the diagonal block, factored in registers by every wavefront
             // that holds rows at or below it: entry (jb + dr, jb + dc)
             if (dc <= dr && dr < nb) v = A[(size_t)(jb + dr) * (jb + dr + 1) / 2 + jb + dc];
@@ -143,12 +161,35 @@ __global__ __launch_bounds__(WIDE_THREADS) void precompute_wide_kernel(Precomput
                     if (t < nb) dg[jb + t] = ljj[t];
                 if (wbad) *badf = 1;
             }
-            // the rows below the block: row a takes the block's steps in
-            // order, each a division by the pivot after the earlier columns'
-            // updates (a block with rows below it is full)
-            if (je < k) {
+            if (solver) {
+                // the block's rows of L w = y, lane t holding row jb + t
+                T ys[ELLMAX];
+#pragma unroll
+                for (int c = 0; c < ELLMAX; ++c) ys[c] = lane < nb ? yb[lane * ELLMAX + c] : T(0);
+#pragma unroll
+                for (int t = 0; t < NB; ++t) {
+                    if (t < nb) {
+                        if (lane == t) {
+#pragma unroll
+                            for (int c = 0; c < ELLMAX; ++c) ys[c] = ys[c] / ljj[t];
+                        }
+                        const T l = lane_shfl<T>(v, (lane & 7) * NB + t);
+#pragma unroll
+                        for (int c = 0; c < ELLMAX; ++c) {
+                            const T wt = lane_value<T>(ys[c], t);
+                            if (lane > t && lane < nb) ys[c] -= l * wt;
+                        }
+                    }
+                }
+                if (lane < nb) {
+#pragma unroll
+                    for (int c = 0; c < ELLMAX; ++c) wf[lane * ELLMAX + c] = ys[c];
+                }
+            } else if (je < k) {
+                // the rows below the block: row a takes the block's steps in
+                // order, each a division by the pivot after the earlier
+                // columns' updates (a block with rows below it is full)
                 const bool mine = a >= je && a < k;
-                T u[NB];
 #pragma unroll
                 for (int t = 0; t < NB; ++t) u[t] = mine ? A[arow + jb + t] : T(0);
 #pragma unroll
@@ -166,6 +207,20 @@ __global__ __launch_bounds__(WIDE_THREADS) void precompute_wide_kernel(Precomput
         __syncthreads();
         if (owner && dc <= dr && dr < nb)
             A[(size_t)(jb + dr) * (jb + dr + 1) / 2 + jb + dc] = v;
+        if (a >= jb && a < je) {  // the block's rows are solved
+#pragma unroll
+            for (int c = 0; c < ELLMAX; ++c) y[c] = wf[(a - jb) * ELLMAX + c];
+        } else if (a >= je && a < k) {
+#pragma unroll
+            for (int t = 0; t < NB; ++t) {
+#pragma unroll
+                for (int c = 0; c < ELLMAX; ++c) y[c] -= u[t] * wf[t * ELLMAX + c];
+            }
+            if (a < je + NB) {  // the next block's rows
+#pragma unroll
+                for (int c = 0; c < ELLMAX; ++c) yb[(a - je) * ELLMAX + c] = y[c];
+            }
+        }
         // trailing columns, the block's steps in order
         for (int r = je + ty; r < k; r += GRID) {
             const size_t rr = (size_t)r * (r + 1) / 2;
@@ -184,41 +239,6 @@ __global__ __launch_bounds__(WIDE_THREADS) void precompute_wide_kernel(Precomput
     }
     const bool bad = *badf != 0;
 
-    T y[ELLMAX];
-#pragma unroll
-    for (int c = 0; c < ELLMAX; ++c) y[c] = (a < k && c < ell) ? Y[p * ell + c] : T(0);
-    for (int jb = 0, blk = 0; jb < k; jb += NB, ++blk) {  // L w = y
-        const int je = jb + NB < k ? jb + NB : k;
-        T *w = wb + (blk & 1) * NB * ELLMAX;
-        if (wave == (jb >> 6)) {
-            for (int j = jb; j < je; ++j) {
-                if (a == j) {
-                    const T ljj = dg[j];
-#pragma unroll
-                    for (int c = 0; c < ELLMAX; ++c) y[c] = y[c] / ljj;
-                }
-                const T l = (a > j && a < je) ? A[arow + j] : T(0);
-#pragma unroll
-                for (int c = 0; c < ELLMAX; ++c) {
-                    const T wj = lane_value<T>(y[c], j & 63);
-                    if (a > j && a < je) y[c] -= l * wj;
-                }
-            }
-            if (a >= jb && a < je) {
-#pragma unroll
-                for (int c = 0; c < ELLMAX; ++c) w[(a - jb) * ELLMAX + c] = y[c];
-            }
-        }
-        __syncthreads();
-        if (a >= je && a < k) {
-            for (int j = jb; j < je; ++j) {
-                const T l = A[arow + j];
-#pragma unroll
-                for (int c = 0; c < ELLMAX; ++c) y[c] -= l * w[(j - jb) * ELLMAX + c];
-            }
-        }
-    }
-    __syncthreads();
     for (int jb = ((k - 1) / NB) * NB, blk = 0; jb >= 0; jb -= NB, ++blk) {  // L^T x = w
         const int je = jb + NB < k ? jb + NB : k;
         T *w = wb + (blk & 1) * NB * ELLMAX;
