@@ -136,23 +136,71 @@ __global__ __launch_bounds__(WIDE_THREADS) void precompute_wide_kernel(Precomput
         for (int t = 0; t < NB; ++t) u[t] = T(0);
         if (rows || solver) {
             // the diagonal block, factored in registers by every wavefront
-            // that holds rows at or below it: entry (jb + dr, jb + dc)
-            if (dc <= dr && dr < nb) v = A[(size_t)(jb + dr) * (jb + dr + 1) / 2 + jb + dc];
+            // that holds rows at or below it: entry (jb + dr, jb + dc); a
+            // partial block is padded with the identity
+            if (dc <= dr)
+                v = dr < nb ? A[(size_t)(jb + dr) * (jb + dr + 1) / 2 + jb + dc]
+                            : (dc == dr ? T(1) : T(0));
             T ljj[NB];
             bool wbad = false;
+            // step t of the diagonal block (branch-free, so that the rows'
+            // own chains interleave with it)
+            auto diag_step = [&](int t) {
+                const T piv = lane_value<T>(v, t * (NB + 1));
+                const bool ok = piv > T(0) && isfinite((double)piv);
+                wbad = wbad || (!ok && t < nb);
+                ljj[t] = ok ? (T)sqrt(piv) : T(1);
+                const T q = v / ljj[t];
+                v = (dc == t && dr > t && dr < nb) ? q : v;
+                const T lr = lane_shfl<T>(v, dr * NB + t);
+                const T lb = lane_shfl<T>(v, dc * NB + t);
+                const T nv = v - lr * lb;
+                v = (dc > t && dc <= dr && dr < nb) ? nv : v;
+            };
+            if (solver) {
+                // the block's rows of L w = y, lane t holding row jb + t (in
+                // y: this wavefront holds no rows of its own)
+                T *ys = y;
 #pragma unroll
-            for (int t = 0; t < NB; ++t) {
-                if (t < nb) {
-                    const T piv = lane_value<T>(v, t * (NB + 1));
-                    const bool ok = piv > T(0) && isfinite((double)piv);
-                    wbad = wbad || !ok;
-                    ljj[t] = ok ? (T)sqrt(piv) : T(1);
-                    if (dc == t && dr > t && dr < nb) v = v / ljj[t];
-                    const T lr = lane_shfl<T>(v, dr * NB + t);
-                    const T lb = lane_shfl<T>(v, dc * NB + t);
-                    if (dc > t && dc <= dr && dr < nb) v -= lr * lb;
-                } else {
-                    ljj[t] = T(1);
+                for (int c = 0; c < ELLMAX; ++c) ys[c] = lane < nb ? yb[lane * ELLMAX + c] : T(0);
+#pragma unroll
+                for (int t = 0; t < NB; ++t) {
+                    diag_step(t);
+#pragma unroll
+                    for (int c = 0; c < ELLMAX; ++c) {
+                        const T q = ys[c] / ljj[t];
+                        ys[c] = lane == t ? q : ys[c];
+                    }
+                    const T l = lane_shfl<T>(v, (lane & 7) * NB + t);
+#pragma unroll
+                    for (int c = 0; c < ELLMAX; ++c) {
+                        const T wt = lane_value<T>(ys[c], t);
+                        const T ny = ys[c] - l * wt;
+                        ys[c] = (lane > t && lane < nb) ? ny : ys[c];
+                    }
+                }
+                if (lane < nb) {
+#pragma unroll
+                    for (int c = 0; c < ELLMAX; ++c) wf[lane * ELLMAX + c] = ys[c];
+                }
+            } else {
+                // the rows below the block take the block's steps in order
+                // alongside it: a division by the pivot once the earlier
+                // columns' updates are in, then this column's update of the
+                // later ones (a block with rows below it is full)
+                const bool mine = je < k && a >= je && a < k;
+#pragma unroll
+                for (int t = 0; t < NB; ++t) u[t] = mine ? A[arow + jb + t] : T(0);
+#pragma unroll
+                for (int t = 0; t < NB; ++t) {
+                    diag_step(t);
+                    u[t] = u[t] / ljj[t];
+#pragma unroll
+                    for (int j = t + 1; j < NB; ++j) u[j] -= u[t] * lane_value<T>(v, j * NB + t);
+                }
+                if (mine) {
+#pragma unroll
+                    for (int t = 0; t < NB; ++t) A[arow + jb + t] = u[t];
                 }
             }
             if (owner && lane == 0) {
@@ -160,48 +208,6 @@ __global__ __launch_bounds__(WIDE_THREADS) void precompute_wide_kernel(Precomput
                 for (int t = 0; t < NB; ++t)
                     if (t < nb) dg[jb + t] = ljj[t];
                 if (wbad) *badf = 1;
-            }
-            if (solver) {
-                // the block's rows of L w = y, lane t holding row jb + t
-                T ys[ELLMAX];
-#pragma unroll
-                for (int c = 0; c < ELLMAX; ++c) ys[c] = lane < nb ? yb[lane * ELLMAX + c] : T(0);
-#pragma unroll
-                for (int t = 0; t < NB; ++t) {
-                    if (t < nb) {
-                        if (lane == t) {
-#pragma unroll
-                            for (int c = 0; c < ELLMAX; ++c) ys[c] = ys[c] / ljj[t];
-                        }
-                        const T l = lane_shfl<T>(v, (lane & 7) * NB + t);
-#pragma unroll
-                        for (int c = 0; c < ELLMAX; ++c) {
-                            const T wt = lane_value<T>(ys[c], t);
-                            if (lane > t && lane < nb) ys[c] -= l * wt;
-                        }
-                    }
-                }
-                if (lane < nb) {
-#pragma unroll
-                    for (int c = 0; c < ELLMAX; ++c) wf[lane * ELLMAX + c] = ys[c];
-                }
-            } else if (je < k) {
-                // the rows below the block: row a takes the block's steps in
-                // order, each a division by the pivot after the earlier
-                // columns' updates (a block with rows below it is full)
-                const bool mine = a >= je && a < k;
-#pragma unroll
-                for (int t = 0; t < NB; ++t) u[t] = mine ? A[arow + jb + t] : T(0);
-#pragma unroll
-                for (int j = 0; j < NB; ++j) {
-#pragma unroll
-                    for (int t = 0; t < j; ++t) u[j] -= u[t] * lane_value<T>(v, j * NB + t);
-                    u[j] = u[j] / ljj[j];
-                }
-                if (mine) {
-#pragma unroll
-                    for (int t = 0; t < NB; ++t) A[arow + jb + t] = u[t];
-                }
             }
         }
         __syncthreads();
@@ -240,20 +246,29 @@ __global__ __launch_bounds__(WIDE_THREADS) void precompute_wide_kernel(Precomput
     const bool bad = *badf != 0;
 
     for (int jb = ((k - 1) / NB) * NB, blk = 0; jb >= 0; jb -= NB, ++blk) {  // L^T x = w
-        const int je = jb + NB < k ? jb + NB : k;
+        const int je = jb + NB < k ? jb + NB : k, nb = je - jb;
         T *w = wb + (blk & 1) * NB * ELLMAX;
         if (wave == (jb >> 6)) {
-            for (int j = je - 1; j >= jb; --j) {
-                if (a == j) {
-                    const T ljj = dg[j];
+            T lc[NB], dj[NB];  // L_{j,a} and L_jj for the block's columns j
 #pragma unroll
-                    for (int c = 0; c < ELLMAX; ++c) y[c] = y[c] / ljj;
+            for (int t = 0; t < NB; ++t) {
+                const int j = jb + t;
+                lc[t] = (t < nb && a >= jb && a < j) ? A[(size_t)j * (j + 1) / 2 + a] : T(0);
+                dj[t] = t < nb ? dg[j] : T(1);
+            }
+#pragma unroll
+            for (int t = NB - 1; t >= 0; --t) {
+                const int j = jb + t;
+#pragma unroll
+                for (int c = 0; c < ELLMAX; ++c) {
+                    const T q = y[c] / dj[t];
+                    y[c] = a == j ? q : y[c];
                 }
-                const T l = (a >= jb && a < j) ? A[(size_t)j * (j + 1) / 2 + a] : T(0);
 #pragma unroll
                 for (int c = 0; c < ELLMAX; ++c) {
                     const T xj = lane_value<T>(y[c], j & 63);
-                    if (a >= jb && a < j) y[c] -= l * xj;
+                    const T ny = y[c] - lc[t] * xj;
+                    y[c] = (t < nb && a >= jb && a < j) ? ny : y[c];
                 }
             }
             if (a >= jb && a < je) {
@@ -263,10 +278,17 @@ __global__ __launch_bounds__(WIDE_THREADS) void precompute_wide_kernel(Precomput
         }
         __syncthreads();
         if (a < jb) {
-            for (int j = je - 1; j >= jb; --j) {
-                const T l = A[(size_t)j * (j + 1) / 2 + a];
+            T lc[NB];
 #pragma unroll
-                for (int c = 0; c < ELLMAX; ++c) y[c] -= l * w[(j - jb) * ELLMAX + c];
+            for (int t = 0; t < NB; ++t)
+                lc[t] = t < nb ? A[(size_t)(jb + t) * (jb + t + 1) / 2 + a] : T(0);
+#pragma unroll
+            for (int t = NB - 1; t >= 0; --t) {
+#pragma unroll
+                for (int c = 0; c < ELLMAX; ++c) {
+                    const T ny = y[c] - lc[t] * w[t * ELLMAX + c];
+                    y[c] = t < nb ? ny : y[c];
+                }
             }
         }
     }
