@@ -126,3 +126,36 @@ def test_wide_loo_loss_and_the_gradient_limit():
         model.loo_loss_grad(rows_d, "matern", 2.5, 0.8, 1e-2)
     assert e.value.status == f.FMG_E_UNSUPPORTED
     model.free()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_wide_not_positive_definite_rows_are_flagged(prec):
+    # Three copies of one far-away point and no nugget: for each copy the two
+    # others are its first two neighbours, so the second pivot is 1 - 1 * 1 = 0
+    # in any arithmetic; every other neighbourhood (exponential kernel, points
+    # of the bulk only) is positive definite.
+    f = fmg()
+    rs = np.random.default_rng(5)
+    X = rs.standard_normal((400, 2))
+    X[397:] = [50.0, 50.0]
+    Y = rs.standard_normal((400, 1))
+    k = 70
+    Xd = torch.from_numpy(np.ascontiguousarray(X, dtype=DT[prec])).cuda()
+    Yd = torch.from_numpy(np.ascontiguousarray(Y, dtype=DT[prec])).cuda()
+    model = f.fastmuygps_build(Xd, Yd, k, "matern", 0.5, 0.5, 0.0, precision=prec,
+                               allow_not_pd=True)
+    assert model.build_status == f.FMG_E_NOT_PD
+    N = model.neighbors().cpu().numpy()
+    C = model.coeffs().cpu().numpy()
+    info = model.info()
+    model.free()
+    X64 = X.astype(DT[prec]).astype(np.float64)
+    Y64 = Y.astype(DT[prec]).astype(np.float64)
+    Nr, _, st = oracle.build_model(X64, Y64, k, "matern", 0.5, 0.5, 0.0)
+    assert np.array_equal(np.flatnonzero(st), [397, 398, 399])
+    assert info["nonpd_rows"] == 3
+    assert np.array_equal(N, Nr)
+    assert np.array_equal(np.isnan(C).all(axis=(1, 2)), st != 0)
+    assert np.isfinite(C[st == 0]).all()
+    be = backward_error(X64, Y64, Nr[:24], C[:24], "matern", 0.5, 0.5, 0.0)
+    assert np.max(be) < (1e-13 if prec == "fp64" else 1e-5)
