@@ -16,9 +16,9 @@
 //      registers (one entry per lane, cross-lane reads), and each thread
 //      below the block then derives its row's NB entries of L; the whole
 //      workgroup applies the block's NB rank-one updates to the trailing
-//      columns (two barriers per block; every entry sees the single-step
-//      updates in step order, so the factor equals the unblocked one bit for
-//      bit);
+//      columns, two rows per thread (two barriers per block; every entry
+//      sees the single-step updates in step order, so the factor equals the
+//      unblocked one bit for bit);
 //   4. forward and back substitution, thread a owning row a of all ell
 //      right-hand sides: a block's rows are solved in turn by one wavefront
 //      (cross-lane reads) and published in LDS, and the rows still to solve
@@ -227,18 +227,39 @@ __global__ __launch_bounds__(WIDE_THREADS) void precompute_wide_kernel(Precomput
                 for (int c = 0; c < ELLMAX; ++c) yb[(a - je) * ELLMAX + c] = y[c];
             }
         }
-        // trailing columns, the block's steps in order
-        for (int r = je + ty; r < k; r += GRID) {
-            const size_t rr = (size_t)r * (r + 1) / 2;
-            T lr[NB];
+        // trailing columns, the block's steps in order; a thread takes two
+        // rows at once, so each column's entries of L are read once for both
+        // (one row in FP64 with more than four right-hand sides, which would
+        // run out of registers)
+        constexpr bool PAIR = !(sizeof(T) == 8 && ELLMAX > 4);
+        for (int r1 = je + ty; r1 < k; r1 += (PAIR ? 2 : 1) * GRID) {
+            const int r2 = r1 + GRID;
+            const bool two = PAIR && r2 < k;
+            const size_t rr1 = (size_t)r1 * (r1 + 1) / 2, rr2 = (size_t)r2 * (r2 + 1) / 2;
+            T l1[NB], l2[NB];
 #pragma unroll
-            for (int t = 0; t < NB; ++t) lr[t] = A[rr + jb + t];
-            for (int b = je + tx; b <= r; b += GRID) {
+            for (int t = 0; t < NB; ++t) {
+                l1[t] = A[rr1 + jb + t];
+                l2[t] = two ? A[rr2 + jb + t] : T(0);
+            }
+            const int bmax = two ? r2 : r1;
+            for (int b = je + tx; b <= bmax; b += GRID) {
                 const T *lb = A + (size_t)b * (b + 1) / 2 + jb;
-                T x = A[rr + b];
+                T cb[NB];
 #pragma unroll
-                for (int t = 0; t < NB; ++t) x -= lr[t] * lb[t];
-                A[rr + b] = x;
+                for (int t = 0; t < NB; ++t) cb[t] = lb[t];
+                if (b <= r1) {
+                    T x = A[rr1 + b];
+#pragma unroll
+                    for (int t = 0; t < NB; ++t) x -= l1[t] * cb[t];
+                    A[rr1 + b] = x;
+                }
+                if (two) {
+                    T x = A[rr2 + b];
+#pragma unroll
+                    for (int t = 0; t < NB; ++t) x -= l2[t] * cb[t];
+                    A[rr2 + b] = x;
+                }
             }
         }
         __syncthreads();
