@@ -13,12 +13,12 @@
 //      ty + 32 r and columns tx + 32 s of the lower triangle);
 //   3. right-looking Cholesky in blocks of NB columns: every wavefront that
 //      holds rows at or below a block factors its NB x NB diagonal block in
-//      registers (one entry per lane, cross-lane reads), and each thread
-//      below the block then derives its row's NB entries of L; the whole
+//      registers (one entry per lane, cross-lane reads), and alongside it
+//      each thread below the block derives its row's NB entries of L; the whole
 //      workgroup applies the block's NB rank-one updates to the trailing
 //      columns, two rows per thread (two barriers per block; every entry
 //      sees the single-step updates in step order, so the factor equals the
-//      unblocked one bit for bit);
+//      column-at-a-time one bit for bit);
 //   4. forward and back substitution, thread a owning row a of all ell
 //      right-hand sides: a block's rows are solved in turn by one wavefront
 //      (cross-lane reads) and published in LDS, and the rows still to solve
@@ -35,7 +35,7 @@ namespace fmg {
 namespace {
 
 constexpr int WIDE_THREADS = 1024;
-constexpr int WIDE_KMAX = 256;  // rows of the column and diagonal buffers
+constexpr int WIDE_KMAX = 256;  // largest k; entries of the diagonal buffer
 constexpr int GRID = 32;        // the thread grid is GRID x GRID
 constexpr int NB = 8;           // columns per block (divides 64: a block's rows share a wavefront)
 
