@@ -199,39 +199,10 @@ __global__ __launch_bounds__(256) void exact_wide_kernel(ExactArgs a) {
                 zw[h * a.d + c] = act[h] ? (double)Qc[q[h] * a.d + c] : 0.0;
         }
         wave_lds_fence();
-        for (int64_t base = 0; base < a.n; base += 64) {
-            const int64_t p = base + lane;
-            double sd[WIDE_Q];
-#pragma unroll
-            for (int h = 0; h < WIDE_Q; ++h) sd[h] = 0.0;
-            if (p < a.n) {
-                const T *__restrict__ xp = X + p * a.d;
-                if (vec2) {
-                    // the row in 16-byte loads, coordinates still summed in order
-                    for (int c = 0; c < a.d; c += 2) {
-                        const double2 v = *(const double2 *)(xp + c);
-#pragma unroll
-                        for (int h = 0; h < WIDE_Q; ++h) {
-                            const double t0 = zw[h * a.d + c] - v.x;
-                            const double u0 = t0 * t0;
-                            sd[h] = sd[h] + u0;
-                            const double t1 = zw[h * a.d + c + 1] - v.y;
-                            const double u1 = t1 * t1;
-                            sd[h] = sd[h] + u1;
-                        }
-                    }
-                } else {
-                    for (int c = 0; c < a.d; ++c) {
-                        const double xv = (double)xp[c];
-#pragma unroll
-                        for (int h = 0; h < WIDE_Q; ++h) {
-                            const double t = zw[h * a.d + c] - xv;
-                            const double t2 = t * t;
-                            sd[h] = sd[h] + t2;
-                        }
-                    }
-                }
-            }
+        // keys of candidate p (distances sd) offered to both rows' pools; the
+        // pools keep every key below the running k-th, so the order in which
+        // candidates are offered does not change the result
+        auto offer = [&](int64_t p, const double (&sd)[WIDE_Q]) {
 #pragma unroll
             for (int h = 0; h < WIDE_Q; ++h) {
                 if (!act[h]) continue;  // uniform
@@ -250,6 +221,90 @@ __global__ __launch_bounds__(256) void exact_wide_kernel(ExactArgs a) {
                     cnt[h] += __popcll(m);
                     if (cnt[h] > WIDE_POOL - 64) cnt[h] = wide_select(pd, pp, cnt[h], a.k, &kth[h]);
                 }
+            }
+        };
+        if (sizeof(T) == 8 && vec2 && a.d <= 8) {
+            // short FP64 rows: two chunks of 64 candidates per step, both rows
+            // loaded whole (16-byte loads) before any arithmetic, so the loads
+            // of a step are in flight together; rows past n read row n - 1
+            // and their keys are dropped
+            const double *__restrict__ X8 = (const double *)a.X;
+            for (int64_t base = 0; base < a.n; base += 128) {
+                const int64_t p0 = base + lane, p1 = base + 64 + lane;
+                const int64_t c0 = p0 < a.n ? p0 : a.n - 1, c1 = p1 < a.n ? p1 : a.n - 1;
+                double2 r0[4], r1[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (2 * i < a.d) {
+                        r0[i] = *(const double2 *)(X8 + c0 * a.d + 2 * i);
+                        r1[i] = *(const double2 *)(X8 + c1 * a.d + 2 * i);
+                    } else {
+                        r0[i] = make_double2(0.0, 0.0);
+                        r1[i] = make_double2(0.0, 0.0);
+                    }
+                }
+                double s0[WIDE_Q], s1[WIDE_Q];
+#pragma unroll
+                for (int h = 0; h < WIDE_Q; ++h) s0[h] = s1[h] = 0.0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (2 * i < a.d) {
+#pragma unroll
+                        for (int h = 0; h < WIDE_Q; ++h) {
+                            const double z0 = zw[h * a.d + 2 * i], z1 = zw[h * a.d + 2 * i + 1];
+                            const double t0 = z0 - r0[i].x;
+                            const double u0 = t0 * t0;
+                            s0[h] = s0[h] + u0;
+                            const double t1 = z1 - r0[i].y;
+                            const double u1 = t1 * t1;
+                            s0[h] = s0[h] + u1;
+                            const double v0 = z0 - r1[i].x;
+                            const double w0 = v0 * v0;
+                            s1[h] = s1[h] + w0;
+                            const double v1 = z1 - r1[i].y;
+                            const double w1 = v1 * v1;
+                            s1[h] = s1[h] + w1;
+                        }
+                    }
+                }
+                offer(p0, s0);
+                offer(p1, s1);
+            }
+        } else {
+            for (int64_t base = 0; base < a.n; base += 64) {
+                const int64_t p = base + lane;
+                double sd[WIDE_Q];
+#pragma unroll
+                for (int h = 0; h < WIDE_Q; ++h) sd[h] = 0.0;
+                if (p < a.n) {
+                    const T *__restrict__ xp = X + p * a.d;
+                    if (vec2) {
+                        // the row in 16-byte loads, coordinates still summed in order
+                        for (int c = 0; c < a.d; c += 2) {
+                            const double2 v = *(const double2 *)(xp + c);
+#pragma unroll
+                            for (int h = 0; h < WIDE_Q; ++h) {
+                                const double t0 = zw[h * a.d + c] - v.x;
+                                const double u0 = t0 * t0;
+                                sd[h] = sd[h] + u0;
+                                const double t1 = zw[h * a.d + c + 1] - v.y;
+                                const double u1 = t1 * t1;
+                                sd[h] = sd[h] + u1;
+                            }
+                        }
+                    } else {
+                        for (int c = 0; c < a.d; ++c) {
+                            const double xv = (double)xp[c];
+#pragma unroll
+                            for (int h = 0; h < WIDE_Q; ++h) {
+                                const double t = zw[h * a.d + c] - xv;
+                                const double t2 = t * t;
+                                sd[h] = sd[h] + t2;
+                            }
+                        }
+                    }
+                }
+                offer(p, sd);
             }
         }
 #pragma unroll
