@@ -37,6 +37,7 @@ CONFIGS = [
     (1200, 97, 8, 150, 1, "rbf", 0.0, 0.8, 5e-2),       # the borehole emulator's k
     (900, 64, 2, 256, 3, "matern", 2.5, 0.15, 5e-2),    # k at its maximum (FP32)
     (1500, 33, 4, 65, 2, "matern", 0.5, 0.5, 1e-2),     # one past a wavefront
+    (1300, 40, 3, 129, 7, "matern", 1.5, 0.4, 1e-1),    # seven responses, one-column last block
 ]
 
 
