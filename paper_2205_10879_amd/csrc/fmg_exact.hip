@@ -322,7 +322,7 @@ __global__ __launch_bounds__(256) void exact_wide_kernel(ExactArgs a) {
     }
 }
 
-constexpr int64_t NN_WAVES = 2048;
+constexpr int64_t NN_WAVES = NN_SPLIT_ENTRIES / 64;
 
 template <typename T, int DMAX>
 __global__ __launch_bounds__(64) void nn_split_kernel(ExactArgs a, int64_t chunk, int splits) {

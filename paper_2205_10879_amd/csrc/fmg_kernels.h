@@ -106,8 +106,8 @@ struct ExactArgs {
 };
 
 // Split nearest-point search: chunks x queries stays within this many
-// partial minima (2048 waves of 64 queries).
-constexpr int64_t NN_SPLIT_ENTRIES = 2048 * 64;
+// partial minima (8192 waves of 64 queries).
+constexpr int64_t NN_SPLIT_ENTRIES = 8192 * 64;
 
 struct PrecomputeArgs {
     const void *X;   // [n, d]
