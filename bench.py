@@ -121,6 +121,16 @@ def main():
         return sum(t[key] for t in timings) / len(timings)
 
     mu_mixed = out.cpu().numpy()
+    # One more (untimed) build + predict whose neighbour lists and nearest
+    # points the oracle leg checks.
+    model = fmg.fastmuygps_build(X, Y, w.k, w.kernel, w.nu, w.rho, w.noise, precision="mixed",
+                                 stream=stream)
+    nn_d = torch.empty(args.m, dtype=torch.int32, device=dev)
+    model.predict(Z, out=out, nn_out=nn_d, stream=stream)
+    N_mixed = model.neighbors(stream=stream).cpu().numpy()
+    nn_mixed = nn_d.cpu().numpy()
+    assert np.array_equal(out.cpu().numpy(), mu_mixed), "repeated prediction differs"
+    model.free()
     rmse_mixed = float(np.sqrt(np.mean((mu_mixed - w.Yz) ** 2)))
     acc_mixed = float(np.mean(np.argmax(mu_mixed, 1) == w.extra["labels_test"]))
 
@@ -167,6 +177,8 @@ def main():
         log("plain FP32 path, one step")
         t32, info32 = step("fp32")
         mu32 = out.cpu().numpy()
+        log("plain FP32: build %.1f ms predict %.1f ms" % (t32["build_total_ms"],
+                                                         t32["predict_total_ms"]))
         rmse32 = float(np.sqrt(np.mean((mu32 - w.Yz) ** 2)))
         result["fp32_plain"] = {
             "build_ms": round(t32["build_total_ms"], 3),
@@ -211,38 +223,84 @@ def main():
         result["p99_ms_served_fp32"] = result["served"]["fp32"]["p99_ms"]
 
     if not args.no_cpu_baseline:
-        import oracle
-        threads = oracle.max_threads()
-        rs = synth.rng(3, 4)
-        rows = np.sort(rs.choice(args.n, args.cpu_rows, replace=False))
-        qs = np.sort(rs.choice(args.m, args.cpu_queries, replace=False))
-        X64 = w.X.astype(np.float64)
-        Y64 = w.Y.astype(np.float64)
-        log("cpu baseline: oracle on %d rows + %d queries, %d threads" % (
-            len(rows), len(qs), threads))
-        c0 = time.perf_counter()
-        oracle.build_model(X64, Y64, w.k, w.kernel, w.nu, w.rho, w.noise, rows=rows,
-                           nthreads=threads)
-        c1 = time.perf_counter()
-        mu_o, _, _ = oracle.predict(X64, Y64, w.Z[qs].astype(np.float64), w.k, w.kernel, w.nu,
-                                    w.rho, w.noise, nthreads=threads)
-        c2 = time.perf_counter()
-        per_row = (c1 - c0) / len(rows)
-        per_query = (c2 - c1) / len(qs)
-        # whole job at the same shape: build all n rows, predict all m queries
-        est = per_row * args.n + per_query * args.m
-        result["cpu_baseline"] = {
-            "value": round(args.m / est, 3), "unit": "predictions/s", "cores": threads,
-            "kind": "oracle",
-            "sample": "FP64 oracle on %d seeded training rows and %d seeded queries of the "
-                      "same workload (%.1f s); per-item times extrapolated to build(n=%d) + "
-                      "predict(m=%d) = %.0f s" % (len(rows), len(qs), c2 - c0, args.n, args.m,
-                                                   est)}
-        err = float(np.max(np.abs(mu_mixed[qs] - mu_o)) / max(
-            float(np.sqrt(np.mean(mu_o ** 2))), 1e-300))
-        result["oracle_sample_max_rel_err_mixed"] = err
+        cpu_baseline_run(np, synth, w, args, result, N_mixed, nn_mixed, mu_mixed,
+                         mu32 if not args.no_fp32 else None)
 
     print(json.dumps(result), flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_run(np, synth, w, args, result, N_gpu, nn_gpu, mu_gpu, mu32):
+    """The FP64 oracle on a seeded sample of the same workload, on this host's
+    cores: its rate (all threads, and one thread on a smaller sample) and the
+    GPU results checked against it (neighbour lists and nearest points bit
+    for bit, means by the relative error max |dmu| / max(|mu_o|, RMS(mu_o)))."""
+    import oracle
+    threads = oracle.max_threads()
+    rs = synth.rng(3, 4)
+    rows = np.sort(rs.choice(args.n, args.cpu_rows, replace=False))
+    qs = np.sort(rs.choice(args.m, args.cpu_queries, replace=False))
+    X64 = w.X.astype(np.float64)
+    Y64 = w.Y.astype(np.float64)
+    Zs = w.Z[qs].astype(np.float64)
+    log("cpu baseline: oracle on %d rows + %d queries, %d threads" % (
+        len(rows), len(qs), threads))
+    c0 = time.perf_counter()
+    N_o, _, _ = oracle.build_model(X64, Y64, w.k, w.kernel, w.nu, w.rho, w.noise, rows=rows,
+                                   nthreads=threads)
+    c1 = time.perf_counter()
+    mu_o, nn_o, _ = oracle.predict(X64, Y64, Zs, w.k, w.kernel, w.nu, w.rho, w.noise,
+                                   nthreads=threads)
+    c2 = time.perf_counter()
+    per_row = (c1 - c0) / len(rows)
+    per_query = (c2 - c1) / len(qs)
+    # whole job at the same shape: build all n rows, predict all m queries
+    est = per_row * args.n + per_query * args.m
+    # one thread, on a smaller sample
+    r1, q1 = rows[:128], Zs[:128]
+    d0 = time.perf_counter()
+    oracle.build_model(X64, Y64, w.k, w.kernel, w.nu, w.rho, w.noise, rows=r1, nthreads=1)
+    d1 = time.perf_counter()
+    oracle.predict(X64, Y64, q1, w.k, w.kernel, w.nu, w.rho, w.noise, nthreads=1)
+    d2 = time.perf_counter()
+    est1 = (d1 - d0) / len(r1) * args.n + (d2 - d1) / len(q1) * args.m
+    result["cpu_baseline"] = {
+        "value": round(args.m / est, 3), "unit": "predictions/s", "cores": threads,
+        "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+        "value_1_thread": round(args.m / est1, 3),
+        "sample": "FP64 oracle on %d seeded training rows and %d seeded queries of the "
+                  "same workload (%.1f s, %d threads); per-item times extrapolated to "
+                  "build(n=%d) + predict(m=%d) = %.0f s; 1-thread rate from 128 rows + 128 "
+                  "queries (%.1f s)" % (len(rows), len(qs), c2 - c0, threads, args.n, args.m,
+                                         est, d2 - d0)}
+
+    def rel_err(got, ref):
+        rms = max(float(np.sqrt(np.mean(ref * ref))), 1e-300)
+        return float(np.max(np.abs(got.astype(np.float64) - ref) / np.maximum(np.abs(ref), rms)))
+
+    def rmse_ratio(got):
+        return float(np.sqrt(np.mean((got - w.Yz[qs]) ** 2)) /
+                     np.sqrt(np.mean((mu_o - w.Yz[qs]) ** 2)))
+
+    chk = {"rows": int(len(rows)), "queries": int(len(qs)),
+           "neighbor_list_mismatches": int(np.count_nonzero(np.any(N_gpu[rows] != N_o, axis=1))),
+           "nearest_mismatches": int(np.count_nonzero(nn_gpu[qs] != nn_o)),
+           "mean_rel_err_mixed": rel_err(mu_gpu[qs], mu_o),
+           "rmse_ratio_mixed": rmse_ratio(mu_gpu[qs])}
+    if mu32 is not None:
+        chk["mean_rel_err_fp32"] = rel_err(mu32[qs], mu_o)
+        chk["rmse_ratio_fp32"] = rmse_ratio(mu32[qs])
+    result["oracle_check"] = chk
+    log("oracle check: %s" % chk)
 
 
 def muygps_run(fmg, np, torch, w, X, Y, Z, out, stream, args, result):

@@ -12,7 +12,8 @@
 // The nearest point of a batch of queries (k = 1, the prediction's lookup)
 // runs one query per lane instead: a wave takes 64 queries and one chunk of
 // candidates, whose coordinates every lane reads at the same address; the
-// chunks are sized so that about 2048 waves fill the device, and a merge
+// chunks are sized so that about 8192 waves (NN_SPLIT_ENTRIES / 64) fill the
+// device, and a merge
 // takes the smallest (distance, index) over the chunks.
 //
 // Neighbourhoods wider than a wavefront (64 < k <= 256) use a pool instead:

@@ -11,8 +11,8 @@
 //       to the requests' host buffers, records latencies, frees the slot.
 // Batches of different slots overlap on the device.  With graphs enabled
 // the enqueued sequence of a batch is captured once per (model, slot,
-// batch-size bucket) and replayed; the queries past the batch in a bucket are
-// stale but finite rows of the pinned buffer and their results are dropped.
+// batch-size bucket) and replayed; the queries past the batch in a bucket
+// repeat its last query and their results are dropped.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -223,6 +223,16 @@ void fmg_server::dispatch_loop() {
         for (fmg_request *r : sl.reqs) {
             memcpy((char *)sl.Zh + off, r->Z, (size_t)r->B * row);
             off += (size_t)r->B * row;
+        }
+        // A graph predicts a whole bucket.  The rows past the batch repeat its
+        // last query: left as they were, they would hold an earlier batch's
+        // bytes, possibly of another model's dtype (FP64 bytes read as FP32
+        // can be NaN or Inf, which fail the certificate and take the exact
+        // rescan).  Their results are dropped.
+        if (opts.use_graphs && m > 0) {
+            const int64_t mb = bucket_of(m, opts.max_batch);
+            const char *last = (const char *)sl.Zh + (size_t)(m - 1) * row;
+            for (int64_t t = m; t < mb; ++t) memcpy((char *)sl.Zh + (size_t)t * row, last, row);
         }
         sl.launch_status = launch(sl, sm, m);
         l.lock();

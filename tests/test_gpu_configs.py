@@ -3,12 +3,15 @@ benchmark times (one build of the whole training set, one predict of the whole
 query set), checked against the FP64 oracle:
 
   cfg1  n=10,000  d=2   k=30 Matern 3/2  FP64   -> full oracle, every row and query
-  cfg2  n=100,000 d=8   k=50 Matern 5/2  FP32   -> sampled oracle
-  cfg3  n=1,000,000 d=40 k=50 RBF ell=10 MIXED  -> sampled oracle
+  cfg2  n=100,000 d=8   k=50 Matern 5/2  FP32   -> full oracle, every row and query
+  cfg3  n=1,000,000 d=40 k=50 RBF ell=10 MIXED  -> sampled oracle: 4,096 rows,
+                                                   20,000 queries
 
 The sampled oracle recomputes, by brute force, the neighbour list and
 coefficient row of seeded sample rows, and the nearest point, neighbourhood,
 coefficients and mean of seeded sample queries."""
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -43,22 +46,38 @@ def gpu_run(w):
     return res
 
 
+def coeff_rel_err(C_gpu, C_ref):
+    """Per row: max |C_gpu - C_ref| / max |C_ref|."""
+    C_gpu = np.asarray(C_gpu, dtype=np.float64)
+    return np.abs(C_gpu - C_ref).max(axis=(1, 2)) / np.abs(C_ref).max(axis=(1, 2))
+
+
 def sampled_check(w, res, rows, queries, prec):
     X64 = w.X.astype(np.float64)
     Y64 = w.Y.astype(np.float64)
+    t0 = time.time()
     Nr, Cr, st = oracle.build_model(X64, Y64, w.k, w.kernel, w.nu, w.rho, w.noise, rows=rows)
     assert np.all(st == 0)
     mism = np.nonzero(np.any(res["N"][rows] != Nr, axis=1))[0]
     assert mism.size == 0, "neighbour lists differ on %d sampled rows" % mism.size
     be = backward_error(X64, Y64, Nr[:64], res["C"][rows[:64]], w.kernel, w.nu, w.rho, w.noise)
     assert np.max(be) < 1e-5
+    ce = coeff_rel_err(res["C"][rows], Cr)
+    t1 = time.time()
     Zs = w.Z[queries].astype(np.float64)
     mu, nn, _ = oracle.predict(X64, Y64, Zs, w.k, w.kernel, w.nu, w.rho, w.noise)
-    assert np.array_equal(res["nn"][queries], nn)
-    assert rel_err(res["mu"][queries], mu) <= TOL_MEAN[prec]
+    nn_mism = int(np.count_nonzero(res["nn"][queries] != nn))
+    err = rel_err(res["mu"][queries], mu)
     yq = w.Yz[queries]
-    assert abs(rmse(res["mu"][queries], yq) / rmse(mu, yq) - 1.0) <= TOL_RMSE
-    return mu
+    rr = rmse(res["mu"][queries], yq) / rmse(mu, yq)
+    print("%s: %d rows (N mismatches 0, coefficient rel err median %.2e max %.2e, %.1f s), "
+          "%d queries (nn mismatches %d, mean rel err %.2e, RMSE ratio %.8f, %.1f s)"
+          % (w.name, len(rows), float(np.median(ce)), float(np.max(ce)), t1 - t0, len(queries),
+             nn_mism, err, rr, time.time() - t1), flush=True)
+    assert nn_mism == 0
+    assert err <= TOL_MEAN[prec]
+    assert abs(rr - 1.0) <= TOL_RMSE
+    return mu, ce
 
 
 def test_cfg1_fp64_full_oracle():
@@ -76,23 +95,44 @@ def test_cfg1_fp64_full_oracle():
     assert abs(rmse(res["mu"], w.Yz) / rmse(mu, w.Yz) - 1.0) <= 1e-9
 
 
-def test_cfg2_fp32_sampled_oracle():
+@pytest.mark.timeout(900)
+def test_cfg2_fp32_full_oracle():
     w = synth.cfg2()
     res = gpu_run(w)
-    rs = synth.rng(2, 4)
-    rows = np.sort(rs.choice(w.X.shape[0], 400, replace=False))
-    queries = np.sort(rs.choice(w.Z.shape[0], 600, replace=False))
-    sampled_check(w, res, rows, queries, "fp32")
     assert res["info"]["nonpd_rows"] == 0
+    X64, Y64, Z64 = (a.astype(np.float64) for a in (w.X, w.Y, w.Z))
+    t0 = time.time()
+    N, C, st = oracle.build_model(X64, Y64, w.k, w.kernel, w.nu, w.rho, w.noise)
+    assert np.all(st == 0)
+    mism = int(np.count_nonzero(np.any(res["N"] != N, axis=1)))
+    assert mism == 0, "neighbour lists differ on %d rows" % mism
+    be = backward_error(X64, Y64, N[::251], res["C"][::251], w.kernel, w.nu, w.rho, w.noise)
+    assert np.max(be) < 1e-5
+    mu, nn, _ = oracle.predict(X64, Y64, Z64, w.k, w.kernel, w.nu, w.rho, w.noise,
+                               model=(N, C, st))
+    nn_mism = int(np.count_nonzero(res["nn"] != nn))
+    err = rel_err(res["mu"], mu)
+    rr = rmse(res["mu"], w.Yz) / rmse(mu, w.Yz)
+    print("cfg2 full oracle (%.1f s): N mismatches %d of %d rows, nn mismatches %d of %d, "
+          "mean rel err %.2e, RMSE ratio %.8f, max backward error %.2e"
+          % (time.time() - t0, mism, N.shape[0], nn_mism, nn.shape[0], err, rr, float(np.max(be))),
+          flush=True)
+    assert nn_mism == 0
+    assert err <= TOL_MEAN["fp32"]
+    assert abs(rr - 1.0) <= TOL_RMSE
 
 
+@pytest.mark.timeout(900)
 def test_cfg3_mixed_sampled_oracle():
     w = synth.cfg3()
     res = gpu_run(w)
     rs = synth.rng(3, 4)
-    rows = np.sort(rs.choice(w.X.shape[0], 96, replace=False))
-    queries = np.sort(rs.choice(w.Z.shape[0], 160, replace=False))
-    sampled_check(w, res, rows, queries, "mixed")
+    rows = np.sort(rs.choice(w.X.shape[0], 4096, replace=False))
+    queries = np.sort(rs.choice(w.Z.shape[0], 20000, replace=False))
+    mu, ce = sampled_check(w, res, rows, queries, "mixed")
+    # refined coefficients: kappa is ~10-14 on this workload, so the FP32
+    # storage of C bounds their error (u_32 = 6e-8, times a small factor)
+    assert float(np.max(ce)) < 1e-5
     assert res["info"]["nonpd_rows"] == 0
     # classification accuracy on the whole test set (argmax of the one-hot means)
     acc = float(np.mean(np.argmax(res["mu"], axis=1) == w.extra["labels_test"]))

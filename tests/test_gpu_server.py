@@ -49,6 +49,13 @@ def test_alone_and_in_the_mix(use_graphs):
     plain, Xb, Yb, Zb = build("fp32", 4000, 2000, 5, 2, 20, seed=12)
     f64, Xc, Yc, Zc = build("fp64", 1500, 800, 3, 1, 16, seed=13)
     refs = {"a": direct(mixed, Za), "b": direct(plain, Zb), "c": direct(f64, Zc)}
+    # These queries certify on the first screen: direct prediction needs no
+    # exact rescan.  Served batches must not need one either (the padding of
+    # a replayed bucket must not turn into invalid queries after batches of
+    # another model, e.g. FP64 bytes left in the staging rows read as FP32).
+    fb0 = {key: m.info()["predict_fallback_rows"] for key, m in
+           (("a", mixed), ("b", plain), ("c", f64))}
+    assert fb0 == {"a": 0, "b": 0, "c": 0}
     with f.Server(slots=3, max_batch=2048, use_graphs=use_graphs) as srv:
         ids = {"a": srv.add_model(mixed), "b": srv.add_model(plain), "c": srv.add_model(f64)}
         assert all(adm for _, adm in ids.values())
@@ -84,6 +91,8 @@ def test_alone_and_in_the_mix(use_graphs):
     assert st["queries"] == 2 * sum(hi - lo for _, lo, hi in reqs)
     assert st["batches"] < st["requests"]  # the mix was coalesced
     assert 0.0 <= st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+    for key, m in (("a", mixed), ("b", plain), ("c", f64)):
+        assert m.info()["predict_fallback_rows"] == 0, key
     for m in (mixed, plain, f64):
         m.free()
 

@@ -73,13 +73,31 @@ def test_kernels(prec, kernel, nu):
     check_against_oracle(prec, X, Y, Z, 20, kernel, nu, 0.05, 1e-3, out)
 
 
+# Measured on MI355X (max relative mean error over the 400 queries):
+#   Matern 5/2: kappa ~2.0e4, cancellation 3.5e4, mixed 1.71e-3, FP32 1.65e-3;
+#   RBF:        kappa ~1.9e4, cancellation 2.5e4, mixed 7.6e-4,  FP32 9.8e-4.
+# The fixed ceilings sit at about twice these, so a regression cannot hide
+# under the (much looser) data-dependent bound.
+ILL_CEILING = {("matern", "mixed"): 3.5e-3, ("matern", "fp32"): 3.5e-3,
+               ("rbf", "mixed"): 1.6e-3, ("rbf", "fp32"): 2e-3}
+
+
 @pytest.mark.parametrize("rho,kernel,nu", [(1.0, "matern", 2.5), (0.3, "rbf", 0.0)])
 def test_ill_conditioned_needs_refinement(rho, kernel, nu):
-    """kappa ~ 3e3 .. 2e4.  The refined MIXED coefficients are accurate to the
-    FP32 storage of C: the remaining mean error is bounded by the rounding of
-    the dot product sum_s |phi_s C_s| in FP32, which refinement cannot remove.
-    The plain FP32 coefficients also carry the kappa * u_32 solve error, which
-    the refinement removes from the coefficients."""
+    """kappa ~ 3e3 .. 2e4, beyond where the 2e-4 mean tolerance is promised.
+
+    The refined MIXED coefficients are accurate to the FP32 storage of C.  The
+    mean is the FP32 dot product sum_s phi_s C_s; its rounding error, and the
+    error that the FP32 storage of C carries into it, are bounded by about
+    k * u_32 * sum_s |phi_s C_s|, and refinement cannot remove that.  When the
+    terms cancel (sum |phi_s C_s| >> |mu|, which ill-conditioned
+    neighbourhoods cause), the relative error grows by the cancellation
+    factor cs = sum_s |phi_s C_s| / max(|mu|, RMS(mu)).  So the test's bar is
+    max(2e-4, 4 k u_32 cs) for MIXED and 4x that for plain FP32 (whose
+    coefficients also carry the kappa * u_32 solve error), plus a fixed
+    ceiling at about twice the measured error.  The plain FP32 coefficients
+    carry the kappa * u_32 solve error, which refinement removes: the refined
+    coefficients must be at least 10x more accurate."""
     d = 2 if kernel == "matern" else 3
     k = 20
     X, Y, Z = synth.small(3001, 400, d, ell=1, seed=31, dist="normal" if d == 2 else "uniform")
@@ -102,9 +120,17 @@ def test_ill_conditioned_needs_refinement(rho, kernel, nu):
         nb = N[nn[t]]
         w = oracle.phi(((X64[nb] - Z64[t]) ** 2).sum(axis=1), kernel, nu, rho, 1.0)
         cs = max(cs, float(np.sum(np.abs(w * C[nn[t], :, 0]))) / max(abs(mu[t, 0]), rms))
+    kap = [np.linalg.cond(oracle.assemble(X64, N[i], kernel, nu, rho, 1e-3, 1.0))
+           for i in range(0, N.shape[0], 10)]
     bound = 4.0 * k * np.finfo(np.float32).eps * cs
+    print("ill-conditioned %s: kappa median %.3g max %.3g; cancellation %.3g; bound %.3g; "
+          "mean rel err mixed %.3g fp32 %.3g; median coefficient err mixed %.3g fp32 %.3g"
+          % (kernel, float(np.median(kap)), float(np.max(kap)), cs, bound, errs["mixed"],
+             errs["fp32"], cerr["mixed"], cerr["fp32"]), flush=True)
     assert errs["mixed"] <= max(TOL_MEAN["mixed"], bound), (errs, bound)
     assert errs["fp32"] <= max(TOL_MEAN["fp32"], 4.0 * bound), (errs, bound)
+    assert errs["mixed"] <= ILL_CEILING[(kernel, "mixed")], errs
+    assert errs["fp32"] <= ILL_CEILING[(kernel, "fp32")], errs
     # the refined coefficients are accurate to their FP32 storage; the plain
     # ones carry the kappa * u_32 solve error
     assert cerr["mixed"] < 1e-5 and cerr["mixed"] * 10.0 < cerr["fp32"], cerr
