@@ -160,6 +160,31 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
 fmg_status fastmuygps_predict(const fmg_model *model, const void *Z, int64_t m, void *out,
                               int32_t *nn_out, void *stream);
 
+/* Allocation-free prediction, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Computes exactly what fastmuygps_predict computes (same
+ * kernels; neighbour index and means bit-identical), but every scratch buffer
+ * comes from one static device array that the library holds on each GPU it
+ * runs on until the process ends (fastmuygps_noalloc_scratch_bytes(), about
+ * 87 MiB); no hipMalloc, hipFree or allocating library routine is called.
+ *   Z, out, nn_out : as in fastmuygps_predict (caller-owned device memory).
+ *   m              : 0 <= m <= FMG_NOALLOC_MAX_M queries per call (m = 0 is
+ *                    a no-op); split larger batches.
+ * The model must live on the current device.  The array keeps the last
+ * call's contents; every buffer that must start cleared is cleared by a
+ * kernel on `stream` (no memset).  All calls on one GPU share its array, so
+ * calls that overlap on one GPU (different streams or host threads without
+ * ordering between them) race: order them on one stream or synchronise.
+ * Errors: FMG_E_INVALID_ARG (null model or pointer, m < 0,
+ * m > FMG_NOALLOC_MAX_M, model on another device), FMG_E_BUSY (model
+ * offloaded by a server), FMG_E_DEVICE. */
+#define FMG_NOALLOC_MAX_M 4096
+fmg_status fastmuygps_predict_noalloc(const fmg_model *model, const void *Z, int64_t m,
+                                      void *out, int32_t *nn_out, void *stream);
+/* Bytes of the static scratch array fastmuygps_predict_noalloc uses on each
+ * device. */
+uint64_t fastmuygps_noalloc_scratch_bytes(void);
+
 /* MuyGPs prediction of novel points (Section 2.1, MuyGPs prediction
  * equation): the per-query method whose training-data part FastMuyGPs
  * precomputes.  For every query z:

@@ -48,7 +48,11 @@ EXPORTS = ("fastmuygps_build", "fastmuygps_predict", "fastmuygps_info", "fastmuy
            "fastmuygps_server_create", "fastmuygps_server_add_model",
            "fastmuygps_server_remove_model", "fastmuygps_server_submit", "fastmuygps_server_wait",
            "fastmuygps_server_stats", "fastmuygps_server_reset_stats",
-           "fastmuygps_server_destroy", "fastmuygps_release_cached")
+           "fastmuygps_server_destroy", "fastmuygps_release_cached",
+           "fastmuygps_predict_noalloc", "fastmuygps_noalloc_scratch_bytes")
+
+# Largest batch of one fastmuygps_predict_noalloc call (FMG_NOALLOC_MAX_M).
+NOALLOC_MAX_M = 4096
 
 
 class FmgHyper(ctypes.Structure):
@@ -105,6 +109,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fastmuygps_build.restype = ctypes.c_int
     lib.fastmuygps_predict.argtypes = [P, P, ctypes.c_int64, P, P, P]
     lib.fastmuygps_predict.restype = ctypes.c_int
+    lib.fastmuygps_predict_noalloc.argtypes = [P, P, ctypes.c_int64, P, P, P]
+    lib.fastmuygps_predict_noalloc.restype = ctypes.c_int
+    lib.fastmuygps_noalloc_scratch_bytes.argtypes = []
+    lib.fastmuygps_noalloc_scratch_bytes.restype = ctypes.c_uint64
     lib.fastmuygps_predict_muygps.argtypes = [P, P, ctypes.c_int64, P, P, P]
     lib.fastmuygps_predict_muygps.restype = ctypes.c_int
     lib.fastmuygps_loo_predict.argtypes = [P, P, ctypes.c_int64, P, P]
@@ -226,6 +234,23 @@ class Model:
         _check(lib().fastmuygps_predict(self.handle, _dev_ptr(Z, self.dtype, "Z"), m,
                                        _dev_ptr(out, self.dtype, "out"), nn_ptr,
                                        _stream_handle(stream)))
+        return out
+
+    def predict_noalloc(self, Z: torch.Tensor, out: torch.Tensor, nn_out: torch.Tensor | None = None,
+                        stream=None) -> torch.Tensor:
+        """fastmuygps_predict_noalloc: the prediction of `predict` with no
+        device allocation (scratch in the library's static per-device array);
+        at most NOALLOC_MAX_M queries per call, `out` supplied by the caller."""
+        if Z.dim() != 2 or Z.shape[1] != self.d:
+            raise ValueError("Z must be [m, %d]" % self.d)
+        if out.dim() != 2 or out.shape[0] != Z.shape[0] or out.shape[1] != self.ell:
+            raise ValueError("out must be [m, %d]" % self.ell)
+        nn_ptr = None
+        if nn_out is not None:
+            nn_ptr = _dev_ptr(nn_out, torch.int32, "nn_out")
+        _check(lib().fastmuygps_predict_noalloc(self.handle, _dev_ptr(Z, self.dtype, "Z"),
+                                               Z.shape[0], _dev_ptr(out, self.dtype, "out"),
+                                               nn_ptr, _stream_handle(stream)))
         return out
 
     def predict_muygps(self, Z: torch.Tensor, out: torch.Tensor | None = None,
@@ -395,6 +420,17 @@ def fastmuygps_build(X: torch.Tensor, Y: torch.Tensor, k: int, kernel: str = "ma
 def fastmuygps_predict(model: Model, Z: torch.Tensor, out=None, nn_out=None, stream=None):
     """fastmuygps_predict(model, Z) -> means (Algorithm 2, prediction)."""
     return model.predict(Z, out=out, nn_out=nn_out, stream=stream)
+
+
+def fastmuygps_predict_noalloc(model: Model, Z: torch.Tensor, out, nn_out=None, stream=None):
+    """fastmuygps_predict_noalloc(model, Z, out): prediction without device
+    allocation, at most NOALLOC_MAX_M queries."""
+    return model.predict_noalloc(Z, out, nn_out=nn_out, stream=stream)
+
+
+def noalloc_scratch_bytes() -> int:
+    """Bytes of the static device array the allocation-free prediction uses."""
+    return int(lib().fastmuygps_noalloc_scratch_bytes())
 
 
 def fastmuygps_info(model: Model) -> dict:

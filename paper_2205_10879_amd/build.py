@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libfastmuygps.so")
 
 SOURCES = ["fmg_api.hip", "fmg_prep.hip", "fmg_exact.hip", "fmg_screen.hip", "fmg_rerank.hip",
            "fmg_precompute.hip", "fmg_precompute32.hip", "fmg_precompute_wide.hip", "fmg_predict.hip",
-           "fmg_server.hip", "fmg_loss.hip", "fmg_grad.hip", "fmg_prune.hip"]
+           "fmg_server.hip", "fmg_loss.hip", "fmg_grad.hip", "fmg_prune.hip", "fmg_noalloc.hip"]
 
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

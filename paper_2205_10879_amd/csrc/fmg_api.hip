@@ -270,6 +270,8 @@ bool screen_geom(int prec, int d, ScreenGeom *g) {
 
 namespace fmg {
 
+void clear_error() { g_err.clear(); }
+
 fmg_status set_error(fmg_status st, const char *fmt, ...) {
     char buf[512];
     va_list ap;
@@ -306,22 +308,36 @@ int64_t ws_pool_rows(int64_t max_m) {
     return splits * m_pad;
 }
 
-constexpr int64_t WS_ROW_BYTES = 256;  // largest screening row (FP32, kp = 64)
-
 }  // namespace
 
 uint64_t predict_ws_bytes(int64_t max_m) {
+    return predict_ws_span(max_m, ws_pool_rows(max_m));
+}
+
+void predict_ws_carve(PredictWs *ws, void *base, int64_t max_m, int64_t pool_rows) {
+    *ws = PredictWs{};
     const int64_t m_pad = round_up(max_m, SCREEN_QPB);
-    const int64_t rows = ws_pool_rows(max_m);
-    uint64_t b = 0;
-    b += (uint64_t)m_pad * WS_ROW_BYTES;                 // Zq
-    b += (uint64_t)max_m * 16;                           // ez, nzz
-    b += (uint64_t)rows * SCREEN_CAP * 8;                // pool
-    b += (uint64_t)rows * SCREEN_CMAX * 8;               // cand (c' <= SCREEN_CMAX)
-    b += (uint64_t)rows * 4;                             // tq
-    b += (uint64_t)max_m * 8 + 16;                       // fbl, nn, fbc
-    b += (uint64_t)NN_SPLIT_ENTRIES * 12;                // nn_key, nn_idx
-    return b;
+    char *p = (char *)base;
+    auto take = [&p](uint64_t bytes) {
+        void *q = p;
+        p += ws_align(bytes);
+        return q;
+    };
+    ws->base = base;
+    ws->Zq = take((uint64_t)m_pad * WS_ROW_BYTES);
+    ws->ez = (double *)take((uint64_t)max_m * 8);
+    ws->nzz = (double *)take((uint64_t)max_m * 8);
+    ws->pool = (uint64_t *)take((uint64_t)pool_rows * SCREEN_CAP * 8);
+    ws->cand = (uint64_t *)take((uint64_t)pool_rows * SCREEN_CMAX * 8);
+    ws->tq = (float *)take((uint64_t)pool_rows * 4);
+    ws->fbl = (int32_t *)take((uint64_t)max_m * 4);
+    ws->nn = (int32_t *)take((uint64_t)max_m * 4);
+    ws->fbc = (int32_t *)take(16);
+    ws->nn_key = (uint64_t *)take((uint64_t)NN_SPLIT_ENTRIES * 8);
+    ws->nn_idx = (int32_t *)take((uint64_t)NN_SPLIT_ENTRIES * 4);
+    ws->max_m = max_m;
+    ws->pool_rows = pool_rows;
+    ws->bytes = predict_ws_span(max_m, pool_rows);
 }
 
 fmg_status predict_ws_alloc(PredictWs *ws, int64_t max_m) {
@@ -329,46 +345,21 @@ fmg_status predict_ws_alloc(PredictWs *ws, int64_t max_m) {
     if (max_m < 1) return fail(FMG_E_INVALID_ARG, "workspace for %lld queries", (long long)max_m);
     const int64_t m_pad = round_up(max_m, SCREEN_QPB);
     const int64_t rows = ws_pool_rows(max_m);
-    struct Item {
-        void **p;
-        size_t bytes;
-    } items[] = {
-        {&ws->Zq, (size_t)m_pad * WS_ROW_BYTES},
-        {(void **)&ws->ez, (size_t)max_m * 8},
-        {(void **)&ws->nzz, (size_t)max_m * 8},
-        {(void **)&ws->pool, (size_t)rows * SCREEN_CAP * 8},
-        {(void **)&ws->cand, (size_t)rows * SCREEN_CMAX * 8},
-        {(void **)&ws->tq, (size_t)rows * 4},
-        {(void **)&ws->fbl, (size_t)max_m * 4},
-        {(void **)&ws->nn, (size_t)max_m * 4},
-        {(void **)&ws->fbc, 16},
-        {(void **)&ws->nn_key, (size_t)NN_SPLIT_ENTRIES * 8},
-        {(void **)&ws->nn_idx, (size_t)NN_SPLIT_ENTRIES * 4},
-    };
-    for (auto &it : items) {
-        hipError_t e = hipMalloc(it.p, it.bytes);
-        if (e != hipSuccess) {
-            predict_ws_free(ws);
-            return hip_fail(e, "prediction workspace");
-        }
-        ws->bytes += it.bytes;
-    }
+    void *base = nullptr;
+    hipError_t e = hipMalloc(&base, predict_ws_span(max_m, rows));
+    if (e != hipSuccess) return hip_fail(e, "prediction workspace");
+    predict_ws_carve(ws, base, max_m, rows);
     // Query rows past a batch are read by the screen: keep them finite.
-    hipError_t e = hipMemset(ws->Zq, 0, (size_t)m_pad * WS_ROW_BYTES);
+    e = hipMemset(ws->Zq, 0, (size_t)m_pad * WS_ROW_BYTES);
     if (e != hipSuccess) {
         predict_ws_free(ws);
         return hip_fail(e, "hipMemset");
     }
-    ws->max_m = max_m;
-    ws->pool_rows = rows;
     return FMG_OK;
 }
 
 void predict_ws_free(PredictWs *ws) {
-    void *ptrs[] = {ws->Zq,  ws->ez, ws->nzz, ws->pool,   ws->cand,  ws->tq,
-                    ws->fbl, ws->nn, ws->fbc, ws->nn_key, ws->nn_idx};
-    for (void *p : ptrs)
-        if (p) (void)hipFree(p);
+    if (ws->base) (void)hipFree(ws->base);
     *ws = PredictWs{};
 }
 

@@ -74,6 +74,7 @@ namespace fmg {
 // that a prediction allocates nothing.  Sized for any model the library can
 // build (screen rows of at most 256 bytes, c' <= SCREEN_CMAX).
 struct PredictWs {
+    void *base = nullptr;   // the one block the buffers below are carved from
     int64_t max_m = 0;
     int64_t pool_rows = 0;  // capacity of the screen pool in (split, query) rows
     void *Zq = nullptr;
@@ -87,12 +88,37 @@ struct PredictWs {
 };
 
 constexpr int PREDICT_MAX_SPLITS = 32;
+constexpr int64_t WS_ROW_BYTES = 256;  // largest screening row (FP32, kp = 64)
+
+constexpr uint64_t ws_align(uint64_t b) { return (b + 255) & ~(uint64_t)255; }
+
+// Bytes of a workspace for up to max_m queries whose screen pool holds
+// pool_rows (split, query) rows, in the layout of predict_ws_carve: each
+// buffer starts on a 256-byte boundary.
+constexpr uint64_t predict_ws_span(int64_t max_m, int64_t pool_rows) {
+    const uint64_t m_pad = (uint64_t)((max_m + SCREEN_QPB - 1) / SCREEN_QPB * SCREEN_QPB);
+    return ws_align(m_pad * WS_ROW_BYTES)                      // Zq
+           + 2 * ws_align((uint64_t)max_m * 8)                 // ez, nzz
+           + ws_align((uint64_t)pool_rows * SCREEN_CAP * 8)    // pool
+           + ws_align((uint64_t)pool_rows * SCREEN_CMAX * 8)   // cand (c' <= SCREEN_CMAX)
+           + ws_align((uint64_t)pool_rows * 4)                 // tq
+           + 2 * ws_align((uint64_t)max_m * 4)                 // fbl, nn
+           + ws_align(16)                                      // fbc
+           + ws_align((uint64_t)NN_SPLIT_ENTRIES * 8)          // nn_key
+           + ws_align((uint64_t)NN_SPLIT_ENTRIES * 4);         // nn_idx
+}
+
+// Point the buffers of ws into [base, base + predict_ws_span(max_m,
+// pool_rows)).  Nothing is allocated or written.
+void predict_ws_carve(PredictWs *ws, void *base, int64_t max_m, int64_t pool_rows);
 // Direct predictions of at least this many queries on a model with a pivot
 // order use the pruned screen (enough workgroups to fill the device from one
 // column range).
 constexpr int64_t PREDICT_PRUNE_MIN = 65536;
 
 fmg_status set_error(fmg_status st, const char *fmt, ...);
+// Clear the calling thread's last error message.
+void clear_error();
 // Bytes of a workspace for max_m queries.
 uint64_t predict_ws_bytes(int64_t max_m);
 fmg_status predict_ws_alloc(PredictWs *ws, int64_t max_m);

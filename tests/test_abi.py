@@ -161,3 +161,24 @@ def test_wide_neighbourhood_limits_are_checked_before_any_device_work(lib):
     assert b(fake, fake, 1000, 4, 1, 256, ctypes.byref(hy), fmg.PREC_FP64, 0, None,
              ctypes.byref(out)) == fmg.FMG_E_UNSUPPORTED
     assert out.value is None
+
+
+def test_noalloc_predict_rejects_bad_arguments_before_any_device_call(lib):
+    import paper_2205_10879_amd as fmg
+    fake = ctypes.c_void_p(16)  # never dereferenced: arguments are checked first
+    assert lib.fastmuygps_predict_noalloc(None, fake, 5, fake, None, None) == fmg.FMG_E_INVALID_ARG
+    assert lib.fastmuygps_predict_noalloc(fake, fake, -1, fake, None, None) == fmg.FMG_E_INVALID_ARG
+    st = lib.fastmuygps_predict_noalloc(fake, fake, fmg.NOALLOC_MAX_M + 1, fake, None, None)
+    assert st == fmg.FMG_E_INVALID_ARG
+    assert b"allocation-free limit" in lib.fastmuygps_last_error()
+    assert lib.fastmuygps_predict_noalloc(fake, fake, 0, fake, None, None) == fmg.FMG_OK
+    # a modest static array: the batch limit's workspace, well under 128 MiB
+    assert 64 << 20 < lib.fastmuygps_noalloc_scratch_bytes() < 128 << 20
+
+
+def test_noalloc_limit_matches_the_header():
+    import re
+
+    import paper_2205_10879_amd as fmg
+    text = open(HEADER).read()
+    assert int(re.search(r"#define FMG_NOALLOC_MAX_M (\d+)", text).group(1)) == fmg.NOALLOC_MAX_M
