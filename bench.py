@@ -146,6 +146,18 @@ def main():
                 "traffic": screen_traffic(args.n), "avg_launch_ms": round(screen_ms, 3),
                 "algorithmic_flops_per_launch": flops}
 
+    # The prediction gather-dot (HBM-bound): per query it must read the query
+    # row, j, N(j), the k neighbour rows, C[j] and write ell means.
+    d_, k_, ell_ = int(w.X.shape[1]), w.k, int(w.Y.shape[1])
+    gbytes = args.m * (4 * d_ + 4 + 4 * k_ + 4 * k_ * d_ + 4 * k_ * ell_ + 4 * ell_)
+    gather_ms = avg("predict_gather_ms")
+    gather_gbs = gbytes / (gather_ms / 1000.0) / 1e9
+    gather_roofline = {"bound": "hbm", "kernel": "gather_vec_kernel<float,10,10>",
+                       "achieved": round(gather_gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                       "frac": round(gather_gbs / PEAK_HBM_GBS, 4),
+                       "avg_launch_ms": round(gather_ms, 4),
+                       "algorithmic_bytes_per_launch": gbytes}
+
     result = {
         "metric": "predictions/s + p99 latency (n=1M,k=50) vs plain FP32 path at equal RMSE",
         "value": round(value, 1),
@@ -171,6 +183,7 @@ def main():
         "rmse_mixed": rmse_mixed,
         "accuracy_mixed": acc_mixed,
         "roofline": roofline,
+        "gather_roofline": gather_roofline,
     }
 
     if not args.no_fp32:

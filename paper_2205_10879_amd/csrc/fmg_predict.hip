@@ -11,6 +11,8 @@
 #include "fmg_device.h"
 #include "fmg_kernels.h"
 
+#include <type_traits>
+
 namespace fmg {
 
 namespace {
@@ -104,6 +106,138 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherArgs a) {
     }
 }
 
+// Neighbourhoods of at most one row per lane, rows of 16-byte vectors, and
+// no divergent branch before the reductions:
+//   - what depends only on the query comes by scalar loads: its position in
+//     the order, its coefficient row j, its coordinates (every lane needs
+//     them);
+//   - C[j] (k * ell contiguous values) is read by coalesced loads of the
+//     whole block into the wave's LDS slice, from which lane s takes row s;
+//   - every lane, live or not, loads a valid neighbour row (indices past k
+//     repeat the last), all NV vectors issued before the first is used;
+//     vectors past the row and lanes past k are masked out of the sums.
+template <typename T>
+using const_ptr = const __attribute__((address_space(4))) T *;
+
+typedef float gv_f32x4 __attribute__((ext_vector_type(4)));
+typedef double gv_f64x2 __attribute__((ext_vector_type(2)));
+
+#ifndef FMG_GATHER_QPW
+#define FMG_GATHER_QPW 2
+#endif
+constexpr int GQ = FMG_GATHER_QPW;  // consecutive queries (in the order) per wave
+#ifndef FMG_GATHER_WAVES
+#define FMG_GATHER_WAVES 4
+#endif
+constexpr int GV_WAVES = FMG_GATHER_WAVES;  // waves per workgroup
+
+template <typename T, int NV, int ELLMAX>
+__global__ __launch_bounds__(64 * GV_WAVES) void gather_vec_kernel(GatherArgs a) {
+    typedef typename std::conditional<sizeof(T) == 4, gv_f32x4, gv_f64x2>::type V;
+    constexpr int EPV = 16 / (int)sizeof(T);  // elements per vector
+    constexpr int CB = 64 * ELLMAX + ELLMAX;  // one C[j] in LDS (row reads stay inside)
+    __shared__ T cbuf[GV_WAVES * CB];
+    const int lane = lane_id();
+    const int wave = (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t w0 = ((int64_t)blockIdx.x * GV_WAVES + wave) * GQ;
+    if (w0 >= a.m) return;
+    const int cnt = (int)(a.m - w0 < GQ ? a.m - w0 : GQ);
+    const int ell = a.ell, k = a.k, d = a.d, nv = d / EPV, kl = k * ell;
+    const int s = lane < k ? lane : k - 1;
+    T *__restrict__ cb = cbuf + wave * CB;
+
+    // Head of query w: its index, row of Z and coefficient row (scalar
+    // loads), then its neighbour indices and C[j] block (vector loads).
+    // A query whose rows fall outside the arrays reads row 0 and is written
+    // as NaN.
+    int64_t q = 0, zr = 0, j = 0, p = 0;
+    bool ok = false;
+    T cf[ELLMAX];
+    auto head = [&](int64_t w) {
+        q = a.order ? (int64_t)((const_ptr<uint32_t>)a.order)[w] : w;
+        zr = a.zrow ? (int64_t)((const_ptr<int32_t>)a.zrow)[q] : q;
+        j = a.nn ? (int64_t)((const_ptr<int32_t>)a.nn)[q] : q;
+        ok = zr >= 0 && zr < a.zrows && j >= 0 && j < a.crows;
+        if (!ok) zr = j = 0;
+        p = a.N[j * k + s];
+        const T *__restrict__ Cj = (const T *)a.C + j * kl;
+#pragma unroll
+        for (int t = 0; t < ELLMAX; ++t) {
+            const int f = lane + 64 * t;
+            cf[t] = Cj[f < kl ? f : kl - 1];
+        }
+    };
+    head(w0);
+    for (int i = 0; i < cnt; ++i) {
+        const int64_t qi = q, zri = zr;
+        const bool oki = ok;
+        // this query's neighbour rows and coordinates
+        const V *__restrict__ xr = (const V *)((const T *)a.X + p * d);
+        V xv[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) xv[v] = xr[v < nv ? v : nv - 1];
+        const const_ptr<V> zc = (const_ptr<V>)((const T *)a.Z + zri * d);
+        V zv[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) zv[v] = zc[v < nv ? v : nv - 1];
+        // its C[j] into the wave's LDS slice (a wave's LDS accesses are
+        // processed in order, so the previous query's reads are done), then
+        // the next query's head
+#pragma unroll
+        for (int t = 0; t < ELLMAX; ++t) cb[lane + 64 * t] = cf[t];
+        if (i + 1 < cnt) head(w0 + i + 1);
+        T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const bool in = v < nv;
+            if constexpr (sizeof(T) == 4) {
+                const float t0 = in ? zv[v].x - xv[v].x : 0.0f;
+                const float t1 = in ? zv[v].y - xv[v].y : 0.0f;
+                const float t2 = in ? zv[v].z - xv[v].z : 0.0f;
+                const float t3 = in ? zv[v].w - xv[v].w : 0.0f;
+                s0 = fmaf(t0, t0, s0);
+                s1 = fmaf(t1, t1, s1);
+                s2 = fmaf(t2, t2, s2);
+                s3 = fmaf(t3, t3, s3);
+            } else {
+                const double t0 = in ? zv[v].x - xv[v].x : 0.0, t1 = in ? zv[v].y - xv[v].y : 0.0;
+                if (v & 1) {
+                    s2 = fma(t0, t0, s2);
+                    s3 = fma(t1, t1, s3);
+                } else {
+                    s0 = fma(t0, t0, s0);
+                    s1 = fma(t1, t1, s1);
+                }
+            }
+        }
+        const T wk = phi_t<T>((s0 + s1) + (s2 + s3), a.kc, (T)a.inv_rho, (T)a.amp);
+        const T wgt = lane < k ? wk : T(0);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const T *__restrict__ crow = cb + s * ell;
+        T *__restrict__ out = (T *)a.out + qi * ell;
+#pragma unroll
+        for (int c = 0; c < ELLMAX; ++c) {
+            const T t = dpp_t_sum_last<T>(wgt * crow[c], lane);
+            if (lane == 63 && c < ell) out[c] = oki ? t : (T)NAN;
+        }
+    }
+}
+
+template <typename T, int NV>
+void launch_gather_vec_nv(const GatherArgs &a, unsigned blocks, hipStream_t s) {
+#define FMG_GV(E) hipLaunchKernelGGL((gather_vec_kernel<T, NV, E>), dim3(blocks), dim3(64 * GV_WAVES), 0, s, a)
+    if (a.ell <= 1) FMG_GV(1);
+    else if (a.ell <= 2) FMG_GV(2);
+    else if (a.ell <= 4) FMG_GV(4);
+    else if (a.ell <= 8) FMG_GV(8);
+    else if (a.ell <= 10) FMG_GV(10);
+    else if (a.ell <= 12) FMG_GV(12);
+    else FMG_GV(16);
+#undef FMG_GV
+}
+
 // Response columns are reduced up to ELLMAX (zeros past ell are not stored).
 template <typename T, bool VEC, int KR>
 void launch_gather_kr(const GatherArgs &a, unsigned blocks, hipStream_t s) {
@@ -121,7 +255,18 @@ void launch_gather_kr(const GatherArgs &a, unsigned blocks, hipStream_t s) {
 
 template <typename T, bool VEC>
 void launch_gather_t(const GatherArgs &a, unsigned blocks, hipStream_t s) {
-    if (a.k <= 64) launch_gather_kr<T, VEC, 1>(a, blocks, s);
+    constexpr int EPV = 16 / (int)sizeof(T);
+    const int nv = a.d / EPV;
+    if (VEC && a.k <= 64 && nv <= 16) {
+        blocks = (unsigned)((a.m + GV_WAVES * GQ - 1) / (GV_WAVES * GQ));
+        if (nv <= 1) launch_gather_vec_nv<T, 1>(a, blocks, s);
+        else if (nv <= 2) launch_gather_vec_nv<T, 2>(a, blocks, s);
+        else if (nv <= 4) launch_gather_vec_nv<T, 4>(a, blocks, s);
+        else if (nv <= 8) launch_gather_vec_nv<T, 8>(a, blocks, s);
+        else if (nv <= 10) launch_gather_vec_nv<T, 10>(a, blocks, s);
+        else if (nv <= 12) launch_gather_vec_nv<T, 12>(a, blocks, s);
+        else launch_gather_vec_nv<T, 16>(a, blocks, s);
+    } else if (a.k <= 64) launch_gather_kr<T, VEC, 1>(a, blocks, s);
     else launch_gather_kr<T, VEC, 4>(a, blocks, s);
 }
 
