@@ -852,8 +852,7 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
         // tiles whose bounding balls no query of a wavefront can reach; the
         // re-rank takes the rows in the same order and maps the candidates'
         // indices back.
-        const bool prune = geom.mode == SCREEN_BF16 && !(flags & FMG_FLAG_NO_PRUNE) &&
-                           prune_pivots(n) > 1 && d <= 64;
+        const bool prune = !(flags & FMG_FLAG_NO_PRUNE) && prune_pivots(n) > 1 && d <= 64;
         uint32_t *perm = nullptr;
         if (prune) {
             uint32_t *asg = nullptr, *asg2 = nullptr, *idx = nullptr;

@@ -8,19 +8,18 @@
 //      nearest pivot of every point (FP32 distances of the centred
 //      coordinates; any assignment is correct, a good one makes tiles
 //      compact);
-//   2. a stable sort by pivot label (hipCUB radix sort over (label, index)),
-//      giving the permutation perm: position i of the screen holds point
-//      perm[i]; the cells of one cluster form a run;
+//   2. a stable sort by pivot label (a one-pass counting sort: per-tile label
+//      counts, their exclusive scan in (label, tile) order, and an in-order
+//      scatter), giving the permutation perm: position i of the screen holds
+//      point perm[i]; the cells of one cluster form a run;
 //   3. the screening rows gathered into that order, with the query norms;
-//   4. per tile of 64 rows: the centroid of its BF16 rows, itself rounded to
-//      BF16 (so it is an exact point of the screened space) and written as a
-//      candidate row, and the FP64 radius max ||x~ - c~|| over the tile's real
-//      rows, rounded up;
+//   4. per tile of 64 rows: the centroid of its screening rows (BF16 or
+//      FP32), itself rounded to the row's format (so it is an exact point of
+//      the screened space) and written as a candidate row, and the FP64
+//      radius max ||x~ - c~|| over the tile's real rows, rounded up;
 //   5. the re-rank takes the rows in the same order and maps each
 //      candidate's index back to its training index, so that the certificate
 //      runs unchanged.
-#include <hipcub/hipcub.hpp>
-
 #include "fmg_device.h"
 #include "fmg_kernels.h"
 
@@ -241,6 +240,171 @@ __global__ __launch_bounds__(64) void tile_bounds_kernel(const uint16_t *__restr
     if (lane == 0) rad[tile] = (float)(sqrt(mx) * (1.0 + 1.0e-6)) * (1.0f + 1.0e-6f);
 }
 
+// One wave per tile of 64 FP32 candidate rows [-2 x~, ||x~||^2, 0 ...] (kp
+// floats, a multiple of 16): the centroid of the rows' x~, rounded to FP32,
+// written as a candidate row (its norm rounded to FP32, within the 1e-6
+// relative slack of the screen's error bound), and the FP64 radius.
+__global__ __launch_bounds__(64) void tile_bounds_f32_kernel(const float *__restrict__ Prows,
+                                                             int64_t n, int d, int kp,
+                                                             float *__restrict__ cen,
+                                                             float *__restrict__ rad) {
+    __shared__ __align__(16) float rows[SCREEN_TILE * 64];
+    __shared__ float ctr[64];
+    const int64_t tile = blockIdx.x;
+    const int lane = threadIdx.x;
+    const int64_t row = tile * SCREEN_TILE + lane;
+    const bool real = row < n;
+    const int cnt = (int)__popcll(__ballot(real));
+    float *crow = cen + tile * kp;
+    if (cnt == 0) {  // padding only: never skipped
+        if (lane < kp) crow[lane] = lane == d ? 1.0e30f : 0.0f;
+        if (lane == 0) rad[tile] = INFINITY;
+        return;
+    }
+    for (int c = 0; c < kp; c += 4) {
+        const float4 v = real ? *(const float4 *)(Prows + row * kp + c) : float4{0.f, 0.f, 0.f, 0.f};
+        *(float4 *)(rows + lane * 64 + c) = v;
+    }
+    __syncthreads();
+    // centroid of the rows' x~ = -(row) / 2 (exact), rounded to FP32
+    double ct = 0.0;
+    if (lane < d) {
+        double sum = 0.0;
+        for (int r = 0; r < SCREEN_TILE; ++r) sum += -0.5 * (double)rows[r * 64 + lane];
+        const float h = (float)(sum / cnt);
+        ct = (double)h;
+        crow[lane] = -2.0f * h;  // exact scale
+    }
+    ctr[lane] = (float)ct;
+    const double nc = wave_sum_f64(ct * ct);
+    __syncthreads();
+    double r2 = 0.0;
+    if (real) {
+        for (int c = 0; c < d; ++c) {
+            const double t = -0.5 * (double)rows[lane * 64 + c] - (double)ctr[c];
+            r2 += t * t;
+        }
+    }
+    double mx = r2;
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const double o = __shfl_xor(mx, w);
+        mx = o > mx ? o : mx;
+    }
+    if (lane >= d && lane < kp) crow[lane] = (lane == d) ? (float)nc : 0.0f;
+    if (lane == 0) rad[tile] = (float)(sqrt(mx) * (1.0 + 1.0e-6)) * (1.0f + 1.0e-6f);
+}
+
+// Stable sort of labels < P <= 256 (a counting sort in one pass): tile t of
+// SORT_TILE consecutive items counts its labels into cnt[label * tiles + t];
+// the exclusive scan of cnt in that (label, tile) order gives every
+// (label, tile) its first output position; each tile then scatters its items
+// in index order.  perm[pos] = the item's index, sorted[pos] = its label.
+constexpr int SORT_TILE = 4096;
+
+int sort_tiles(int64_t n) { return (int)((n + SORT_TILE - 1) / SORT_TILE); }
+
+__global__ __launch_bounds__(64) void label_count_kernel(const uint32_t *__restrict__ lab,
+                                                         int64_t n, int P, int tiles,
+                                                         uint32_t *__restrict__ cnt) {
+    __shared__ uint32_t h[256];
+    const int lane = threadIdx.x;
+    for (int l = lane; l < 256; l += 64) h[l] = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
+    for (int i = lane; i < SORT_TILE; i += 64) {
+        const int64_t g = base + i;
+        if (g < n) atomicAdd(&h[lab[g]], 1u);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    for (int l = lane; l < P; l += 64) cnt[(int64_t)l * tiles + blockIdx.x] = h[l];
+}
+
+// Exclusive scan of cnt[len] in place, one workgroup of 1024 threads (each
+// sums a contiguous chunk, the chunk totals are scanned in LDS, then each
+// chunk is rewritten).
+__global__ __launch_bounds__(1024) void label_scan_kernel(uint32_t *__restrict__ cnt,
+                                                          int64_t len) {
+    __shared__ uint32_t part[1024];
+    const int t = threadIdx.x;
+    const int64_t per = (len + 1023) / 1024;
+    const int64_t b = t * per, e = b + per < len ? b + per : len;
+    uint32_t sum = 0;
+    for (int64_t i = b; i < e; ++i) sum += cnt[i];
+    part[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t v = t >= off ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - sum;
+    for (int64_t i = b; i < e; ++i) {
+        const uint32_t c = cnt[i];
+        cnt[i] = run;
+        run += c;
+    }
+}
+
+// One wave per tile: 64 items at a time in index order; lanes with equal
+// labels are found by ballots over the label's bits, ranked by lane, and
+// placed after the label's running position (kept in LDS).
+__global__ __launch_bounds__(64) void label_scatter_kernel(const uint32_t *__restrict__ lab,
+                                                           int64_t n, int P, int tiles,
+                                                           const uint32_t *__restrict__ start,
+                                                           uint32_t *__restrict__ sorted,
+                                                           uint32_t *__restrict__ perm) {
+    __shared__ uint32_t off[256];
+    const int lane = threadIdx.x;
+    for (int l = lane; l < P; l += 64) off[l] = start[(int64_t)l * tiles + blockIdx.x];
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
+    for (int r = 0; r < SORT_TILE; r += 64) {
+        if (base + r >= n) break;
+        const int64_t g = base + r + lane;
+        const bool valid = g < n;
+        const uint32_t l = valid ? lab[g] : 256u;  // 256: no item (9 label bits)
+        uint64_t peers = ~0ull;
+#pragma unroll
+        for (int b = 0; b < 9; ++b) {
+            const uint64_t m = __ballot((l >> b) & 1u);
+            peers &= ((l >> b) & 1u) ? m : ~m;
+        }
+        const int leader = __ffsll((long long)peers) - 1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        uint32_t first = 0u;
+        if (valid && lane == leader) {
+            first = off[l];
+            off[l] = first + (uint32_t)__popcll(peers);
+        }
+        first = (uint32_t)__shfl((int)first, leader);
+        if (valid) {
+            const uint32_t pos = first + (uint32_t)__popcll(peers & lt);
+            sorted[pos] = l;
+            perm[pos] = (uint32_t)g;
+        }
+    }
+}
+
+hipError_t launch_label_sort(const uint32_t *lab, int64_t n, int P, void *tmp, size_t tmp_bytes,
+                             uint32_t *sorted, uint32_t *perm, hipStream_t s) {
+    const int tiles = sort_tiles(n);
+    if (P < 1 || P > 256 || tmp_bytes < (size_t)P * tiles * 4) return hipErrorInvalidValue;
+    uint32_t *cnt = (uint32_t *)tmp;
+    hipLaunchKernelGGL(label_count_kernel, dim3(tiles), dim3(64), 0, s, lab, n, P, tiles, cnt);
+    hipLaunchKernelGGL(label_scan_kernel, dim3(1), dim3(1024), 0, s, cnt, (int64_t)P * tiles);
+    hipLaunchKernelGGL(label_scatter_kernel, dim3(tiles), dim3(64), 0, s, lab, n, P, tiles, cnt,
+                       sorted, perm);
+    return hipGetLastError();
+}
+
 // cell[j] = first position of pivot j in the sorted assignment (j <= P).
 __global__ __launch_bounds__(256) void cell_start_kernel(const uint32_t *__restrict__ asg_sorted,
                                                          int64_t n, int P,
@@ -275,17 +439,9 @@ int prune_pivots(int64_t n) {
     return (int)(p < 1 ? 1 : (p > 256 ? 256 : p));
 }
 
-static int pivot_bits(int64_t n) {
-    int bits = 1;
-    while ((1 << bits) < prune_pivots(n)) ++bits;
-    return bits;
-}
-
 hipError_t prune_sort_bytes(int64_t n, size_t *bytes) {
-    *bytes = 0;
-    return hipcub::DeviceRadixSort::SortPairs(nullptr, *bytes, (const uint32_t *)nullptr,
-                                              (uint32_t *)nullptr, (const uint32_t *)nullptr,
-                                              (uint32_t *)nullptr, (int)n, 0, pivot_bits(n));
+    *bytes = (size_t)prune_pivots(n) * sort_tiles(n) * 4;
+    return hipSuccess;
 }
 
 hipError_t launch_prune_order(const float *X, int64_t n, int d, const float *mu, void *sort_tmp,
@@ -299,15 +455,15 @@ hipError_t launch_prune_order(const float *X, int64_t n, int d, const float *mu,
     launch_assign(X, X, n, d, mu, P, stride, label, asg, idx, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return hipcub::DeviceRadixSort::SortPairs(sort_tmp, sort_bytes, asg, asg_sorted, idx, perm,
-                                              (int)n, 0, pivot_bits(n), s);
+    (void)idx;
+    return launch_label_sort(asg, n, P, sort_tmp, sort_bytes, asg_sorted, perm, s);
 }
 
 hipError_t launch_prune_rows(const ScreenGeom &g, const void *Qrows, const void *Prows,
                              const double *nz, const uint32_t *perm, int64_t n, int64_t n_pad,
                              int d, void *Qout, void *Pout, float *nzq, void *tile_c,
                              float *tile_r, hipStream_t s) {
-    if (g.mode != SCREEN_BF16 || g.row_bytes % 16 != 0) return hipErrorInvalidValue;
+    if (g.row_bytes % 16 != 0) return hipErrorInvalidValue;
     const int chunks = g.row_bytes / 16;
     const int64_t items = n_pad * chunks;
     hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s,
@@ -315,9 +471,15 @@ hipError_t launch_prune_rows(const ScreenGeom &g, const void *Qrows, const void 
                        (uint4 *)Qout, (uint4 *)Pout, nzq);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (g.kp != 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(tile_bounds_kernel, dim3((unsigned)(n_pad / SCREEN_TILE)), dim3(64), 0, s,
-                       (const uint16_t *)Pout, n, d, (uint16_t *)tile_c, tile_r);
+    if (g.mode == SCREEN_BF16) {
+        if (g.kp != 64) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(tile_bounds_kernel, dim3((unsigned)(n_pad / SCREEN_TILE)), dim3(64), 0,
+                           s, (const uint16_t *)Pout, n, d, (uint16_t *)tile_c, tile_r);
+    } else {
+        if (g.kp > 64 || g.kp % 16 != 0 || d >= g.kp) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(tile_bounds_f32_kernel, dim3((unsigned)(n_pad / SCREEN_TILE)), dim3(64),
+                           0, s, (const float *)Pout, n, d, g.kp, (float *)tile_c, tile_r);
+    }
     return hipGetLastError();
 }
 
@@ -335,14 +497,14 @@ hipError_t launch_prune_queries(const float *X, int64_t n, const float *Z, int64
                                 uint32_t *qperm, const ScreenGeom &g, const void *Zq,
                                 const double *nzz, int64_t m_pad, void *Zq_out, float *nzq,
                                 const int32_t *cell, int32_t *rot, hipStream_t s) {
-    if (d > 64 || g.mode != SCREEN_BF16 || g.row_bytes % 16 != 0) return hipErrorInvalidValue;
+    if (d > 64 || g.row_bytes % 16 != 0) return hipErrorInvalidValue;
     const int P = prune_pivots(n);
     const int64_t stride = n / P;
     launch_assign(X, Z, m, d, mu, P, stride, label, asg, idx, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = hipcub::DeviceRadixSort::SortPairs(sort_tmp, sort_bytes, asg, asg_sorted, idx, qperm,
-                                           (int)m, 0, pivot_bits(n), s);
+    (void)idx;
+    e = launch_label_sort(asg, m, P, sort_tmp, sort_bytes, asg_sorted, qperm, s);
     if (e != hipSuccess) return e;
     const int chunks = g.row_bytes / 16;
     const int64_t items = m_pad * chunks;
@@ -356,10 +518,8 @@ hipError_t launch_prune_queries(const float *X, int64_t n, const float *Z, int64
 }
 
 hipError_t prune_query_sort_bytes(int64_t n, int64_t m, size_t *bytes) {
-    *bytes = 0;
-    return hipcub::DeviceRadixSort::SortPairs(nullptr, *bytes, (const uint32_t *)nullptr,
-                                              (uint32_t *)nullptr, (const uint32_t *)nullptr,
-                                              (uint32_t *)nullptr, (int)m, 0, pivot_bits(n));
+    *bytes = (size_t)prune_pivots(n) * sort_tiles(m) * 4;
+    return hipSuccess;
 }
 
 }  // namespace fmg

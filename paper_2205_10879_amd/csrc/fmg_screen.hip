@@ -524,6 +524,8 @@ hipError_t launch_screen(const ScreenGeom &g, const ScreenArgs &a, hipStream_t s
     if (a.c < 1 || a.c > SCREEN_CMAX) return hipErrorInvalidValue;
 #define FMG_SCREEN_LAUNCH(OP, KS) \
     hipLaunchKernelGGL((screen_kernel<OP, KS, SCREEN_CAP, false>), grid, dim3(256), 0, s, a)
+#define FMG_SCREEN_LAUNCH_PRUNED(OP, KS) \
+    hipLaunchKernelGGL((screen_kernel<OP, KS, SCREEN_CAP, true>), grid, dim3(256), 0, s, a)
     if (g.mode == SCREEN_BF16) {
         if (g.ksteps != 2) return hipErrorInvalidValue;
         if (a.prune) {
@@ -533,8 +535,16 @@ hipError_t launch_screen(const ScreenGeom &g, const ScreenArgs &a, hipStream_t s
         } else {
             FMG_SCREEN_LAUNCH(OpBF16, 2);
         }
+    } else if (a.prune) {
+        if (a.splits != 1 || !a.tile_c || !a.tile_r || !a.nzq) return hipErrorInvalidValue;
+        switch (g.ksteps) {
+        case 4: FMG_SCREEN_LAUNCH_PRUNED(OpF32, 4); break;
+        case 8: FMG_SCREEN_LAUNCH_PRUNED(OpF32, 8); break;
+        case 12: FMG_SCREEN_LAUNCH_PRUNED(OpF32, 12); break;
+        case 16: FMG_SCREEN_LAUNCH_PRUNED(OpF32, 16); break;
+        default: return hipErrorInvalidValue;
+        }
     } else {
-        if (a.prune) return hipErrorInvalidValue;
         switch (g.ksteps) {
         case 4: FMG_SCREEN_LAUNCH(OpF32, 4); break;
         case 8: FMG_SCREEN_LAUNCH(OpF32, 8); break;
@@ -544,6 +554,7 @@ hipError_t launch_screen(const ScreenGeom &g, const ScreenArgs &a, hipStream_t s
         }
     }
 #undef FMG_SCREEN_LAUNCH
+#undef FMG_SCREEN_LAUNCH_PRUNED
     return hipGetLastError();
 }
 
