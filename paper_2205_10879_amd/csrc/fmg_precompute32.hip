@@ -581,6 +581,7 @@ hipError_t launch_pc32_k(const PrecomputeArgs &a, hipStream_t s) {
     if (a.ell <= 1) return launch_pc32<64, 1, REFINE>(a, s);
     if (a.ell <= 4) return launch_pc32<64, 4, REFINE>(a, s);
     if (a.ell <= 8) return launch_pc32<64, 8, REFINE>(a, s);
+    if (a.ell <= 10) return launch_pc32<64, 10, REFINE>(a, s);
     if (a.ell <= 12) return launch_pc32<64, 12, REFINE>(a, s);
     return launch_pc32<64, 16, REFINE>(a, s);
 }
