@@ -297,6 +297,9 @@ typedef struct {
     int32_t slots;      /* batches in flight (one stream each), 1..8; 0 = 3 */
     int32_t max_batch;  /* queries per batch and per request, 1..65536; 0 = 16384 */
     int32_t use_graphs; /* replay captured HIP graphs per batch (1) or launch (0) */
+    int32_t swap_idle;  /* 1: a waiting model with queued requests is swapped in for idle
+                           resident models (no queued or running batch, resident at least
+                           50 ms), least recently used first; 0: it waits for removals */
 } fmg_server_opts;
 
 typedef struct {
@@ -308,6 +311,7 @@ typedef struct {
     uint64_t hbm_resident;  /* bytes: admitted models + slot workspaces */
     uint64_t hbm_peak;
     int32_t models_resident, models_waiting;
+    int64_t swaps;          /* models swapped in by the swap_idle policy */
 } fmg_server_stats;
 
 /* Create a server on the current device.  hbm_budget (bytes) bounds the
@@ -320,7 +324,9 @@ fmg_status fastmuygps_server_create(uint64_t hbm_budget, const fmg_server_opts *
 /* Register a built model (the caller keeps ownership and frees it after
  * removing it or destroying the server).  FMG_OK: admitted, resident.
  * FMG_E_BUSY: over budget now -- the model's arrays are moved to pinned host
- * memory and it is admitted (moved back) when a removal frees enough budget;
+ * memory and it is admitted (moved back) when a removal frees enough budget,
+ * or, with swap_idle, when requests for it arrive and idle resident models
+ * can make room (they move to host memory in turn and wait);
  * *id is valid and requests may be submitted meanwhile (they wait).
  * FMG_E_OOM: the model alone exceeds the budget.  FMG_E_INVALID_ARG: null
  * arguments, a model built with FMG_FLAG_TIMING, or d/ell beyond the slots. */

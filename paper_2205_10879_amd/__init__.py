@@ -78,7 +78,7 @@ class FmgTimings(ctypes.Structure):
 
 class FmgServerOpts(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("use_graphs", ctypes.c_int32)]
+                ("use_graphs", ctypes.c_int32), ("swap_idle", ctypes.c_int32)]
 
 
 class FmgServerStats(ctypes.Structure):
@@ -88,7 +88,7 @@ class FmgServerStats(ctypes.Structure):
                 ("max_ms", ctypes.c_double), ("wall_s", ctypes.c_double),
                 ("queries_per_s", ctypes.c_double), ("hbm_resident", ctypes.c_uint64),
                 ("hbm_peak", ctypes.c_uint64), ("models_resident", ctypes.c_int32),
-                ("models_waiting", ctypes.c_int32)]
+                ("models_waiting", ctypes.c_int32), ("swaps", ctypes.c_int64)]
 
 
 class FmgError(RuntimeError):
@@ -464,8 +464,9 @@ class Server:
     (host numpy query arrays) over several in-flight slots."""
 
     def __init__(self, hbm_budget: int = 0, slots: int = 3, max_batch: int = 16384,
-                 use_graphs: bool = True):
-        opts = FmgServerOpts(int(slots), int(max_batch), 1 if use_graphs else 0)
+                 use_graphs: bool = True, swap_idle: bool = False):
+        opts = FmgServerOpts(int(slots), int(max_batch), 1 if use_graphs else 0,
+                             1 if swap_idle else 0)
         h = ctypes.c_void_p()
         _check(lib().fastmuygps_server_create(int(hbm_budget), ctypes.byref(opts),
                                              ctypes.byref(h)))

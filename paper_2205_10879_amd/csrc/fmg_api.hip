@@ -555,12 +555,12 @@ fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_
     return FMG_OK;
 }
 
-fmg_status model_offload(fmg_model *M) {
+fmg_status model_offload(fmg_model *M, bool idle) {
     if (!M->resident) return FMG_OK;
-    HIPCHK(hipDeviceSynchronize(), "sync");
+    if (!idle) HIPCHK(hipDeviceSynchronize(), "sync");
     for (int a = 0; a < MA_COUNT; ++a) {
         void **p = model_array(M, a);
-        if (!*p) continue;
+        if (!*p || M->host[a]) continue;  // host copies kept from an earlier offload
         void *h = nullptr;
         HIPCHK(hipHostMalloc(&h, M->arr_bytes[a], hipHostMallocDefault), "pinned host memory");
         M->host[a] = h;
@@ -569,7 +569,10 @@ fmg_status model_offload(fmg_model *M) {
     for (int a = 0; a < MA_COUNT; ++a) {
         void **p = model_array(M, a);
         if (!*p) continue;
-        HIPCHK(hipFree(*p), "hipFree");
+        if (idle)
+            array_release(M->device, *p, M->arr_bytes[a]);
+        else
+            HIPCHK(hipFree(*p), "hipFree");
         *p = nullptr;
         M->bytes -= M->arr_bytes[a];
     }
@@ -577,7 +580,7 @@ fmg_status model_offload(fmg_model *M) {
     return FMG_OK;
 }
 
-fmg_status model_restore(fmg_model *M) {
+fmg_status model_restore(fmg_model *M, bool keep_host) {
     if (M->resident) return FMG_OK;
     for (int a = 0; a < MA_COUNT; ++a) {
         if (!M->host[a]) continue;
@@ -598,10 +601,11 @@ fmg_status model_restore(fmg_model *M) {
         M->bytes += M->arr_bytes[a];
         HIPCHK(hipMemcpy(*p, M->host[a], M->arr_bytes[a], hipMemcpyHostToDevice), "restore copy");
     }
-    for (int a = 0; a < MA_COUNT; ++a) {
-        if (M->host[a]) (void)hipHostFree(M->host[a]);
-        M->host[a] = nullptr;
-    }
+    if (!keep_host)
+        for (int a = 0; a < MA_COUNT; ++a) {
+            if (M->host[a]) (void)hipHostFree(M->host[a]);
+            M->host[a] = nullptr;
+        }
     M->resident = true;
     return FMG_OK;
 }

@@ -128,8 +128,13 @@ void predict_ws_free(PredictWs *ws);
 fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_t *nn_out,
                        hipStream_t s, const PredictWs *ws);
 // Move the model's arrays to pinned host memory and free their device memory
-// (synchronous), or bring them back.
-fmg_status model_offload(fmg_model *M);
-fmg_status model_restore(fmg_model *M);
+// (synchronous), or bring them back.  The arrays never change after the
+// build, so host copies kept from an earlier offload are reused without a
+// copy.  idle: no work on the device still reads the model, so neither a
+// device-wide synchronisation nor a synchronising free is needed (its device
+// arrays go to the library's array cache).  keep_host: keep the host copies
+// for later offloads.
+fmg_status model_offload(fmg_model *M, bool idle = false);
+fmg_status model_restore(fmg_model *M, bool keep_host = false);
 
 }  // namespace fmg

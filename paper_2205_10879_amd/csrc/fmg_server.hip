@@ -12,7 +12,9 @@
 // Batches of different slots overlap on the device.  With graphs enabled
 // the enqueued sequence of a batch is captured once per (model, slot,
 // batch-size bucket) and replayed; the queries past the batch in a bucket
-// repeat its last query and their results are dropped.
+// repeat its last query and their results are dropped.  Models that do not
+// fit the budget wait in pinned host memory; with swap_idle, a waiting model
+// with requests is swapped in for idle resident ones.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -69,6 +71,9 @@ struct ServerModel {
     uint64_t footprint = 0;
     bool admitted = false;
     bool removed = false;
+    bool loading = false;      // being swapped in (budget reserved, not yet admitted)
+    int64_t last_use = 0;      // ns: last dispatch (least recently used is swapped out first)
+    int64_t admitted_at = 0;   // ns
     int running = 0;  // slots holding a batch of this model
     std::deque<fmg_request *> queue;
     size_t esz = 4;
@@ -114,7 +119,7 @@ struct fmg_server {
     std::thread dispatcher, completer;
     // statistics
     std::vector<double> lat;
-    int64_t n_req = 0, n_q = 0, n_batch = 0;
+    int64_t n_req = 0, n_q = 0, n_batch = 0, n_swaps = 0;
     int64_t t_first = 0, t_last = 0;
 
     void note_resident() { peak = std::max(peak, resident); }
@@ -122,7 +127,91 @@ struct fmg_server {
     void complete_loop();
     fmg_status launch(Slot &sl, ServerModel &sm, int64_t m);
     void admit_waiting();
+    bool swap_in(std::unique_lock<std::mutex> &l);
 };
+
+// A resident model is swapped out only after it has been resident this long
+// (a quantum against thrashing when every model has a stream of requests).
+constexpr int64_t SWAP_MIN_RESIDENT_NS = 50'000'000;
+
+// Swap policy (opts.swap_idle): the first waiting model with queued requests
+// is brought in, swapping out idle resident models (no queued or running
+// batch), least recently used first, until it fits the budget.  The budget
+// accounting changes under the lock; the copies run without it (the
+// completer keeps finishing other slots' batches), in the dispatcher thread.
+// The swapped-out models join the waiting list and come back the same way
+// when requests for them arrive.  Returns whether a swap was made.
+bool fmg_server::swap_in(std::unique_lock<std::mutex> &l) {
+    int w = -1;
+    for (int32_t id : waiting) {
+        const ServerModel &sm = models[id];
+        if (!sm.removed && !sm.loading && !sm.queue.empty()) {
+            w = id;
+            break;
+        }
+    }
+    if (w < 0) return false;
+    const int64_t t = now_ns();
+    const uint64_t need = models[w].footprint;
+    std::vector<int32_t> idle;
+    for (int32_t id = 0; id < (int32_t)models.size(); ++id) {
+        const ServerModel &sm = models[id];
+        if (sm.admitted && !sm.removed && sm.queue.empty() && sm.running == 0 &&
+            t - sm.admitted_at >= SWAP_MIN_RESIDENT_NS)
+            idle.push_back(id);
+    }
+    std::sort(idle.begin(), idle.end(),
+              [&](int32_t x, int32_t y) { return models[x].last_use < models[y].last_use; });
+    uint64_t res = resident;
+    std::vector<int32_t> out;
+    for (int32_t id : idle) {
+        if (res + need <= budget) break;
+        out.push_back(id);
+        res -= models[id].footprint;
+    }
+    if (res + need > budget) return false;
+    // Their graphs hold the device addresses of the arrays that are about to
+    // move: drop them (none is in flight: the models are idle, and only this
+    // thread launches or captures graphs).
+    for (int32_t id : out) {
+        ServerModel &sm = models[id];
+        sm.admitted = false;
+        resident -= sm.footprint;
+        waiting.push_back(id);
+        for (Slot &sl : slots)
+            for (auto it = sl.graphs.begin(); it != sl.graphs.end();) {
+                if (it->first.first == id) {
+                    (void)hipGraphExecDestroy(it->second);
+                    it = sl.graphs.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+    }
+    ServerModel &in = models[w];
+    in.loading = true;
+    resident += need;
+    waiting.erase(std::find(waiting.begin(), waiting.end(), w));
+    l.unlock();
+    fmg_status st = FMG_OK;
+    for (int32_t id : out) {
+        fmg_status so = model_offload(models[id].M, true);
+        if (so != FMG_OK) st = so;
+    }
+    if (st == FMG_OK) st = model_restore(in.M, true);
+    l.lock();
+    in.loading = false;
+    if (st != FMG_OK) {  // stays waiting; the swapped-out models wait as well
+        resident -= need;
+        waiting.push_front(w);
+        return false;
+    }
+    in.admitted = true;
+    in.admitted_at = now_ns();
+    n_swaps += 1;
+    note_resident();
+    return true;
+}
 
 fmg_status fmg_server::launch(Slot &sl, ServerModel &sm, int64_t m) {
     fmg_model *M = sm.M;
@@ -197,13 +286,18 @@ void fmg_server::dispatch_loop() {
                 }
             }
         }
+        if (free_slot >= 0 && opts.swap_idle && !waiting.empty() && swap_in(l)) continue;
         if (pick < 0) {
             if (stop) break;
-            cv_work.wait(l);
+            if (opts.swap_idle && !waiting.empty())
+                cv_work.wait_for(l, std::chrono::milliseconds(5));  // models may turn idle
+            else
+                cv_work.wait(l);
             continue;
         }
         rr = (pick + 1) % (int)models.size();
         ServerModel &sm = models[pick];
+        sm.last_use = now_ns();
         Slot &sl = slots[free_slot];
         sl.busy = true;
         sl.model = pick;
@@ -301,8 +395,9 @@ void fmg_server::admit_waiting() {
             continue;
         }
         if (resident + sm.footprint > budget) break;
-        if (model_restore(sm.M) != FMG_OK) break;
+        if (model_restore(sm.M, opts.swap_idle != 0) != FMG_OK) break;
         sm.admitted = true;
+        sm.admitted_at = now_ns();
         resident += sm.footprint;
         note_resident();
         waiting.pop_front();
@@ -316,7 +411,7 @@ fmg_status fastmuygps_server_create(uint64_t hbm_budget, const fmg_server_opts *
                                     fmg_server **out) {
     if (!out) return set_error(FMG_E_INVALID_ARG, "out is null");
     *out = nullptr;
-    fmg_server_opts o{3, 16384, 1};
+    fmg_server_opts o{3, 16384, 1, 0};
     if (opts) {
         o = *opts;
         if (o.slots == 0) o.slots = 3;
@@ -390,6 +485,7 @@ fmg_status fastmuygps_server_add_model(fmg_server *S, fmg_model *M, int32_t *id)
     *id = (int32_t)S->models.size();
     if (S->waiting.empty() && S->resident + sm.footprint <= S->budget) {
         sm.admitted = true;
+        sm.admitted_at = now_ns();
         S->resident += sm.footprint;
         S->note_resident();
         S->models.push_back(sm);
@@ -409,7 +505,7 @@ fmg_status fastmuygps_server_remove_model(fmg_server *S, int32_t id) {
         return set_error(FMG_E_INVALID_ARG, "unknown model id %d", id);
     {
         ServerModel &sm = S->models[id];
-        if (!sm.admitted) {
+        if (!sm.admitted && !S->opts.swap_idle) {
             // never admitted: fail its queued requests
             const int64_t t = now_ns();
             for (fmg_request *r : sm.queue) finish(r, FMG_E_BUSY, t);
@@ -418,7 +514,7 @@ fmg_status fastmuygps_server_remove_model(fmg_server *S, int32_t id) {
     }
     S->cv_idle.wait(l, [&] {
         const ServerModel &sm = S->models[id];
-        return sm.queue.empty() && sm.running == 0;
+        return sm.queue.empty() && sm.running == 0 && !sm.loading;
     });
     ServerModel &sm = S->models[id];
     sm.removed = true;
@@ -499,6 +595,7 @@ fmg_status fastmuygps_server_stats(fmg_server *S, fmg_server_stats *st) {
     st->queries_per_s = st->wall_s > 0.0 ? (double)S->n_q / st->wall_s : 0.0;
     st->hbm_resident = S->resident;
     st->hbm_peak = S->peak;
+    st->swaps = S->n_swaps;
     for (const ServerModel &sm : S->models) {
         if (sm.removed) continue;
         if (sm.admitted) st->models_resident += 1;
@@ -511,7 +608,7 @@ fmg_status fastmuygps_server_reset_stats(fmg_server *S) {
     if (!S) return set_error(FMG_E_INVALID_ARG, "server is null");
     std::lock_guard<std::mutex> l(S->mu);
     S->lat.clear();
-    S->n_req = S->n_q = S->n_batch = 0;
+    S->n_req = S->n_q = S->n_batch = S->n_swaps = 0;
     S->t_first = S->t_last = 0;
     return FMG_OK;
 }
@@ -521,15 +618,17 @@ void fastmuygps_server_destroy(fmg_server *S) {
     {
         std::unique_lock<std::mutex> l(S->mu);
         const int64_t t = now_ns();
-        for (ServerModel &sm : S->models) {
-            if (sm.admitted) continue;
-            for (fmg_request *r : sm.queue) finish(r, FMG_E_BUSY, t);
-            sm.queue.clear();
-        }
-        // admitted models: let the loop finish their queues
+        if (!S->opts.swap_idle)
+            for (ServerModel &sm : S->models) {
+                if (sm.admitted) continue;
+                for (fmg_request *r : sm.queue) finish(r, FMG_E_BUSY, t);
+                sm.queue.clear();
+            }
+        // admitted models (and, when swapping, waiting ones): let the loop
+        // finish their queues
         S->cv_idle.wait(l, [&] {
             for (const ServerModel &sm : S->models)
-                if (!sm.queue.empty() || sm.running > 0) return false;
+                if (!sm.queue.empty() || sm.running > 0 || sm.loading) return false;
             return true;
         });
         S->stop = true;

@@ -167,3 +167,49 @@ def test_destroy_fails_requests_of_models_never_admitted():
     assert ref.shape == (len(Z2), 2)
     m1.free()
     m2.free()
+
+
+@pytest.mark.parametrize("use_graphs", [True, False])
+def test_swapping_idle_models_serves_every_stream(use_graphs):
+    # Three models, a budget for two: with swap_idle, requests for the model
+    # that waits in host memory bring it in for an idle one (least recently
+    # used), and every result still equals direct prediction.
+    f = fmg()
+    ma, Xa, Ya, Za = build("mixed", 9000, 1500, 12, 3, 30, seed=51)
+    mb, Xb, Yb, Zb = build("fp32", 8000, 1500, 8, 2, 25, seed=52)
+    mc, Xc, Yc, Zc = build("fp64", 3000, 1200, 2, 1, 20, seed=53)
+    models = {"a": ma, "b": mb, "c": mc}
+    Zs = {"a": Za, "b": Zb, "c": Zc}
+    refs = {key: direct(m, Zs[key]) for key, m in models.items()}
+    fps = sorted(m.info()["device_bytes"] for m in models.values())
+    with f.Server(slots=2, max_batch=1024) as probe:
+        ws = probe.stats()["hbm_resident"]
+    budget = ws + fps[2] + fps[1] + fps[0] // 2  # any two fit, not all three
+    with f.Server(hbm_budget=budget, slots=2, max_batch=1024, use_graphs=use_graphs,
+                  swap_idle=True) as srv:
+        ids = {key: srv.add_model(m) for key, m in models.items()}
+        assert sum(adm for _, adm in ids.values()) == 2
+        results = {key: [] for key in models}
+        # rounds of requests, each round to one model at a time, so that the
+        # others turn idle and can be swapped out
+        rs = np.random.default_rng(7)
+        for rnd in range(6):
+            for key in ("c", "a", "b") if rnd % 2 else ("a", "b", "c"):
+                Z = Zs[key]
+                lo = int(rs.integers(0, len(Z) - 300))
+                hi = lo + int(rs.integers(1, 300))
+                ts = [srv.submit(ids[key][0], Z[lo:hi]), srv.submit(ids[key][0], Z[:17])]
+                outs = [t.wait()[0] for t in ts]
+                results[key].append((lo, hi, outs))
+        st = srv.stats()
+    for key, lst in results.items():
+        for lo, hi, (o1, o2) in lst:
+            assert np.array_equal(o1, refs[key][lo:hi]), key
+            assert np.array_equal(o2, refs[key][:17]), key
+    assert st["swaps"] >= 2
+    assert st["hbm_peak"] <= budget
+    assert st["requests"] == 36
+    # every model is back on the device for its owner
+    for key, m in models.items():
+        assert np.array_equal(direct(m, Zs[key]), refs[key])
+        m.free()
