@@ -44,8 +44,16 @@ def main():
     ap.add_argument("--cpu-queries", type=int, default=8192, help="oracle sample: queries")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=8.0,
-                    help="length of each served (Poisson stream) run; 0 skips serving")
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="length of the served (Poisson stream) run of the mixed-precision "
+                         "model; 0 skips serving")
+    ap.add_argument("--serve-seconds-fp32", type=float, default=8.0,
+                    help="length of the plain FP32 served run (it falls behind the offered "
+                         "load, so its backlog grows with the length)")
+    ap.add_argument("--cfg5-seconds", type=float, default=10.0,
+                    help="length of each multi-model served run (9 models); 0 skips it")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the cfg-1 and cfg-2 build and predict lines")
     ap.add_argument("--serve-qps", type=float, default=2.0e6, help="offered queries per second")
     ap.add_argument("--no-muygps", action="store_true",
                     help="skip the MuyGPs prediction beside FastMuyGPs")
@@ -176,6 +184,8 @@ def main():
                    "kernel": "rbf", "length_scale": w.rho, "noise_var": w.noise,
                    "precision": "mixed", "step": "build(all n) + predict(all m)"},
         "build_ms": round(avg("build_total_ms"), 3),
+        "builds_per_s": round(1000.0 / avg("build_total_ms"), 3),
+        "training_points_per_s": round(args.n / (avg("build_total_ms") / 1000.0), 1),
         "predict_ms": round(avg("predict_total_ms"), 3),
         "predict_only_predictions_per_s": round(args.m / (avg("predict_total_ms") / 1000.0), 1),
         "phases_ms": {k: round(avg(k), 3) for k in timings[0]},
@@ -218,26 +228,39 @@ def main():
 
     # The borehole emulator (Section 4.2): k = 150 in FP64, its single-query
     # latency and an MCMC calibration driven by its predictions.
+    bh_sample = None
     if not args.no_borehole:
-        borehole_run(fmg, np, torch, synth, stream, result)
+        bh_sample = borehole_run(fmg, np, torch, synth, stream, result)
+
+    # Build and predict lines of the cfg-1 (FP64) and cfg-2 (FP32) workloads.
+    cfg_sample = None
+    if not args.no_configs:
+        cfg_sample = configs_run(fmg, np, torch, synth, result)
 
     if args.serve_seconds > 0:
         result["served"] = {}
-        for prec in ("mixed", "fp32"):
+        for prec, secs in (("mixed", args.serve_seconds), ("fp32", args.serve_seconds_fp32)):
             log("served run (%s): Poisson stream, %.0f queries/s offered, %.1f s" % (
-                prec, args.serve_qps, args.serve_seconds))
+                prec, args.serve_qps, secs))
             model = fmg.fastmuygps_build(X, Y, w.k, w.kernel, w.nu, w.rho, w.noise,
                                          precision=prec, stream=stream)
-            result["served"][prec] = serve_run(fmg, synth, np, model, args.serve_qps,
-                                               args.serve_seconds)
+            result["served"][prec] = serve_run(fmg, synth, np, torch, model, args.serve_qps,
+                                               secs)
             model.free()
             log("served %s: %s" % (prec, result["served"][prec]))
         result["p99_ms_served_mixed"] = result["served"]["mixed"]["p99_ms"]
         result["p99_ms_served_fp32"] = result["served"]["fp32"]["p99_ms"]
 
+    # Several resident models admitted by HBM budget (multi-model serving).
+    cfg5_sample = None
+    if args.cfg5_seconds > 0:
+        result["served_cfg5"], cfg5_sample = cfg5_run(fmg, np, torch, synth, args.cfg5_seconds,
+                                                      args.serve_qps)
+
     if not args.no_cpu_baseline:
         cpu_baseline_run(np, synth, w, args, result, N_mixed, nn_mixed, mu_mixed,
                          mu32 if not args.no_fp32 else None)
+        oracle_samples(np, result, bh_sample, cfg_sample, cfg5_sample)
 
     print(json.dumps(result), flush=True)
 
@@ -314,6 +337,48 @@ def cpu_baseline_run(np, synth, w, args, result, N_gpu, nn_gpu, mu_gpu, mu32):
         chk["rmse_ratio_fp32"] = rmse_ratio(mu32[qs])
     result["oracle_check"] = chk
     log("oracle check: %s" % chk)
+
+
+def oracle_samples(np, result, bh_sample, cfg_sample, cfg5_sample):
+    """The FP64 oracle on seeded samples of the other workloads' outputs:
+    neighbour lists and nearest points bit for bit, means by the relative
+    error max |dmu| / max(|mu_o|, RMS(mu_o))."""
+    import oracle
+    threads = oracle.max_threads()
+
+    def rel_err(got, ref):
+        rms = max(float(np.sqrt(np.mean(ref * ref))), 1e-300)
+        return float(np.max(np.abs(got.astype(np.float64) - ref) / np.maximum(np.abs(ref), rms)))
+
+    def check(w, qs_means, nn_gpu, Zq, rows=None, N_gpu=None):
+        X64, Y64 = w.X.astype(np.float64), w.Y.astype(np.float64)
+        out = {"queries": int(len(Zq))}
+        if rows is not None:
+            N_o, _, _ = oracle.build_model(X64, Y64, w.k, w.kernel, w.nu, w.rho, w.noise,
+                                           rows=rows, nthreads=threads)
+            out["rows"] = int(len(rows))
+            out["neighbor_list_mismatches"] = int(np.count_nonzero(np.any(N_gpu != N_o, axis=1)))
+        mu_o, nn_o, _ = oracle.predict(X64, Y64, Zq.astype(np.float64), w.k, w.kernel, w.nu,
+                                       w.rho, w.noise, nthreads=threads)
+        out["nearest_mismatches"] = int(np.count_nonzero(nn_gpu != nn_o))
+        out["mean_rel_err"] = rel_err(qs_means, mu_o)
+        return out
+
+    c0 = time.perf_counter()
+    if bh_sample is not None:
+        w, qs, mu, nn = bh_sample
+        result["borehole"]["oracle_check"] = check(w, mu, nn, w.Z[qs])
+        log("borehole oracle check: %s" % result["borehole"]["oracle_check"])
+    if cfg_sample is not None:
+        for w, rows, N_g, qs, mu, nn in cfg_sample:
+            result["configs"][w.name]["oracle_check"] = check(w, mu, nn, w.Z[qs], rows, N_g)
+            log("%s oracle check: %s" % (w.name, result["configs"][w.name]["oracle_check"]))
+    if cfg5_sample is not None:
+        for j, (w, qs, mu, nn) in enumerate(cfg5_sample):
+            result["served_cfg5"]["models"][j]["oracle_check"] = check(w, mu, nn, w.Z[qs])
+        log("cfg5 oracle checks: %s" % [m["oracle_check"] for m in
+                                        result["served_cfg5"]["models"]])
+    result["oracle_samples_seconds"] = round(time.perf_counter() - c0, 1)
 
 
 def muygps_run(fmg, np, torch, w, X, Y, Z, out, stream, args, result):
@@ -393,6 +458,10 @@ def borehole_run(fmg, np, torch, synth, stream, result, chains=4096, steps=300, 
         lat.append((time.perf_counter() - c0) * 1e3)
     lat = np.sort(np.array(lat[10:]))
     mc = borehole_mcmc(fmg, np, torch, synth, w, model, chains, steps, burn)
+    qs = np.sort(synth.rng(6, 4).choice(w.Z.shape[0], 64, replace=False))
+    nn = torch.empty(len(qs), dtype=torch.int32, device="cuda")
+    mu_s = model.predict(Z[torch.from_numpy(qs).cuda()], nn_out=nn, stream=stream)
+    sample = (w, qs, mu_s.cpu().numpy(), nn.cpu().numpy())
     model.free()
     result["borehole"] = {
         "workload": w.name, "n": int(w.X.shape[0]), "m": int(w.Z.shape[0]), "k": w.k,
@@ -404,6 +473,7 @@ def borehole_run(fmg, np, torch, synth, stream, result, chains=4096, steps=300, 
         "rmse": rm, "single_query_p50_ms": round(float(np.percentile(lat, 50)), 4),
         "single_query_p99_ms": round(float(np.percentile(lat, 99)), 4), "mcmc": mc}
     log("borehole: %s" % result["borehole"])
+    return sample
 
 
 def borehole_mcmc(fmg, np, torch, synth, w, model, chains, steps, burn, step_sd=0.01,
@@ -474,17 +544,83 @@ def screen_traffic(n):
         return None
 
 
-def serve_run(fmg, synth, np, model, qps, seconds, bmax=4096):
-    """Open-loop served run: requests arrive as a Poisson stream with batch
-    sizes log-uniform in [1, bmax] (mean offered load `qps` queries/s); latency
-    runs from each request's scheduled arrival to its results in host memory."""
+def mean_batch(bmax):
+    """E[floor(exp(U ln(bmax + 1)))], the mean of the log-uniform batch sizes."""
+    return (bmax + 1) / math.log(bmax + 1) - 1.0
+
+
+def drive(srv, ids, pools, events, keep=6):
+    """Submit `events` [(time_s, model index, B)] open loop, each at its
+    scheduled time (latency runs from that time, so a server that falls
+    behind is charged for it); a waiter thread collects every request's
+    latency per model and keeps the first `keep` results of each model (with
+    their pool offsets) for a check against direct prediction."""
     import queue
     import threading
-    mean_b = (bmax + 1) / math.log(bmax + 1) - 1.0  # E[floor(exp(U ln(bmax+1)))] ~
-    rate = qps / mean_b
-    t_arr, B = synth.poisson_stream(rate, seconds, bmax)
+    tickets = queue.Queue()
+    lat = [[] for _ in ids]
+    kept = [[] for _ in ids]
+
+    def waiter():
+        while True:
+            item = tickets.get()
+            if item is None:
+                return
+            j, o, b, t = item
+            out, ms = t.wait()
+            lat[j].append(ms)
+            if len(kept[j]) < keep:
+                kept[j].append((o, b, out.copy()))
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    offs = [0] * len(ids)
+    t0 = time.monotonic_ns() + 20_000_000
+    for ta, j, b in events:
+        due = t0 + int(ta * 1e9)
+        while True:
+            now = time.monotonic_ns()
+            if now >= due:
+                break
+            if due - now > 200_000:
+                time.sleep((due - now - 100_000) * 1e-9)
+        pool = pools[j]
+        o = offs[j] % (len(pool) - b + 1)
+        offs[j] += b
+        tickets.put((j, o, b, srv.submit(ids[j], pool[o:o + b], arrival_ns=due)))
+    tickets.put(None)
+    th.join()
+    return lat, kept
+
+
+def served_equals_direct(torch, models, pools, kept):
+    """Kept served results against fastmuygps_predict of the same queries:
+    the number of requests compared and of those bit-identical."""
+    n = same = 0
+    for j, lst in enumerate(kept):
+        for o, b, out in lst:
+            ref = models[j].predict(torch.from_numpy(pools[j][o:o + b]).cuda()).cpu().numpy()
+            n += 1
+            same += int(ref.shape == out.shape and (ref == out).all())
+    return n, same
+
+
+def pct(v, p):
+    """Nearest-rank percentile."""
+    v = sorted(v)
+    if not v:
+        return None
+    r = max(1, int(math.ceil(p / 100.0 * len(v))))
+    return v[r - 1]
+
+
+def serve_run(fmg, synth, np, torch, model, qps, seconds, bmax=4096):
+    """One resident model (the cfg-3 model) under an open-loop Poisson stream
+    of requests with batch sizes log-uniform in [1, bmax] (mean offered load
+    `qps` queries/s); latency runs from each request's scheduled arrival to
+    its results in host memory."""
+    t_arr, B = synth.poisson_stream(qps / mean_batch(bmax), seconds, bmax)
     pool = synth.cfg3_queries(1 << 20)
-    offs = np.concatenate([[0], np.cumsum(B)[:-1]]) % (len(pool) - bmax)
     srv = fmg.Server(slots=3, max_batch=16384)
     mid, _ = srv.add_model(model)
     # warm-up: one request per batch-size bucket the stream can form
@@ -492,39 +628,153 @@ def serve_run(fmg, synth, np, model, qps, seconds, bmax=4096):
         for _ in range(3):
             srv.submit(mid, pool[:b]).wait()
     srv.reset_stats()
-    tickets = queue.Queue()
-    lat = []
-
-    def waiter():
-        while True:
-            t = tickets.get()
-            if t is None:
-                return
-            lat.append(t.wait()[1])
-
-    th = threading.Thread(target=waiter)
-    th.start()
-    t0 = time.monotonic_ns() + 20_000_000
-    for i in range(len(t_arr)):
-        due = t0 + int(t_arr[i] * 1e9)
-        while True:
-            now = time.monotonic_ns()
-            if now >= due:
-                break
-            if due - now > 200_000:
-                time.sleep((due - now - 100_000) * 1e-9)
-        o = int(offs[i])
-        tickets.put(srv.submit(mid, pool[o:o + int(B[i])], arrival_ns=due))
-    tickets.put(None)
-    th.join()
+    events = [(float(t), 0, int(b)) for t, b in zip(t_arr, B)]
+    _, kept = drive(srv, [mid], [pool], events)
     st = srv.stats()
     srv.close()
-    return {"requests": int(st["requests"]), "queries": int(st["queries"]),
+    n, same = served_equals_direct(torch, [model], [pool], kept)
+    return {"seconds": seconds, "requests": int(st["requests"]), "queries": int(st["queries"]),
             "batches": int(st["batches"]), "offered_qps": qps,
             "predictions_per_s": round(st["queries_per_s"], 1),
             "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
             "mean_ms": round(st["mean_ms"], 3), "max_ms": round(st["max_ms"], 3),
-            "hbm_peak_bytes": int(st["hbm_peak"])}
+            "hbm_peak_bytes": int(st["hbm_peak"]),
+            "served_checked_against_direct": n, "served_bit_identical": same}
+
+
+def cfg5_run(fmg, np, torch, synth, seconds, qps, bmax=8192):
+    """Several resident models admitted by HBM budget: model A (n = 5M, d = 3,
+    Matern 1/2, FP32) and eight models of the cfg-1/2/3 kinds (synth.cfg5_models),
+    each with its own Poisson stream (batch sizes log-uniform in [1, 8192],
+    the total offered load split equally), interleaved.  Two runs: (i) the
+    whole device, (ii) a budget of the slot workspaces plus 60 % of the sum of
+    the model footprints, where the server swaps idle models out to host
+    memory for models with waiting requests.  Returns the block and, for the
+    oracle leg, a seeded sample of every model's direct predictions."""
+    ws = synth.cfg5_models()
+    models, build_ms = [], []
+    for w in ws:
+        dt = torch.float64 if w.precision == "fp64" else torch.float32
+        X = torch.from_numpy(w.X).to("cuda", dt)
+        Y = torch.from_numpy(w.Y).to("cuda", dt)
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        models.append(fmg.fastmuygps_build(X, Y, w.k, w.kernel, w.nu, w.rho, w.noise,
+                                           precision=w.precision))
+        torch.cuda.synchronize()
+        build_ms.append((time.perf_counter() - c0) * 1e3)
+        del X, Y
+        log("cfg5 model %s built in %.1f ms" % (w.name, build_ms[-1]))
+    fps = [int(m.info()["device_bytes"]) for m in models]
+    pools = [np.ascontiguousarray(w.Z) for w in ws]
+    rate = qps / len(ws) / mean_batch(bmax)
+    events = []
+    for j in range(len(ws)):
+        t_arr, B = synth.poisson_stream(rate, seconds, bmax, cfg=60 + j)
+        events += [(float(t), j, int(b)) for t, b in zip(t_arr, B)]
+    events.sort()
+    with fmg.Server(slots=3, max_batch=bmax) as probe:
+        wsb = int(probe.stats()["hbm_resident"])
+    block = {"offered_qps": qps, "seconds": seconds, "batch_max": bmax,
+             "slot_workspace_bytes": wsb, "sum_footprints_bytes": sum(fps),
+             "models": [{"name": w.name, "n": int(w.X.shape[0]), "d": int(w.X.shape[1]),
+                         "k": w.k, "ell": int(w.Y.shape[1]), "precision": w.precision,
+                         "kernel": w.kernel, "nu": w.nu, "build_ms": round(b, 2),
+                         "footprint_bytes": f,
+                         "rmse": float(np.sqrt(np.mean((models[j].predict(
+                             torch.from_numpy(pools[j]).cuda()).cpu().numpy() - w.Yz) ** 2)))}
+                        for j, (w, b, f) in enumerate(zip(ws, build_ms, fps))],
+             "builds_per_s": round(len(ws) / (sum(build_ms) / 1e3), 3)}
+    for label, budget, swap in (("whole_device", 0, False),
+                                ("budget_60pct", wsb + int(0.6 * sum(fps)), True)):
+        log("cfg5 served run (%s): 9 models, %.0f queries/s offered, %.1f s" % (
+            label, qps, seconds))
+        srv = fmg.Server(hbm_budget=budget, slots=3, max_batch=bmax, swap_idle=swap)
+        ids = [srv.add_model(m)[0] for m in models]
+        for j in range(len(ws)):
+            for b in (1, 300, 1000, 4000, bmax):
+                srv.submit(ids[j], pools[j][:b]).wait()
+        srv.reset_stats()
+        lat, kept = drive(srv, ids, pools, events)
+        st = srv.stats()
+        srv.close()
+        n, same = served_equals_direct(torch, models, pools, kept)
+        run = {"hbm_budget_bytes": budget if budget else None, "swap_idle": swap,
+               "requests": int(st["requests"]), "queries": int(st["queries"]),
+               "batches": int(st["batches"]),
+               "predictions_per_s": round(st["queries_per_s"], 1),
+               "p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+               "hbm_peak_bytes": int(st["hbm_peak"]), "swaps": int(st["swaps"]),
+               "per_model": [{"name": w.name, "requests": len(lat[j]),
+                              "p50_ms": round(pct(lat[j], 50), 3) if lat[j] else None,
+                              "p99_ms": round(pct(lat[j], 99), 3) if lat[j] else None}
+                             for j, w in enumerate(ws)],
+               "served_checked_against_direct": n, "served_bit_identical": same}
+        block[label] = run
+        log("cfg5 %s: %s" % (label, {k: v for k, v in run.items() if k != "per_model"}))
+    # seeded sample of each model's direct predictions for the oracle leg
+    sample = []
+    rs = synth.rng(5, 4)
+    for j, w in enumerate(ws):
+        q = np.sort(rs.choice(len(pools[j]), 24, replace=False))
+        nn = torch.empty(len(q), dtype=torch.int32, device="cuda")
+        mu = models[j].predict(torch.from_numpy(pools[j][q]).cuda(), nn_out=nn)
+        sample.append((w, q, mu.cpu().numpy(), nn.cpu().numpy()))
+        models[j].free()
+    return block, sample
+
+
+def configs_run(fmg, np, torch, synth, result):
+    """Build and predict rates of the full-size cfg-1 (FP64) and cfg-2 (FP32)
+    workloads with the bound of their dominant kernel.  Returns a seeded
+    sample of their outputs for the oracle leg."""
+    out, sample = {}, []
+    for w, peak, unit in ((synth.cfg1(), 78.6, "FP64 TFLOP/s"),
+                          (synth.cfg2(), PEAK_FP32_MFMA_TFLOPS, "FP32 MFMA TFLOP/s")):
+        dt = torch.float64 if w.precision == "fp64" else torch.float32
+        X = torch.from_numpy(w.X).to("cuda", dt)
+        Y = torch.from_numpy(w.Y).to("cuda", dt)
+        Z = torch.from_numpy(w.Z).to("cuda", dt)
+        ts = []
+        for rep in range(3):
+            m = fmg.fastmuygps_build(X, Y, w.k, w.kernel, w.nu, w.rho, w.noise,
+                                     precision=w.precision, flags=fmg.FLAG_TIMING)
+            nn = torch.empty(Z.shape[0], dtype=torch.int32, device="cuda")
+            mu = m.predict(Z, nn_out=nn)
+            ts.append(m.timings())
+            if rep < 2:
+                m.free()
+        t = ts[-1]
+        n, d, mq = w.X.shape[0], w.X.shape[1], w.Z.shape[0]
+        # dominant kernel: the build's neighbour search over n^2 pairs; its
+        # algorithmic work is 3d FP64 operations per pair (exact FP64 search)
+        # or 2d flops per pair (FP32 MFMA screen)
+        per_pair = 3 * d if w.precision == "fp64" else 2 * d
+        search_ms = t["build_screen_ms"]
+        achieved = per_pair * float(n) * n / (search_ms / 1e3) / 1e12
+        rmse = float(np.sqrt(np.mean((mu.cpu().numpy() - w.Yz) ** 2)))
+        out[w.name] = {
+            "n_train": int(n), "n_test": int(mq), "d": int(d), "k": w.k,
+            "precision": w.precision, "build_ms": round(t["build_total_ms"], 3),
+            "predict_ms": round(t["predict_total_ms"], 3),
+            "builds_per_s": round(1e3 / t["build_total_ms"], 3),
+            "training_points_per_s": round(n / (t["build_total_ms"] / 1e3), 1),
+            "predictions_per_s": round(mq / (t["predict_total_ms"] / 1e3), 1),
+            "phases_ms": {k: round(v, 3) for k, v in t.items()},
+            "search_roofline": {"achieved": round(achieved, 2), "peak": peak, "unit": unit,
+                                "frac": round(achieved / peak, 4),
+                                "algorithmic_ops_per_launch": per_pair * float(n) * n},
+            "rmse": rmse}
+        rs = synth.rng(7, 4)
+        rows = np.sort(rs.choice(n, 256, replace=False))
+        qs = np.sort(rs.choice(mq, min(1024, mq), replace=False))
+        sample.append((w, rows, m.neighbors().cpu().numpy()[rows], qs, mu.cpu().numpy()[qs],
+                       nn.cpu().numpy()[qs]))
+        m.free()
+        del X, Y, Z
+        log("%s: %s" % (w.name, {k: v for k, v in out[w.name].items() if k != "phases_ms"}))
+    result["configs"] = out
+    return sample
 
 
 if __name__ == "__main__":

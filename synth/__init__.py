@@ -19,7 +19,9 @@ shapes):
   cfg 3: 40-D ten-cluster Gaussian mixture with a one-hot +-0.5 multi-response,
          RBF, mixed precision (stands in for the star/galaxy classifier,
          Section 4.3).
-  cfg 5a: 3-D uniform inputs with a random-Fourier response, Matern nu=1/2.
+  cfg 5a: 3-D uniform inputs with a random-Fourier response, Matern nu=1/2;
+         with eight models of the kinds above (cfg5_models) it forms the
+         multi-model serving workload.
   cfg 6: the borehole flow-rate function (Section 4.2) on Latin-hypercube
          inputs, anisotropically scaled, RBF with k = 150, FP64.
 """
@@ -68,11 +70,12 @@ def _fourier_eval(X, w, a, b):
     return np.cos(X.astype(np.float64) @ w.T + b) @ a
 
 
-def cfg1(n: int = 10_000, m: int = 1_000) -> Workload:
+def cfg1(n: int = 10_000, m: int = 1_000, cfg: int = 1) -> Workload:
     """n points uniform on [0,1]^2, y = sin(2 pi x1) cos(2 pi x2) + N(0, 0.01^2);
-    k=30, Matern nu=3/2, rho=0.1, sigma^2=1e-4, FP64."""
+    k=30, Matern nu=3/2, rho=0.1, sigma^2=1e-4, FP64.  `cfg` selects the seed
+    stream (other values draw further models of the same kind)."""
     def draw(role, cnt):
-        rs = rng(1, role)
+        rs = rng(cfg, role)
         X = rs.uniform(0.0, 1.0, size=(cnt, 2))
         y = np.sin(2 * np.pi * X[:, 0]) * np.cos(2 * np.pi * X[:, 1])
         y = y + rs.normal(0.0, 0.01, size=cnt)
@@ -82,14 +85,14 @@ def cfg1(n: int = 10_000, m: int = 1_000) -> Workload:
     return Workload("cfg1-spatial2d", X, Y, Z, Yz, 30, "matern", 1.5, 0.1, 1e-4, "fp64")
 
 
-def cfg2(n: int = 100_000, m: int = 100_000) -> Workload:
+def cfg2(n: int = 100_000, m: int = 100_000, cfg: int = 2) -> Workload:
     """X ~ N(0, I_8), y = sum_{64} a cos(w.x + b) + N(0, 0.05^2) with
     w ~ N(0, I/0.5^2), a ~ N(0, 1/64), b ~ U[0, 2pi); k=50, Matern nu=5/2,
-    rho=1, sigma^2=1e-3, FP32."""
-    w, a, b = _fourier(rng(2, 0), 64, 8, 0.5)
+    rho=1, sigma^2=1e-3, FP32.  `cfg` selects the seed stream."""
+    w, a, b = _fourier(rng(cfg, 0), 64, 8, 0.5)
 
     def draw(role, cnt):
-        rs = rng(2, role)
+        rs = rng(cfg, role)
         X = rs.normal(0.0, 1.0, size=(cnt, 8)).astype(np.float32)
         y = _fourier_eval(X, w, a, b) + rs.normal(0.0, 0.05, size=cnt)
         return X, y.astype(np.float32)[:, None]
@@ -98,14 +101,16 @@ def cfg2(n: int = 100_000, m: int = 100_000) -> Workload:
     return Workload("cfg2-fourier8d", X, Y, Z, Yz, 50, "matern", 2.5, 1.0, 1e-3, "fp32")
 
 
-def cfg3(n: int = 1_000_000, m: int = 200_000, d: int = 40, classes: int = 10) -> Workload:
+def cfg3(n: int = 1_000_000, m: int = 200_000, d: int = 40, classes: int = 10,
+         cfg: int = 3) -> Workload:
     """Ten-cluster Gaussian mixture in 40-D: means ~ N(0, 4 I), unit covariance,
     labels uniform; responses are the one-hot label mapped 1 -> +0.5,
-    0 -> -0.5 (ell = 10).  k=50, RBF, rho=3, sigma^2=1e-2, mixed precision."""
-    means = rng(3, 0).normal(0.0, 2.0, size=(classes, d))
+    0 -> -0.5 (ell = 10).  k=50, RBF, rho=3, sigma^2=1e-2, mixed precision.
+    `cfg` selects the seed stream."""
+    means = rng(cfg, 0).normal(0.0, 2.0, size=(classes, d))
 
     def draw(role, cnt):
-        rs = rng(3, role)
+        rs = rng(cfg, role)
         lab = rs.integers(0, classes, size=cnt)
         X = means[lab] + rs.normal(0.0, 1.0, size=(cnt, d))
         Y = np.full((cnt, classes), -0.5, dtype=np.float32)
@@ -132,6 +137,38 @@ def cfg5a(n: int = 5_000_000, m: int = 100_000) -> Workload:
     X, Y = draw(1, n)
     Z, Yz = draw(2, m)
     return Workload("cfg5a-fourier3d", X, Y, Z, Yz, 30, "matern", 0.5, 0.2, 4e-4, "fp32")
+
+
+def cfg5_specs():
+    """The eight further models of the multi-model serving workload: n
+    log-uniform in [1e4, 2e6], d uniform on {2, 8, 40}, k uniform on {30, 50}
+    (drawn from seed stream 50).  Returns [(n, d, k)]."""
+    rs = rng(50, 0)
+    n = np.floor(np.exp(rs.uniform(math.log(1e4), math.log(2e6), size=8))).astype(np.int64)
+    d = rs.choice([2, 8, 40], size=8)
+    k = rs.choice([30, 50], size=8)
+    return [(int(n[i]), int(d[i]), int(k[i])) for i in range(8)]
+
+
+def cfg5_models(m: int = 65_536, n_a: int = 5_000_000):
+    """Model A (cfg5a: n = 5,000,000, d = 3, Matern nu=1/2, FP32) and the eight
+    models of cfg5_specs().  Each of those takes the generator, kernel,
+    precision and number of responses of the workload of its dimension: d=2
+    like cfg 1 (FP64, Matern 3/2, ell 1), d=8 like cfg 2 (FP32, Matern 5/2,
+    ell 1), d=40 like cfg 3 (mixed, RBF, ell 10), on seed stream 51 + i, with
+    its own n and k.  m queries per model (the serving pool)."""
+    out = [cfg5a(n=n_a, m=m)]
+    for i, (n, d, k) in enumerate(cfg5_specs()):
+        if d == 2:
+            w = cfg1(n=n, m=m, cfg=51 + i)
+        elif d == 8:
+            w = cfg2(n=n, m=m, cfg=51 + i)
+        else:
+            w = cfg3(n=n, m=m, cfg=51 + i)
+        w.k = k
+        w.name = "cfg5-%d-%s-n%d-k%d" % (i + 1, w.name.split("-")[1], n, k)
+        out.append(w)
+    return out
 
 
 # Borehole function (Section 4.2): parameter order, bounds, and the divisors
