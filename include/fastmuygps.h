@@ -374,6 +374,15 @@ const char *fastmuygps_last_error(void);
 /* Library version string, e.g. "fastmuygps-gfx950 0.1". */
 const char *fastmuygps_version(void);
 
+/* Diagnostic, for tests of the arithmetic: y[i] = exp(x[i]) for x[i] <= 0,
+ * evaluated on the device by the FP64 exponential that the MIXED
+ * refinement's residual uses for kernel values (additive range reduction
+ * x = n ln2 + r with ln2 in two parts (Cody and Waite), the Taylor series of
+ * exp(r) to degree 12, scaling by 2^n; it underflows to 0 below about -745).
+ * x and y are device pointers [n].  Asynchronous on `stream`.  Errors:
+ * FMG_E_INVALID_ARG (n < 0, null pointers), FMG_E_DEVICE. */
+fmg_status fastmuygps_debug_exp_nonpos(const double *x, double *y, int64_t n, void *stream);
+
 /* Return the device memory the library keeps cached on the current device
  * (the arrays of freed models and the freed scratch of earlier calls) to the
  * device.  Synchronises the device first; no call may be running on it.

@@ -586,7 +586,20 @@ hipError_t launch_pc32_k(const PrecomputeArgs &a, hipStream_t s) {
     return launch_pc32<64, 16, REFINE>(a, s);
 }
 
+__global__ __launch_bounds__(256) void exp_nonpos64_kernel(const double *__restrict__ x,
+                                                          double *__restrict__ y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) y[i] = exp_nonpos64(x[i]);
+}
+
 }  // namespace
+
+hipError_t launch_exp_nonpos64(const double *x, double *y, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(exp_nonpos64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       x, y, n);
+    return hipGetLastError();
+}
 
 hipError_t launch_precompute32(bool refine, const PrecomputeArgs &a, hipStream_t s) {
     if (a.n <= 0) return hipSuccess;
