@@ -240,6 +240,8 @@ def main():
     if args.serve_seconds > 0:
         result["served"] = {}
         for prec, secs in (("mixed", args.serve_seconds), ("fp32", args.serve_seconds_fp32)):
+            if secs <= 0:
+                continue
             log("served run (%s): Poisson stream, %.0f queries/s offered, %.1f s" % (
                 prec, args.serve_qps, secs))
             model = fmg.fastmuygps_build(X, Y, w.k, w.kernel, w.nu, w.rho, w.noise,
@@ -248,8 +250,8 @@ def main():
                                                secs)
             model.free()
             log("served %s: %s" % (prec, result["served"][prec]))
-        result["p99_ms_served_mixed"] = result["served"]["mixed"]["p99_ms"]
-        result["p99_ms_served_fp32"] = result["served"]["fp32"]["p99_ms"]
+        for prec in result["served"]:
+            result["p99_ms_served_" + prec] = result["served"][prec]["p99_ms"]
 
     # Several resident models admitted by HBM budget (multi-model serving).
     cfg5_sample = None
