@@ -249,6 +249,10 @@ void **model_array(fmg_model *M, int idx) {
     case MA_TC: return &M->tile_c;
     case MA_TR: return (void **)&M->tile_r;
     case MA_CELL: return (void **)&M->cell;
+    case MA_KEYS: return (void **)&M->keys;
+    case MA_BOX: return (void **)&M->box;
+    case MA_SC: return &M->sup_c;
+    case MA_SR: return (void **)&M->sup_r;
     default: return (void **)&M->mu;
     }
 }
@@ -458,30 +462,32 @@ fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_
         sa.cand = cand;
         sa.tq = tq;
         if (prune) {
-            uint32_t *asg = nullptr, *asg2 = nullptr, *idx = nullptr;
+            uint32_t *ka = nullptr, *kb = nullptr, *va = nullptr;
             void *sort_tmp = nullptr, *Zq2 = nullptr;
             float *nzq = nullptr;
             int32_t *rot = nullptr;
             size_t sort_bytes = 0;
             HIPCHK(prune_query_sort_bytes(M->n, m, &sort_bytes), "sort size");
             HIPCHK(tmp.alloc((void **)&qperm, (size_t)m * 4), "scratch");
-            HIPCHK(tmp.alloc((void **)&asg, (size_t)m * 4), "scratch");
-            HIPCHK(tmp.alloc((void **)&asg2, (size_t)m * 4), "scratch");
-            HIPCHK(tmp.alloc((void **)&idx, (size_t)m * 4), "scratch");
+            HIPCHK(tmp.alloc((void **)&ka, (size_t)m * 4), "scratch");
+            HIPCHK(tmp.alloc((void **)&kb, (size_t)m * 4), "scratch");
+            HIPCHK(tmp.alloc((void **)&va, (size_t)m * 4), "scratch");
             HIPCHK(tmp.alloc(&sort_tmp, sort_bytes), "scratch");
             HIPCHK(tmp.alloc(&Zq2, (size_t)m_pad * g.row_bytes), "scratch");
             HIPCHK(tmp.alloc((void **)&nzq, (size_t)m_pad * 4), "scratch");
             HIPCHK(tmp.alloc((void **)&rot, (size_t)(m_pad / SCREEN_QPB) * 4), "scratch");
             HIPCHK(launch_prune_queries((const float *)M->X, M->n, (const float *)Z, m, M->d, M->mu,
                                         sort_tmp, sort_bytes, M->cell + prune_pivots(M->n) + 1,
-                                        asg, asg2, idx, qperm, g, Zq, nzz,
-                                        m_pad, Zq2, nzq, M->cell, rot, s),
+                                        M->box, ka, kb, va, qperm, g, Zq, nzz, m_pad, Zq2, nzq,
+                                        M->keys, rot, s),
                    "query order");
             sa.Q = Zq2;
             sa.P = M->Xpp;
             sa.prune = 1;
             sa.tile_c = M->tile_c;
             sa.tile_r = M->tile_r;
+            sa.sup_c = M->sup_c;
+            sa.sup_r = M->sup_r;
             sa.nzq = nzq;
             sa.acc_coef = M->acc_coef;
             sa.nx_max = M->nx_max;
@@ -773,6 +779,7 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
     // Screening rows (FP32 and MIXED): the candidate side is kept by the
     // model for the queries' search, the query side serves the build.
     int64_t n_pad = 0;
+    bool prune = false;
     void *Xq = nullptr;
     double *ex = nullptr, *nzx = nullptr;
     if (kk == 0) {
@@ -797,7 +804,10 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
         HCHK(launch_exact_topk(true, ea, n, s), "exact search");
         for (int e = EV_SCREEN; e <= EV_FALLBACK; ++e) record(M, M->evb, e, s);
     } else {
-        n_pad = round_up(n, SCREEN_QPB);
+        // A pruned screen takes whole super-tiles of candidate rows.
+        prune = !(flags & FMG_FLAG_NO_PRUNE) && prune_pivots(n) > 1 && d <= 64 &&
+                round_up(n, SCREEN_SUPER_ROWS) / SCREEN_SUPER_ROWS <= SCREEN_SUPER_MAX;
+        n_pad = round_up(n, prune ? SCREEN_SUPER_ROWS : SCREEN_QPB);
         M->n_pad = n_pad;
         MCHK(model_alloc(M, MA_MU, (void **)&M->mu, (size_t)d * 4, "model mu"));
         if (flags & FMG_FLAG_NO_CENTER)
@@ -836,7 +846,15 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
         HCHK(launch_exact_topk(false, ea, n, s), "exact search");
         for (int e = EV_SCREEN; e <= EV_FALLBACK; ++e) record(M, M->evb, e, s);
     } else if (kk > 0 && !f64) {
-        M->c_build = prec == FMG_PREC_MIXED ? 2 * kk : kk + 8;
+        // Candidates per row: 2k for the BF16 screen; k + 8 for the FP32
+        // screen, or 2k (at most SCREEN_CMAX) in up to four dimensions, where
+        // many points cluster tightly and the screen's error bound is a
+        // large fraction of the k-th distance, so that k + 8 candidates would
+        // often leave rows uncertified (each such row is rescanned exactly).
+        M->c_build = prec == FMG_PREC_MIXED ? 2 * kk
+                     : d <= 4              ? (2 * kk < SCREEN_CMAX ? 2 * kk : SCREEN_CMAX)
+                                           : kk + 8;
+        if (M->c_build < kk + 8 && kk + 8 <= SCREEN_CMAX) M->c_build = kk + 8;
         const int c = M->c_build;
         uint64_t *pool = nullptr, *cand = nullptr;
         float *tq = nullptr;
@@ -865,10 +883,9 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
         // tiles whose bounding balls no query of a wavefront can reach; the
         // re-rank takes the rows in the same order and maps the candidates'
         // indices back.
-        const bool prune = !(flags & FMG_FLAG_NO_PRUNE) && prune_pivots(n) > 1 && d <= 64;
         uint32_t *perm = nullptr;
         if (prune) {
-            uint32_t *asg = nullptr, *asg2 = nullptr, *idx = nullptr;
+            uint32_t *ka = nullptr, *va = nullptr;
             void *sort_tmp = nullptr, *Xq2 = nullptr;
             float *nzq = nullptr;
             size_t sort_bytes = 0;
@@ -881,19 +898,23 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
             MCHK(model_alloc(M, MA_TR, (void **)&M->tile_r, tiles * 4, "model tiles"));
             MCHK(model_alloc(M, MA_CELL, (void **)&M->cell, (size_t)(2 * npiv + 1) * 4,
                              "model cells"));
+            MCHK(model_alloc(M, MA_KEYS, (void **)&M->keys, (size_t)n * 4, "model keys"));
+            MCHK(model_alloc(M, MA_BOX, (void **)&M->box, 128 * 4, "model box"));
+            const size_t nsup = (size_t)(n_pad / SCREEN_SUPER_ROWS);
+            MCHK(model_alloc(M, MA_SC, &M->sup_c, nsup * geom.row_bytes, "model super-tiles"));
+            MCHK(model_alloc(M, MA_SR, (void **)&M->sup_r, nsup * 4, "model super-tiles"));
             perm = M->perm;
-            HCHK(tmp.alloc((void **)&asg, (size_t)n * 4), "scratch");
-            HCHK(tmp.alloc((void **)&asg2, (size_t)n * 4), "scratch");
-            HCHK(tmp.alloc((void **)&idx, (size_t)n * 4), "scratch");
+            HCHK(tmp.alloc((void **)&ka, (size_t)n * 4), "scratch");
+            HCHK(tmp.alloc((void **)&va, (size_t)n * 4), "scratch");
             HCHK(tmp.alloc(&sort_tmp, sort_bytes), "scratch");
             HCHK(tmp.alloc(&Xq2, (size_t)n_pad * geom.row_bytes), "scratch");
             HCHK(tmp.alloc((void **)&nzq, (size_t)n_pad * 4), "scratch");
             HCHK(launch_prune_order((const float *)M->X, n, d, M->mu, sort_tmp, sort_bytes,
-                                    M->cell + npiv + 1, asg, asg2, idx, perm, s),
+                                    M->cell + npiv + 1, M->box, ka, M->keys, va, perm, s),
                  "pivot order");
-            HCHK(launch_cell_starts(asg2, n, npiv, M->cell, s), "cell starts");
+            HCHK(launch_cell_starts(M->keys, n, npiv, M->cell, s), "cell starts");
             HCHK(launch_prune_rows(geom, Xq, M->Xp, nzx, perm, n, n_pad, d, Xq2, M->Xpp, nzq,
-                                   M->tile_c, M->tile_r, s),
+                                   M->tile_c, M->tile_r, M->sup_c, M->sup_r, s),
                  "pruning rows");
             MCHK(read_maxima());
             sa.Q = Xq2;
@@ -901,6 +922,8 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
             sa.prune = 1;
             sa.tile_c = M->tile_c;
             sa.tile_r = M->tile_r;
+            sa.sup_c = M->sup_c;
+            sa.sup_r = M->sup_r;
             sa.nzq = nzq;
             sa.acc_coef = M->acc_coef;
             sa.nx_max = M->nx_max;

@@ -18,6 +18,12 @@ constexpr int SCREEN_QPB = 256;
 // and the largest number of candidates kept per query and split.
 constexpr int SCREEN_CAP = 512;
 constexpr int SCREEN_CMAX = 128;
+// Pruned screens group tiles into super-tiles of SCREEN_SUPER tiles (a
+// pruned model pads its candidate rows to whole super-tiles) and keep at
+// most SCREEN_SUPER_MAX of them (n <= 33.5M).
+constexpr int SCREEN_SUPER = 256;
+constexpr int SCREEN_SUPER_ROWS = SCREEN_SUPER * SCREEN_TILE;
+constexpr int SCREEN_SUPER_MAX = 2048;
 
 // Row layout of the screening arrays: `kp` elements per row (bf16 or f32),
 // row bytes = kp * elem.  bf16: kp = 64 (2 MFMA k-steps of 32); f32: kp a
@@ -49,6 +55,8 @@ struct ScreenArgs {
     int prune;
     const void *tile_c;  // [n_pad / SCREEN_TILE, kp]
     const float *tile_r; // [n_pad / SCREEN_TILE]
+    const void *sup_c;   // [n_pad / SCREEN_SUPER_ROWS, kp] super-tile centroid rows
+    const float *sup_r;  // [n_pad / SCREEN_SUPER_ROWS] super-tile radii
     const float *nzq;    // [m_pad] ||z~||^2 of the query rows
     double acc_coef, nx_max;
     // Optional start column of each workgroup (a multiple of SCREEN_TILE);
@@ -208,36 +216,42 @@ hipError_t launch_loo_grad(bool f64, const GradArgs &a, double *part, double *ou
                            hipStream_t s);
 
 // Tile pruning of the build screen (fmg_prune.hip): the order of the training
-// points by nearest pivot (perm), the screening rows and query norms gathered
-// into it with the per-tile centroid rows and radii (the re-rank then takes
-// the rows in the same order).
+// points by (nearest pivot, Morton code in low dimensions) (perm), the
+// screening rows and query norms gathered into it with the per-tile centroid
+// rows and radii (the re-rank then takes the rows in the same order).
 int prune_pivots(int64_t n);
 hipError_t prune_sort_bytes(int64_t n, size_t *bytes);
-// label [P]: pivot labels along a nearest-neighbour chain (written here,
-// reused for the queries of predictions).
+// label [P]: pivot labels along a nearest-neighbour chain; box [128]: the
+// centred bounding box of the Morton code; keys [n]: the sorted keys (all
+// three written here and kept by the model for predictions); ka, va [n]:
+// scratch; perm [n]: position -> training point.
 hipError_t launch_prune_order(const float *X, int64_t n, int d, const float *mu, void *sort_tmp,
-                              size_t sort_bytes, int32_t *label, uint32_t *asg,
-                              uint32_t *asg_sorted, uint32_t *idx, uint32_t *perm,
-                              hipStream_t s);
+                              size_t sort_bytes, int32_t *label, float *box, uint32_t *ka,
+                              uint32_t *keys, uint32_t *va, uint32_t *perm, hipStream_t s);
+// Also the super-tile balls: per SCREEN_SUPER tiles a centroid row (the mean
+// of the tiles' real centroids, in the row format) and a radius
+// max_t (||c_t - c|| + r_t) (FP64, rounded up); n_pad must be a multiple of
+// SCREEN_SUPER_ROWS.  Tiles and super-tiles with no real row get a negative
+// radius of -1e18, so every screen skips them.
 hipError_t launch_prune_rows(const ScreenGeom &g, const void *Qrows, const void *Prows,
                              const double *nz, const uint32_t *perm, int64_t n, int64_t n_pad,
                              int d, void *Qout, void *Pout, float *nzq, void *tile_c,
-                             float *tile_r, hipStream_t s);
-// cell[j], j <= P: first position of pivot j in the pivot order.
-hipError_t launch_cell_starts(const uint32_t *asg_sorted, int64_t n, int P, int32_t *cell,
+                             float *tile_r, void *sup_c, float *sup_r, hipStream_t s);
+// cell[j], j <= P: first position of pivot j in the sorted keys.
+hipError_t launch_cell_starts(const uint32_t *keys, int64_t n, int P, int32_t *cell,
                               hipStream_t s);
-// Queries of a prediction in pivot order: their nearest pivots (the model's),
-// the stable sort (qperm: position -> query), the query rows and norms
-// gathered into that order, and each workgroup's start column (the cell of
-// its first query's pivot).
+// Queries of a prediction in the same key order: their keys (the model's
+// pivots and box), the stable sort (qperm: position -> query; ka, kb, va:
+// scratch [m]), the query rows and norms gathered into that order, and each
+// workgroup's start column (where its first query's key falls among the
+// model's sorted training keys).
 hipError_t prune_query_sort_bytes(int64_t n, int64_t m, size_t *bytes);
 hipError_t launch_prune_queries(const float *X, int64_t n, const float *Z, int64_t m, int d,
                                 const float *mu, void *sort_tmp, size_t sort_bytes,
-                                const int32_t *label, uint32_t *asg, uint32_t *asg_sorted,
-                                uint32_t *idx,
-                                uint32_t *qperm, const ScreenGeom &g, const void *Zq,
-                                const double *nzz, int64_t m_pad, void *Zq_out, float *nzq,
-                                const int32_t *cell, int32_t *rot, hipStream_t s);
+                                const int32_t *label, const float *box, uint32_t *ka,
+                                uint32_t *kb, uint32_t *va, uint32_t *qperm, const ScreenGeom &g,
+                                const void *Zq, const double *nzz, int64_t m_pad, void *Zq_out,
+                                float *nzq, const uint32_t *keys, int32_t *rot, hipStream_t s);
 
 // y[i] = the FP64 exponential of x[i] <= 0 that the refinement's residual
 // evaluates kernel values with (fmg_precompute32.hip).

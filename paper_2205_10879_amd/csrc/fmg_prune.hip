@@ -27,13 +27,19 @@ namespace fmg {
 
 namespace {
 
-// Nearest pivot of points Pts [n, d]; pivot j is training row j * stride of X.
-// Coordinates are zero padded to DP (a multiple of 16 covering d), so the
-// loop has no guards and reads each pivot row as 16-byte vectors.  The
-// nearest pivot minimises ||p_j||^2 - 2 x.p_j (||x||^2 is common to all j):
-// one FMA per coordinate.  Any assignment serves the pruning (the tile radii
-// are measured on the tiles' actual rows), so the rounding of this form is
-// harmless.
+// Sort key of points Pts [n, d]: the label of the nearest pivot in the top
+// 8 bits and, for low-dimensional data, a Morton code of the centred
+// coordinates in the low 24 bits, so that the points of one cell are ordered
+// along a space-filling curve and 64 consecutive points form a compact tile.
+// Pivot j is training row j * stride of X.  Coordinates are zero padded to
+// DP (a multiple of 16 covering d), so the loop has no guards and reads each
+// pivot row as 16-byte vectors.  The nearest pivot minimises
+// ||p_j||^2 - 2 x.p_j (||x||^2 is common to all j): one FMA per coordinate.
+// Any assignment and any order serve the pruning (the tile radii are
+// measured on the tiles' actual rows), so the rounding of this form is
+// harmless.  box (nullable): per coordinate the low end and 2^bits / width
+// of the training points' centred bounding box; bits = Morton bits per
+// coordinate (bits * d <= 24).
 template <int DP>
 __global__ __launch_bounds__(256) void pivot_assign_kernel(const float *__restrict__ X,
                                                            const float *__restrict__ Pts,
@@ -41,8 +47,9 @@ __global__ __launch_bounds__(256) void pivot_assign_kernel(const float *__restri
                                                            const float *__restrict__ mu, int P,
                                                            int64_t stride,
                                                            const int32_t *__restrict__ label,
-                                                           uint32_t *__restrict__ asg,
-                                                           uint32_t *__restrict__ idx) {
+                                                           const float *__restrict__ box,
+                                                           int bits,
+                                                           uint32_t *__restrict__ key) {
     extern __shared__ __align__(16) float piv[];  // [P, DP] centred pivots, zero past d; [P] norms
     float *pn = piv + P * DP;
     for (int e = threadIdx.x; e < P * DP; e += blockDim.x) {
@@ -80,8 +87,22 @@ __global__ __launch_bounds__(256) void pivot_assign_kernel(const float *__restri
             bj = (uint32_t)j;
         }
     }
-    asg[i] = (uint32_t)label[bj];
-    idx[i] = (uint32_t)i;
+    uint32_t code = 0;
+    if (box && bits > 0) {
+        const uint32_t top = (1u << bits) - 1u;
+        uint32_t q[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            q[c] = 0u;
+            if (c < d) {
+                const float t = (x[c < DP ? c : 0] - box[c]) * box[64 + c];
+                q[c] = t <= 0.0f ? 0u : (t >= (float)top ? top : (uint32_t)t);
+            }
+        }
+        for (int b = bits - 1; b >= 0; --b)
+            for (int c = 0; c < d; ++c) code = (code << 1) | ((q[c] >> b) & 1u);
+    }
+    key[i] = ((uint32_t)label[bj] << 24) | code;
 }
 
 // Pivot labels along a greedy nearest-neighbour chain (pivot 0 first, then
@@ -139,22 +160,81 @@ __global__ __launch_bounds__(256) void pivot_chain_kernel(const float *__restric
 
 template <int DP>
 void launch_assign_t(const float *X, const float *Pts, int64_t n, int d, const float *mu, int P,
-                     int64_t stride, const int32_t *label, uint32_t *asg, uint32_t *idx,
-                     hipStream_t s) {
+                     int64_t stride, const int32_t *label, const float *box, int bits,
+                     uint32_t *key, hipStream_t s) {
     const size_t shm = (size_t)P * (DP + 1) * sizeof(float);
     (void)hipFuncSetAttribute((const void *)pivot_assign_kernel<DP>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     hipLaunchKernelGGL((pivot_assign_kernel<DP>), dim3((unsigned)((n + 255) / 256)), dim3(256), shm,
-                       s, X, Pts, n, d, mu, P, stride, label, asg, idx);
+                       s, X, Pts, n, d, mu, P, stride, label, box, bits, key);
 }
 
 void launch_assign(const float *X, const float *Pts, int64_t n, int d, const float *mu, int P,
-                   int64_t stride, const int32_t *label, uint32_t *asg, uint32_t *idx,
-                   hipStream_t s) {
-    if (d <= 16) launch_assign_t<16>(X, Pts, n, d, mu, P, stride, label, asg, idx, s);
-    else if (d <= 32) launch_assign_t<32>(X, Pts, n, d, mu, P, stride, label, asg, idx, s);
-    else if (d <= 48) launch_assign_t<48>(X, Pts, n, d, mu, P, stride, label, asg, idx, s);
-    else launch_assign_t<64>(X, Pts, n, d, mu, P, stride, label, asg, idx, s);
+                   int64_t stride, const int32_t *label, const float *box, int bits,
+                   uint32_t *key, hipStream_t s) {
+    if (d <= 16) launch_assign_t<16>(X, Pts, n, d, mu, P, stride, label, box, bits, key, s);
+    else if (d <= 32) launch_assign_t<32>(X, Pts, n, d, mu, P, stride, label, box, bits, key, s);
+    else if (d <= 48) launch_assign_t<48>(X, Pts, n, d, mu, P, stride, label, box, bits, key, s);
+    else launch_assign_t<64>(X, Pts, n, d, mu, P, stride, label, box, bits, key, s);
+}
+
+// Centred bounding box of the training points: per coordinate the minimum
+// and maximum of x - mu, kept as order-preserving unsigned bits (atomics).
+__device__ __forceinline__ uint32_t ord_bits(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float ord_float(uint32_t o) {
+    return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
+}
+
+__global__ __launch_bounds__(256) void box_init_kernel(uint32_t *__restrict__ ob, int d) {
+    const int c = threadIdx.x;
+    if (c < d) {
+        ob[c] = 0xffffffffu;  // min
+        ob[64 + c] = 0u;      // max
+    }
+}
+
+__global__ __launch_bounds__(256) void box_kernel(const float *__restrict__ X, int64_t n, int d,
+                                                  const float *__restrict__ mu,
+                                                  uint32_t *__restrict__ ob) {
+    const int lane = lane_id();
+    for (int c = 0; c < d; ++c) {
+        uint32_t lo = 0xffffffffu, hi = 0u;
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+             i += (int64_t)gridDim.x * blockDim.x) {
+            const uint32_t o = ord_bits(X[i * d + c] - mu[c]);
+            lo = o < lo ? o : lo;
+            hi = o > hi ? o : hi;
+        }
+#pragma unroll
+        for (int w = 32; w >= 1; w >>= 1) {
+            const uint32_t a = (uint32_t)__shfl_xor((int)lo, w), b = (uint32_t)__shfl_xor((int)hi, w);
+            lo = a < lo ? a : lo;
+            hi = b > hi ? b : hi;
+        }
+        if (lane == 0) {
+            atomicMin(&ob[c], lo);
+            atomicMax(&ob[64 + c], hi);
+        }
+    }
+}
+
+// box[c] = low end, box[64 + c] = 2^bits / width (0 for a constant coordinate).
+__global__ __launch_bounds__(64) void box_final_kernel(const uint32_t *__restrict__ ob, int d,
+                                                       int bits, float *__restrict__ box) {
+    const int c = threadIdx.x;
+    if (c < 64) {
+        float lo = 0.0f, sc = 0.0f;
+        if (c < d) {
+            lo = ord_float(ob[c]);
+            const float w = ord_float(ob[64 + c]) - lo;
+            sc = w > 0.0f ? (float)(1u << bits) / w : 0.0f;
+        }
+        box[c] = lo;
+        box[64 + c] = sc;
+    }
 }
 
 // Rows i < n come from point perm[i]; padding rows stay in place.
@@ -192,9 +272,9 @@ __global__ __launch_bounds__(64) void tile_bounds_kernel(const uint16_t *__restr
     const bool real = row < n;
     const int cnt = (int)__popcll(__ballot(real));
     uint16_t *crow = cen + tile * KP;
-    if (cnt == 0) {  // padding only: never skipped
+    if (cnt == 0) {  // padding only: no candidate, always skipped
         crow[lane] = lane == d ? f32_to_bf16_rn(1.0e30f) : (uint16_t)0;
-        if (lane == 0) rad[tile] = INFINITY;
+        if (lane == 0) rad[tile] = -1.0e18f;
         return;
     }
     {
@@ -256,9 +336,9 @@ __global__ __launch_bounds__(64) void tile_bounds_f32_kernel(const float *__rest
     const bool real = row < n;
     const int cnt = (int)__popcll(__ballot(real));
     float *crow = cen + tile * kp;
-    if (cnt == 0) {  // padding only: never skipped
+    if (cnt == 0) {  // padding only: no candidate, always skipped
         if (lane < kp) crow[lane] = lane == d ? 1.0e30f : 0.0f;
-        if (lane == 0) rad[tile] = INFINITY;
+        if (lane == 0) rad[tile] = -1.0e18f;
         return;
     }
     for (int c = 0; c < kp; c += 4) {
@@ -295,17 +375,104 @@ __global__ __launch_bounds__(64) void tile_bounds_f32_kernel(const float *__rest
     if (lane == 0) rad[tile] = (float)(sqrt(mx) * (1.0 + 1.0e-6)) * (1.0f + 1.0e-6f);
 }
 
-// Stable sort of labels < P <= 256 (a counting sort in one pass): tile t of
-// SORT_TILE consecutive items counts its labels into cnt[label * tiles + t];
-// the exclusive scan of cnt in that (label, tile) order gives every
-// (label, tile) its first output position; each tile then scatters its items
-// in index order.  perm[pos] = the item's index, sorted[pos] = its label.
+// One wave per super-tile of SCREEN_SUPER tiles: the centroid row of the
+// super-tile (the mean of its real tiles' centroids, rounded to the row
+// format: BF16 rows hold -2 c then three BF16 parts of ||c||^2, FP32 rows
+// -2 c then ||c||^2) and the radius max_t (||c_t - c|| + r_t) over its real
+// tiles (FP64, rounded up): by the triangle inequality every row of the
+// super-tile lies within it.  Coordinates are recovered exactly from the
+// rows' -2 x entries.
+template <bool BF16>
+__global__ __launch_bounds__(64) void super_bounds_kernel(const void *__restrict__ tile_c,
+                                                          const float *__restrict__ tile_r,
+                                                          int d, int kp,
+                                                          void *__restrict__ sup_c,
+                                                          float *__restrict__ sup_r) {
+    __shared__ double ctr[64];
+    const int lane = threadIdx.x;
+    const int64_t s0 = (int64_t)blockIdx.x * SCREEN_SUPER;
+    auto coord = [&](int64_t t, int c) -> double {
+        if (BF16) return -0.5 * (double)bf16_to_f32(((const uint16_t *)tile_c)[t * kp + c]);
+        return -0.5 * (double)((const float *)tile_c)[t * kp + c];
+    };
+    // real tiles: radius not negative
+    int cnt = 0;
+    double sum = 0.0;
+    for (int t = 0; t < SCREEN_SUPER; ++t) {
+        if (!(tile_r[s0 + t] >= 0.0f)) continue;
+        ++cnt;
+        if (lane < d) sum += coord(s0 + t, lane);
+    }
+    double ct = 0.0;
+    if (cnt > 0 && lane < d) {
+        if (BF16) {
+            const uint16_t h = f32_to_bf16_rn((float)(sum / cnt));
+            ct = (double)bf16_to_f32(h);
+        } else {
+            ct = (double)(float)(sum / cnt);
+        }
+    }
+    ctr[lane] = ct;
+    __syncthreads();
+    const double nc = wave_sum_f64(ct * ct);
+    // radius: lane handles tiles lane, lane + 64, ...
+    double mx = cnt > 0 ? 0.0 : -1.0e18;
+    for (int t = lane; t < SCREEN_SUPER; t += 64) {
+        const float r = tile_r[s0 + t];
+        if (!(r >= 0.0f)) continue;
+        double e2 = 0.0;
+        for (int c = 0; c < d; ++c) {
+            const double u = coord(s0 + t, c) - ctr[c];
+            e2 += u * u;
+        }
+        const double b = sqrt(e2) * (1.0 + 1.0e-12) + (double)r;
+        mx = b > mx ? b : mx;
+    }
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const double o = __shfl_xor(mx, w);
+        mx = o > mx ? o : mx;
+    }
+    if (lane == 0)
+        sup_r[blockIdx.x] = cnt > 0 ? (float)(mx * (1.0 + 1.0e-6)) * (1.0f + 1.0e-6f) : -1.0e18f;
+    if (BF16) {
+        uint16_t *row = (uint16_t *)sup_c + (int64_t)blockIdx.x * kp;
+        if (cnt == 0) {
+            row[lane] = lane == d ? f32_to_bf16_rn(1.0e30f) : (uint16_t)0;
+            return;
+        }
+        const uint16_t hi = f32_to_bf16_rn((float)nc);
+        const double q1 = nc - (double)bf16_to_f32(hi);
+        const uint16_t mid = f32_to_bf16_rn((float)q1);
+        const double q2 = q1 - (double)bf16_to_f32(mid);
+        const uint16_t lo = f32_to_bf16_rn((float)q2);
+        if (lane < d)
+            row[lane] = f32_to_bf16_rn(-2.0f * (float)ct);  // exact scale of a BF16 value
+        else
+            row[lane] = (lane == d) ? hi : (lane == d + 1) ? mid : (lane == d + 2) ? lo : (uint16_t)0;
+    } else {
+        float *row = (float *)sup_c + (int64_t)blockIdx.x * kp;
+        if (lane >= kp) return;
+        if (cnt == 0) {
+            row[lane] = lane == d ? 1.0e30f : 0.0f;
+            return;
+        }
+        row[lane] = lane < d ? -2.0f * (float)ct : (lane == d ? (float)nc : 0.0f);
+    }
+}
+
+// Stable LSD radix sort of 32-bit keys by 8-bit digits, one pass per
+// digit: tile t of SORT_TILE consecutive items counts its digits into
+// cnt[digit * tiles + t]; the exclusive scan of cnt in that (digit, tile)
+// order gives every (digit, tile) its first output position; each tile then
+// scatters its items in index order.  vals_out[pos] = the item's value
+// (vals_in[item], or the item's index when vals_in is null).
 constexpr int SORT_TILE = 4096;
 
 int sort_tiles(int64_t n) { return (int)((n + SORT_TILE - 1) / SORT_TILE); }
 
-__global__ __launch_bounds__(64) void label_count_kernel(const uint32_t *__restrict__ lab,
-                                                         int64_t n, int P, int tiles,
+__global__ __launch_bounds__(64) void digit_count_kernel(const uint32_t *__restrict__ key,
+                                                         int64_t n, int shift, int tiles,
                                                          uint32_t *__restrict__ cnt) {
     __shared__ uint32_t h[256];
     const int lane = threadIdx.x;
@@ -316,18 +483,18 @@ __global__ __launch_bounds__(64) void label_count_kernel(const uint32_t *__restr
     const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
     for (int i = lane; i < SORT_TILE; i += 64) {
         const int64_t g = base + i;
-        if (g < n) atomicAdd(&h[lab[g]], 1u);
+        if (g < n) atomicAdd(&h[(key[g] >> shift) & 255u], 1u);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    for (int l = lane; l < P; l += 64) cnt[(int64_t)l * tiles + blockIdx.x] = h[l];
+    for (int l = lane; l < 256; l += 64) cnt[(int64_t)l * tiles + blockIdx.x] = h[l];
 }
 
 // Exclusive scan of cnt[len] in place, one workgroup of 1024 threads (each
 // sums a contiguous chunk, the chunk totals are scanned in LDS, then each
 // chunk is rewritten).
-__global__ __launch_bounds__(1024) void label_scan_kernel(uint32_t *__restrict__ cnt,
+__global__ __launch_bounds__(1024) void digit_scan_kernel(uint32_t *__restrict__ cnt,
                                                           int64_t len) {
     __shared__ uint32_t part[1024];
     const int t = threadIdx.x;
@@ -352,23 +519,25 @@ __global__ __launch_bounds__(1024) void label_scan_kernel(uint32_t *__restrict__
 }
 
 // One wave per tile: 64 items at a time in index order; lanes with equal
-// labels are found by ballots over the label's bits, ranked by lane, and
-// placed after the label's running position (kept in LDS).
-__global__ __launch_bounds__(64) void label_scatter_kernel(const uint32_t *__restrict__ lab,
-                                                           int64_t n, int P, int tiles,
+// digits are found by ballots over the digit's bits, ranked by lane, and
+// placed after the digit's running position (kept in LDS).
+__global__ __launch_bounds__(64) void digit_scatter_kernel(const uint32_t *__restrict__ key_in,
+                                                           const uint32_t *__restrict__ val_in,
+                                                           int64_t n, int shift, int tiles,
                                                            const uint32_t *__restrict__ start,
-                                                           uint32_t *__restrict__ sorted,
-                                                           uint32_t *__restrict__ perm) {
+                                                           uint32_t *__restrict__ key_out,
+                                                           uint32_t *__restrict__ val_out) {
     __shared__ uint32_t off[256];
     const int lane = threadIdx.x;
-    for (int l = lane; l < P; l += 64) off[l] = start[(int64_t)l * tiles + blockIdx.x];
+    for (int l = lane; l < 256; l += 64) off[l] = start[(int64_t)l * tiles + blockIdx.x];
     const uint64_t lt = (1ull << lane) - 1ull;
     const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
     for (int r = 0; r < SORT_TILE; r += 64) {
         if (base + r >= n) break;
         const int64_t g = base + r + lane;
         const bool valid = g < n;
-        const uint32_t l = valid ? lab[g] : 256u;  // 256: no item (9 label bits)
+        const uint32_t k = valid ? key_in[g] : 0u;
+        const uint32_t l = valid ? ((k >> shift) & 255u) : 256u;  // 256: no item (9 bits)
         uint64_t peers = ~0ull;
 #pragma unroll
         for (int b = 0; b < 9; ++b) {
@@ -387,26 +556,45 @@ __global__ __launch_bounds__(64) void label_scatter_kernel(const uint32_t *__res
         first = (uint32_t)__shfl((int)first, leader);
         if (valid) {
             const uint32_t pos = first + (uint32_t)__popcll(peers & lt);
-            sorted[pos] = l;
-            perm[pos] = (uint32_t)g;
+            key_out[pos] = k;
+            val_out[pos] = val_in ? val_in[g] : (uint32_t)g;
         }
     }
 }
 
-hipError_t launch_label_sort(const uint32_t *lab, int64_t n, int P, void *tmp, size_t tmp_bytes,
-                             uint32_t *sorted, uint32_t *perm, hipStream_t s) {
+// Morton bits per coordinate for d-dimensional points (0: no Morton order;
+// high-dimensional cells have no finer structure worth ordering).
+int morton_bits(int d) { return d <= 8 ? 24 / d : 0; }
+
+// Radix passes over the key digits in use: the Morton bits (low 24), then
+// the pivot label (top 8).  The keys start in buffer `(npass + 1) % 2` of
+// {ka, kb} and end in kb, the values in perm.
+int sort_passes(int d) { return (morton_bits(d) * d + 7) / 8 + 1; }
+
+hipError_t launch_key_sort(int d, int64_t n, uint32_t *ka, uint32_t *kb, uint32_t *va,
+                           uint32_t *perm, void *tmp, size_t tmp_bytes, hipStream_t s) {
     const int tiles = sort_tiles(n);
-    if (P < 1 || P > 256 || tmp_bytes < (size_t)P * tiles * 4) return hipErrorInvalidValue;
+    if (tmp_bytes < (size_t)256 * tiles * 4) return hipErrorInvalidValue;
     uint32_t *cnt = (uint32_t *)tmp;
-    hipLaunchKernelGGL(label_count_kernel, dim3(tiles), dim3(64), 0, s, lab, n, P, tiles, cnt);
-    hipLaunchKernelGGL(label_scan_kernel, dim3(1), dim3(1024), 0, s, cnt, (int64_t)P * tiles);
-    hipLaunchKernelGGL(label_scatter_kernel, dim3(tiles), dim3(64), 0, s, lab, n, P, tiles, cnt,
-                       sorted, perm);
+    const int np = sort_passes(d);
+    const int low = np - 1;  // Morton digit passes (bits 0-7, 8-15, 16-23 as needed)
+    uint32_t *K[2] = {ka, kb}, *V[2] = {va, perm};
+    int cur = (np + 1) % 2;
+    for (int p = 0; p < np; ++p) {
+        const int shift = p < low ? 8 * p : 24;
+        hipLaunchKernelGGL(digit_count_kernel, dim3(tiles), dim3(64), 0, s, K[cur], n, shift, tiles,
+                           cnt);
+        hipLaunchKernelGGL(digit_scan_kernel, dim3(1), dim3(1024), 0, s, cnt, (int64_t)256 * tiles);
+        hipLaunchKernelGGL(digit_scatter_kernel, dim3(tiles), dim3(64), 0, s, K[cur],
+                           p == 0 ? (const uint32_t *)nullptr : V[cur], n, shift, tiles, cnt,
+                           K[cur ^ 1], V[cur ^ 1]);
+        cur ^= 1;
+    }
     return hipGetLastError();
 }
 
-// cell[j] = first position of pivot j in the sorted assignment (j <= P).
-__global__ __launch_bounds__(256) void cell_start_kernel(const uint32_t *__restrict__ asg_sorted,
+// cell[j] = first position of pivot j in the sorted keys (j <= P).
+__global__ __launch_bounds__(256) void cell_start_kernel(const uint32_t *__restrict__ keys,
                                                          int64_t n, int P,
                                                          int32_t *__restrict__ cell) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -414,22 +602,32 @@ __global__ __launch_bounds__(256) void cell_start_kernel(const uint32_t *__restr
     int64_t lo = 0, hi = n;
     while (lo < hi) {
         const int64_t mid = (lo + hi) / 2;
-        if (asg_sorted[mid] < (uint32_t)j) lo = mid + 1;
+        if ((keys[mid] >> 24) < (uint32_t)j) lo = mid + 1;
         else hi = mid;
     }
     cell[j] = (int32_t)lo;
 }
 
-// Start column of query block b: the cell of the block's first query's pivot,
-// rounded down to a tile.
-__global__ __launch_bounds__(256) void block_start_kernel(const uint32_t *__restrict__ qasg_sorted,
+// Start column of query block b: where the key of the block's first query
+// falls among the training points' sorted keys (its pivot cell and, in low
+// dimensions, its place on the cell's space-filling curve), rounded down to
+// a tile.
+__global__ __launch_bounds__(256) void block_start_kernel(const uint32_t *__restrict__ qkeys,
                                                           int64_t m, int64_t blocks,
-                                                          const int32_t *__restrict__ cell,
-                                                          int32_t *__restrict__ rot) {
+                                                          const uint32_t *__restrict__ keys,
+                                                          int64_t n, int32_t *__restrict__ rot) {
     const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= blocks) return;
     const int64_t q = b * SCREEN_QPB < m ? b * SCREEN_QPB : m - 1;
-    rot[b] = cell[qasg_sorted[q]] & ~(SCREEN_TILE - 1);
+    const uint32_t key = qkeys[q];
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if (keys[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    if (lo >= n) lo = n - 1;
+    rot[b] = (int32_t)(lo & ~(int64_t)(SCREEN_TILE - 1));
 }
 
 }  // namespace
@@ -440,30 +638,42 @@ int prune_pivots(int64_t n) {
 }
 
 hipError_t prune_sort_bytes(int64_t n, size_t *bytes) {
-    *bytes = (size_t)prune_pivots(n) * sort_tiles(n) * 4;
+    *bytes = (size_t)256 * sort_tiles(n) * 4 + 1024;
     return hipSuccess;
 }
 
 hipError_t launch_prune_order(const float *X, int64_t n, int d, const float *mu, void *sort_tmp,
-                              size_t sort_bytes, int32_t *label, uint32_t *asg,
-                              uint32_t *asg_sorted, uint32_t *idx, uint32_t *perm,
-                              hipStream_t s) {
+                              size_t sort_bytes, int32_t *label, float *box, uint32_t *ka,
+                              uint32_t *keys, uint32_t *va, uint32_t *perm, hipStream_t s) {
     const int P = prune_pivots(n);
     const int64_t stride = n / P;
-    if (d > 64 || P > 256) return hipErrorInvalidValue;
+    if (d > 64 || P > 256 || sort_bytes < (size_t)256 * sort_tiles(n) * 4 + 1024)
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(pivot_chain_kernel, dim3(1), dim3(256), 0, s, X, d, mu, P, stride, label);
-    launch_assign(X, X, n, d, mu, P, stride, label, asg, idx, s);
+    const int bits = morton_bits(d);
+    if (bits > 0) {
+        // the bounding box's order bits sit past the sort counters
+        uint32_t *ob = (uint32_t *)((char *)sort_tmp + (size_t)256 * sort_tiles(n) * 4);
+        const int64_t nb = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;
+        hipLaunchKernelGGL(box_init_kernel, dim3(1), dim3(256), 0, s, ob, d);
+        hipLaunchKernelGGL(box_kernel, dim3((unsigned)nb), dim3(256), 0, s, X, n, d, mu, ob);
+        hipLaunchKernelGGL(box_final_kernel, dim3(1), dim3(64), 0, s, ob, d, bits, box);
+    } else {
+        hipLaunchKernelGGL(box_final_kernel, dim3(1), dim3(64), 0, s, (const uint32_t *)nullptr, 0,
+                           0, box);
+    }
+    uint32_t *first = (sort_passes(d) + 1) % 2 == 0 ? ka : keys;
+    launch_assign(X, X, n, d, mu, P, stride, label, bits > 0 ? box : nullptr, bits, first, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    (void)idx;
-    return launch_label_sort(asg, n, P, sort_tmp, sort_bytes, asg_sorted, perm, s);
+    return launch_key_sort(d, n, ka, keys, va, perm, sort_tmp, sort_bytes, s);
 }
 
 hipError_t launch_prune_rows(const ScreenGeom &g, const void *Qrows, const void *Prows,
                              const double *nz, const uint32_t *perm, int64_t n, int64_t n_pad,
                              int d, void *Qout, void *Pout, float *nzq, void *tile_c,
-                             float *tile_r, hipStream_t s) {
-    if (g.row_bytes % 16 != 0) return hipErrorInvalidValue;
+                             float *tile_r, void *sup_c, float *sup_r, hipStream_t s) {
+    if (g.row_bytes % 16 != 0 || n_pad % SCREEN_SUPER_ROWS != 0) return hipErrorInvalidValue;
     const int chunks = g.row_bytes / 16;
     const int64_t items = n_pad * chunks;
     hipLaunchKernelGGL(gather_rows_kernel, dim3((unsigned)((items + 255) / 256)), dim3(256), 0, s,
@@ -480,31 +690,38 @@ hipError_t launch_prune_rows(const ScreenGeom &g, const void *Qrows, const void 
         hipLaunchKernelGGL(tile_bounds_f32_kernel, dim3((unsigned)(n_pad / SCREEN_TILE)), dim3(64),
                            0, s, (const float *)Pout, n, d, g.kp, (float *)tile_c, tile_r);
     }
+    const unsigned nsup = (unsigned)(n_pad / SCREEN_SUPER_ROWS);
+    if (g.mode == SCREEN_BF16)
+        hipLaunchKernelGGL(super_bounds_kernel<true>, dim3(nsup), dim3(64), 0, s,
+                           (const void *)tile_c, (const float *)tile_r, d, g.kp, sup_c, sup_r);
+    else
+        hipLaunchKernelGGL(super_bounds_kernel<false>, dim3(nsup), dim3(64), 0, s,
+                           (const void *)tile_c, (const float *)tile_r, d, g.kp, sup_c, sup_r);
     return hipGetLastError();
 }
 
-hipError_t launch_cell_starts(const uint32_t *asg_sorted, int64_t n, int P, int32_t *cell,
+hipError_t launch_cell_starts(const uint32_t *keys, int64_t n, int P, int32_t *cell,
                               hipStream_t s) {
     hipLaunchKernelGGL(cell_start_kernel, dim3((unsigned)((P + 1 + 255) / 256)), dim3(256), 0, s,
-                       asg_sorted, n, P, cell);
+                       keys, n, P, cell);
     return hipGetLastError();
 }
 
 hipError_t launch_prune_queries(const float *X, int64_t n, const float *Z, int64_t m, int d,
                                 const float *mu, void *sort_tmp, size_t sort_bytes,
-                                const int32_t *label, uint32_t *asg, uint32_t *asg_sorted,
-                                uint32_t *idx,
-                                uint32_t *qperm, const ScreenGeom &g, const void *Zq,
-                                const double *nzz, int64_t m_pad, void *Zq_out, float *nzq,
-                                const int32_t *cell, int32_t *rot, hipStream_t s) {
+                                const int32_t *label, const float *box, uint32_t *ka,
+                                uint32_t *kb, uint32_t *va, uint32_t *qperm, const ScreenGeom &g,
+                                const void *Zq, const double *nzz, int64_t m_pad, void *Zq_out,
+                                float *nzq, const uint32_t *keys, int32_t *rot, hipStream_t s) {
     if (d > 64 || g.row_bytes % 16 != 0) return hipErrorInvalidValue;
     const int P = prune_pivots(n);
     const int64_t stride = n / P;
-    launch_assign(X, Z, m, d, mu, P, stride, label, asg, idx, s);
+    const int bits = morton_bits(d);
+    uint32_t *first = (sort_passes(d) + 1) % 2 == 0 ? ka : kb;
+    launch_assign(X, Z, m, d, mu, P, stride, label, bits > 0 ? box : nullptr, bits, first, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    (void)idx;
-    e = launch_label_sort(asg, m, P, sort_tmp, sort_bytes, asg_sorted, qperm, s);
+    e = launch_key_sort(d, m, ka, kb, va, qperm, sort_tmp, sort_bytes, s);
     if (e != hipSuccess) return e;
     const int chunks = g.row_bytes / 16;
     const int64_t items = m_pad * chunks;
@@ -513,12 +730,13 @@ hipError_t launch_prune_queries(const float *X, int64_t n, const float *Z, int64
                        (uint4 *)Zq_out, (uint4 *)nullptr, nzq);
     const int64_t blocks = m_pad / SCREEN_QPB;
     hipLaunchKernelGGL(block_start_kernel, dim3((unsigned)((blocks + 255) / 256)), dim3(256), 0, s,
-                       asg_sorted, m, blocks, cell, rot);
+                       kb, m, blocks, keys, n, rot);
     return hipGetLastError();
 }
 
 hipError_t prune_query_sort_bytes(int64_t n, int64_t m, size_t *bytes) {
-    *bytes = (size_t)prune_pivots(n) * sort_tiles(m) * 4;
+    (void)n;
+    *bytes = (size_t)256 * sort_tiles(m) * 4;
     return hipSuccess;
 }
 

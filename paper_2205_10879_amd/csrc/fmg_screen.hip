@@ -222,6 +222,10 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
     __shared__ __align__(16) char ringB[TPB][TILE * RB];
     __shared__ __align__(16) uint32_t hist_all[4][256];
     __shared__ __align__(16) uint64_t stage_all[4][SCREEN_CMAX];
+    // Pruned scans: super-tiles some wave of the workgroup cannot skip (one
+    // bit each), and their list in scan order.
+    __shared__ uint32_t sup_keep[PRUNE ? SCREEN_SUPER_MAX / 32 : 1];
+    __shared__ uint16_t sup_list[PRUNE ? SCREEN_SUPER_MAX : 1];
 
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
@@ -230,16 +234,33 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
     const int split = blockIdx.y;
     const int cb = split * (int)a.col_chunk;
     const int ce = (cb + a.col_chunk < a.n_pad) ? cb + (int)a.col_chunk : (int)a.n_pad;
-    // Columns are visited at virtual positions v = 0, TILE, ... < len; with
-    // pruning the scan starts at this workgroup's own rows (the self-join's
-    // rows and columns share one order) and wraps around.
-    const int len = ce - cb;
-    const int rot = !PRUNE ? 0
-                    : a.rot_tab ? (int)(a.rot_tab[blockIdx.x] % len)
-                                : (int)(((int64_t)blockIdx.x * SCREEN_QPB) % len);
-    auto phys = [&](int v) {
-        int p = cb + v + rot;
-        return p >= ce ? p - len : p;
+    // Columns are visited at virtual positions v = 0, TILE, ... < len.
+    // Without pruning: in order.  With pruning (one split, n_pad a multiple
+    // of SCREEN_SUPER_ROWS) in two phases: first this workgroup's own
+    // super-tile, starting at its own rows (the self-join's rows and columns
+    // share one order; a prediction's start column comes from rot_tab) and
+    // wrapping within the super-tile; then, in order after it, the other
+    // super-tiles that some wave cannot skip with its thresholds at the end
+    // of the first phase (sup_list).
+    int len = ce - cb;
+    int own_sup = 0, rot_t = 0;
+    if constexpr (PRUNE) {
+        const int start = a.rot_tab ? (int)(a.rot_tab[blockIdx.x] % (ce - cb))
+                                    : (int)(((int64_t)blockIdx.x * SCREEN_QPB) % (ce - cb));
+        own_sup = start / SCREEN_SUPER_ROWS;
+        rot_t = (start % SCREEN_SUPER_ROWS) / TILE;
+        len = SCREEN_SUPER_ROWS;  // the first phase
+        if (threadIdx.x < SCREEN_SUPER_MAX / 32) sup_keep[threadIdx.x] = 0u;
+    }
+    auto phys = [&](int v) -> int {
+        if constexpr (!PRUNE) {
+            return cb + v;
+        } else {
+            const int t = v / TILE;
+            if (t < SCREEN_SUPER) return (own_sup * SCREEN_SUPER + ((rot_t + t) & (SCREEN_SUPER - 1))) * TILE;
+            return ((int)sup_list[(t - SCREEN_SUPER) / SCREEN_SUPER] * SCREEN_SUPER +
+                    (t & (SCREEN_SUPER - 1))) * TILE;
+        }
     };
     const int n_real = (int)a.n, m_real = (int)a.m;
     const char *__restrict__ Pb = (const char *)a.P;
@@ -311,11 +332,12 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
                             1.0e-6 * 1.02 * a.nx_max);
         }
     }
-    auto prune_mask = [&](int v0) -> uint32_t {
-        // centroid row r16 of the group belongs to the tile at v0 + r16 * TILE
-        const int vr = v0 + r16 * TILE;
+    // Skip bits of 16 balls (centre rows `cen`, radii `radius`): ball_row(j)
+    // and ball_rad(j) give the centre row and radius of ball j < 16 (a
+    // radius of +inf for a ball past the range: never skipped).
+    auto ball_mask = [&](auto ball_row, auto ball_rad) -> uint32_t {
         typename Op::frag_t af[KSTEPS];
-        const char *crow = (const char *)a.tile_c + (int64_t)(phys(vr < len ? vr : 0) / TILE) * RB;
+        const char *crow = ball_row(r16);
 #pragma unroll
         for (int s = 0; s < KSTEPS; ++s) af[s] = Op::load(crow + g * KSTEPS * Op::BPS + s * Op::BPS);
         f32x4 ac[4];
@@ -328,10 +350,7 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
         // this lane holds centroid rows 4g + i of the group
         float rad[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int vj = v0 + (4 * g + i) * TILE;
-            rad[i] = vj < len ? a.tile_r[phys(vj) / TILE] : INFINITY;
-        }
+        for (int i = 0; i < 4; ++i) rad[i] = ball_rad(4 * g + i);
         uint32_t skip = 0xffffu;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -355,6 +374,18 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
             }
         }
         return skip;
+    };
+    // The 16 tiles at virtual positions v0 + j * TILE.
+    auto prune_mask = [&](int v0) -> uint32_t {
+        return ball_mask(
+            [&](int j) {
+                const int vr = v0 + j * TILE;
+                return (const char *)a.tile_c + (int64_t)(phys(vr < len ? vr : 0) / TILE) * RB;
+            },
+            [&](int j) {
+                const int vj = v0 + j * TILE;
+                return vj < len ? a.tile_r[phys(vj) / TILE] : INFINITY;
+            });
     };
 
     // Counts of the four sub-pools of wave query (t, rl).
@@ -485,6 +516,68 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
         period(v, ringA, ringB);
         if (v + TPB * TILE < len) period(v + TPB * TILE, ringB, ringA);
     }
+    if constexpr (PRUNE) {
+        // Second phase: every wave marks the super-tiles it cannot skip with
+        // its current thresholds (which only fall, so a super-tile skipped
+        // now holds no candidate for any later threshold either); the kept
+        // ones after the own super-tile, in order and wrapping, are scanned.
+        const int nsup = (int)((ce - cb) / SCREEN_SUPER_ROWS);
+        for (int s0 = 0; s0 < nsup; s0 += 16) {
+            const uint32_t skip = ball_mask(
+                [&](int j) {
+                    const int sj = s0 + j < nsup ? s0 + j : s0;
+                    return (const char *)a.sup_c + (int64_t)sj * RB;
+                },
+                [&](int j) { return s0 + j < nsup ? a.sup_r[s0 + j] : INFINITY; });
+            const uint32_t keep = ~skip & 0xffffu;
+            if (lane == 0 && keep) atomicOr(&sup_keep[s0 / 32], keep << (s0 & 31));
+        }
+        __syncthreads();
+        if (wave == 0) {
+            // list: own + 1, ..., nsup - 1, then 0, ..., own - 1 (lane w
+            // counts word w; two exclusive scans place the indices)
+            int total = 0;
+            for (int part = 0; part < 2; ++part) {
+                for (int w0 = 0; w0 < SCREEN_SUPER_MAX / 32; w0 += 64) {
+                    const int w = w0 + lane;
+                    uint32_t bits = 0u;
+                    if (w * 32 < nsup) {
+                        bits = sup_keep[w];
+                        for (int b = 0; b < 32; ++b) {
+                            const int sidx = w * 32 + b;
+                            const bool in = sidx < nsup && sidx != own_sup &&
+                                            (part == 0 ? sidx > own_sup : sidx < own_sup);
+                            if (!in) bits &= ~(1u << b);
+                        }
+                    }
+                    const int cnt = __popc(bits);
+                    const int incl = wave_incl_scan(cnt, lane);
+                    int pos = total + incl - cnt;
+                    while (bits) {
+                        const int b = __ffs(bits) - 1;
+                        bits &= bits - 1;
+                        sup_list[pos++] = (uint16_t)(w * 32 + b);
+                    }
+                    total += __builtin_amdgcn_readlane(incl, 63);
+                }
+            }
+            if (lane == 0) sup_keep[0] = (uint32_t)total;  // the count, for every wave
+        }
+        __syncthreads();
+        const int kept = (int)sup_keep[0];
+        len = SCREEN_SUPER_ROWS * (1 + kept);
+        const int v1 = SCREEN_SUPER_ROWS;
+        if (v1 < len) {
+#pragma unroll
+            for (int j = 0; j < TPB; ++j) load_tile(phys(v1 + j * TILE), ringA[j]);
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            for (int v = v1; v < len; v += 2 * TPB * TILE) {
+                period(v, ringA, ringB);
+                if (v + TPB * TILE < len) period(v + TPB * TILE, ringB, ringA);
+            }
+        }
+    }
 
     // Final selection, sort and output of every real query of this wave.
     for (int ql = 0; ql < 64; ++ql) {
@@ -519,6 +612,13 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
 
 }  // namespace
 
+// A pruned screen: one split over whole super-tiles, with every bound array.
+bool pruned_args_ok(const ScreenArgs &a) {
+    return a.splits == 1 && a.col_chunk >= a.n_pad && a.tile_c && a.tile_r && a.sup_c &&
+           a.sup_r && a.nzq && a.n_pad % SCREEN_SUPER_ROWS == 0 &&
+           a.n_pad / SCREEN_SUPER_ROWS <= SCREEN_SUPER_MAX;
+}
+
 hipError_t launch_screen(const ScreenGeom &g, const ScreenArgs &a, hipStream_t s) {
     dim3 grid((unsigned)(a.m_pad / SCREEN_QPB), (unsigned)a.splits);
     if (a.c < 1 || a.c > SCREEN_CMAX) return hipErrorInvalidValue;
@@ -529,14 +629,14 @@ hipError_t launch_screen(const ScreenGeom &g, const ScreenArgs &a, hipStream_t s
     if (g.mode == SCREEN_BF16) {
         if (g.ksteps != 2) return hipErrorInvalidValue;
         if (a.prune) {
-            if (a.splits != 1 || !a.tile_c || !a.tile_r || !a.nzq) return hipErrorInvalidValue;
+            if (!pruned_args_ok(a)) return hipErrorInvalidValue;
             hipLaunchKernelGGL((screen_kernel<OpBF16, 2, SCREEN_CAP, true>), grid, dim3(256), 0, s,
                                a);
         } else {
             FMG_SCREEN_LAUNCH(OpBF16, 2);
         }
     } else if (a.prune) {
-        if (a.splits != 1 || !a.tile_c || !a.tile_r || !a.nzq) return hipErrorInvalidValue;
+        if (!pruned_args_ok(a)) return hipErrorInvalidValue;
         switch (g.ksteps) {
         case 4: FMG_SCREEN_LAUNCH_PRUNED(OpF32, 4); break;
         case 8: FMG_SCREEN_LAUNCH_PRUNED(OpF32, 8); break;
