@@ -119,7 +119,10 @@ void predict_ws_carve(PredictWs *ws, void *base, int64_t max_m, int64_t pool_row
 // Direct predictions of at least this many queries on a model with a pivot
 // order use the pruned screen (enough workgroups to fill the device from one
 // column range).
-constexpr int64_t PREDICT_PRUNE_MIN = 65536;
+#ifndef FMG_PREDICT_PRUNE_MIN
+#define FMG_PREDICT_PRUNE_MIN 65536
+#endif
+constexpr int64_t PREDICT_PRUNE_MIN = FMG_PREDICT_PRUNE_MIN;
 
 fmg_status set_error(fmg_status st, const char *fmt, ...);
 // Clear the calling thread's last error message.

@@ -226,6 +226,9 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
     // bit each), and their list in scan order.
     __shared__ uint32_t sup_keep[PRUNE ? SCREEN_SUPER_MAX / 32 : 1];
     __shared__ uint16_t sup_list[PRUNE ? SCREEN_SUPER_MAX : 1];
+    // Pruned scans: per group of 16 tiles the tiles some wave needs (one bit
+    // each, OR over the waves), three buffers used in turn.
+    __shared__ uint32_t grp_need[3];
 
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
@@ -251,6 +254,7 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
         rot_t = (start % SCREEN_SUPER_ROWS) / TILE;
         len = SCREEN_SUPER_ROWS;  // the first phase
         if (threadIdx.x < SCREEN_SUPER_MAX / 32) sup_keep[threadIdx.x] = 0u;
+        if (threadIdx.x < 3) grp_need[threadIdx.x] = 0u;
     }
     auto phys = [&](int v) -> int {
         if constexpr (!PRUNE) {
@@ -507,16 +511,61 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
         __syncthreads();
     };
 
+    // Pruned scans go a group of 16 tiles at a time: every wave computes its
+    // skip bits for the group, the workgroup ORs the tiles some wave needs,
+    // and only those are loaded; a group no wave needs costs one barrier.
+    // Within a group the periods run as in the full scan, the next period's
+    // needed tiles loading while the current one is screened.
+    int grp = 0;
+    auto run_groups = [&](int v_begin) {
+        for (int v0 = v_begin; v0 < len; v0 += 16 * TILE, ++grp) {
+            skip16 = prune_mask(v0);
+            const int gb = grp % 3;
+            if (lane == 0 && (skip16 & 0xffffu) != 0xffffu) atomicOr(&grp_need[gb], ~skip16 & 0xffffu);
+            __syncthreads();
+            const uint32_t need = grp_need[gb];
+            if (threadIdx.x == 0) grp_need[(grp + 2) % 3] = 0u;  // ordered by the next group's barrier
+            if (need == 0u) continue;
+            auto load_period = [&](int vp, char (*dst)[TILE * RB]) {
 #pragma unroll
-    for (int j = 0; j < TPB; ++j)
-        if (j * TILE < len) load_tile(phys(j * TILE), ringA[j]);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-    __syncthreads();
-    for (int v = 0; v < len; v += 2 * TPB * TILE) {
-        period(v, ringA, ringB);
-        if (v + TPB * TILE < len) period(v + TPB * TILE, ringB, ringA);
-    }
-    if constexpr (PRUNE) {
+                for (int j = 0; j < TPB; ++j) {
+                    const int t = ((vp - v0) >> 6) + j;
+                    if (vp + j * TILE < len && ((need >> t) & 1u)) load_tile(phys(vp + j * TILE), dst[j]);
+                }
+            };
+            load_period(v0, ringA);
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+#pragma unroll 1
+            for (int p = 0; p < 16 / TPB; ++p) {
+                const int vp = v0 + p * TPB * TILE;
+                char(*cur)[TILE * RB] = (p & 1) ? ringB : ringA;
+                char(*nxt)[TILE * RB] = (p & 1) ? ringA : ringB;
+                if (p + 1 < 16 / TPB) load_period(vp + TPB * TILE, nxt);
+#pragma unroll 1
+                for (int j = 0; j < TPB; ++j)
+                    if (vp + j * TILE < len)
+                        screen_tile(phys(vp + j * TILE), cur[j], ((vp >> 6) + j) & 15);
+                if (__ballot(cnt[0] > TRIG || cnt[1] > TRIG || cnt[2] > TRIG || cnt[3] > TRIG) != 0)
+                    flush_full();
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                __syncthreads();
+            }
+        }
+    };
+    if constexpr (!PRUNE) {
+#pragma unroll
+        for (int j = 0; j < TPB; ++j)
+            if (j * TILE < len) load_tile(phys(j * TILE), ringA[j]);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        for (int v = 0; v < len; v += 2 * TPB * TILE) {
+            period(v, ringA, ringB);
+            if (v + TPB * TILE < len) period(v + TPB * TILE, ringB, ringA);
+        }
+    } else {
+        __syncthreads();  // the LDS words above are cleared
+        run_groups(0);
         // Second phase: every wave marks the super-tiles it cannot skip with
         // its current thresholds (which only fall, so a super-tile skipped
         // now holds no candidate for any later threshold either); the kept
@@ -566,17 +615,7 @@ __global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
         __syncthreads();
         const int kept = (int)sup_keep[0];
         len = SCREEN_SUPER_ROWS * (1 + kept);
-        const int v1 = SCREEN_SUPER_ROWS;
-        if (v1 < len) {
-#pragma unroll
-            for (int j = 0; j < TPB; ++j) load_tile(phys(v1 + j * TILE), ringA[j]);
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-            __syncthreads();
-            for (int v = v1; v < len; v += 2 * TPB * TILE) {
-                period(v, ringA, ringB);
-                if (v + TPB * TILE < len) period(v + TPB * TILE, ringB, ringA);
-            }
-        }
+        run_groups(SCREEN_SUPER_ROWS);
     }
 
     // Final selection, sort and output of every real query of this wave.
