@@ -461,72 +461,80 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
         lds_sync();
         const double diag64 = P.amp + P.noise;
         const PhiForm<double> pf64 = phi_form<double>(P.kc, P.inv_rho, P.amp);
-        // Column tiles go in groups of PG: each MFMA operand formed from the
-        // raw rows serves every tile of the group.
-        constexpr int PG = 2;
-        static_assert(NT % PG == 0, "column tile groups");
-        f64x4 R[NT];
+        // The Gram matrix is symmetric: only its tiles on and below the
+        // diagonal, (r, c) with r >= c, go through the MFMA (each operand
+        // formed from the raw rows serves every tile of its k-step), and
+        // kernel values are evaluated once per such tile.  A tile above the
+        // diagonal is the transpose of its mirror: the same products summed in
+        // the same order and the two norms added the other way round, so its
+        // entries are exactly the mirror's, read back transposed through LDS.
+        constexpr int NL = NT * (NT + 1) / 2;
+        f64x4 G[NL];  // tile (r, c), r >= c, at r (r + 1) / 2 + c
 #pragma unroll
-        for (int c0 = 0; c0 < NT; c0 += PG) {
-            f64x4 g[PG][NT];
+        for (int t = 0; t < NL; ++t) G[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+        for (int s = 0; s < d4; s += 4) {
+            double f[NT];
+            const double cc = (double)xc[s + fk];
 #pragma unroll
-            for (int h = 0; h < PG; ++h)
-#pragma unroll
-                for (int r = 0; r < NT; ++r) g[h][r] = f64x4{0.0, 0.0, 0.0, 0.0};
-            if (c0 * 16 < k) {
-                for (int s = 0; s < d4; s += 4) {
-                    double f[NT];
-                    const double cc = (double)xc[s + fk];
-#pragma unroll
-                    for (int r = 0; r < NT; ++r) {
-                        const int row = r * 16 + fr;
-                        f[r] = (row < k) ? (double)xr[row * ld + s + fk] - cc : 0.0;
-                    }
-#pragma unroll
-                    for (int h = 0; h < PG; ++h) {
-                        if (h == 0 || (c0 + h) * 16 < k) {
-#pragma unroll
-                            for (int r = 0; r < NT; ++r)
-                                g[h][r] = __builtin_amdgcn_mfma_f64_16x16x4f64(f[r], f[c0 + h],
-                                                                               g[h][r], 0, 0, 0);
-                        }
-                    }
-                }
+            for (int r = 0; r < NT; ++r) {
+                const int row = r * 16 + fr;
+                f[r] = (row < k) ? (double)xr[row * ld + s + fk] - cc : 0.0;
             }
 #pragma unroll
-            for (int h = 0; h < PG; ++h) {
-                const int ct = c0 + h;
-                const int rb = ct * 16 + fr;
-                const double ncol = nrm64[rb];
+            for (int r = 0; r < NT; ++r)
 #pragma unroll
-                for (int r = 0; r < NT; ++r) {
+                for (int c = 0; c <= r; ++c)
+                    if (r * 16 < k)
+                        G[r * (r + 1) / 2 + c] =
+                            __builtin_amdgcn_mfma_f64_16x16x4f64(f[r], f[c], G[r * (r + 1) / 2 + c], 0, 0, 0);
+        }
+        // kernel values of the lower tiles, in place: lane l holds entries
+        // (r * 16 + 4 q + l / 16, c * 16 + l % 16)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const double D = nrm64[r * 16 + 4 * q + fk] + ncol - 2.0 * g[h][r][q];
-                        g[h][r][q] = D > 0.0 ? D : 0.0;
-                    }
+        for (int r = 0; r < NT; ++r)
+#pragma unroll
+            for (int c = 0; c <= r; ++c) {
+                f64x4 &T = G[r * (r + 1) / 2 + c];
+                const int col = c * 16 + fr;
+                const double ncol = nrm64[col];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = r * 16 + 4 * q + fk;
+                    double D = nrm64[row] + ncol - 2.0 * T[q];
+                    D = D > 0.0 ? D : 0.0;
+                    if (pf64.root) D = sqrt(D);
+                    double kab = 0.0;
+                    if (row < k && col < k) kab = (row == col) ? diag64 : phi_arg64(pf64, D);
+                    T[q] = kab;
                 }
-                if (pf64.root) {
+            }
+        lds_sync();  // the raw rows are dead: their space holds the transposes
+        double *tr = (double *)(smem + L.off_r1);  // [NT - 1][16 x 16]
+        f64x4 R[NT];
 #pragma unroll
-                    for (int r = 0; r < NT; ++r)
+        for (int ct = 0; ct < NT; ++ct) {
+            // tiles (r, ct), r < ct: the transposes of the lower tiles (ct, r)
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) g[h][r][q] = sqrt(g[h][r][q]);
-                }
-                f64x4 acc64 = f64x4{0.0, 0.0, 0.0, 0.0};
+            for (int r = 0; r < ct; ++r)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) tr[r * 256 + (4 * q + fk) * 16 + fr] = G[ct * (ct + 1) / 2 + r][q];
+            lds_sync();
+            f64x4 acc64 = f64x4{0.0, 0.0, 0.0, 0.0};
+            if (ct * 16 < k) {
 #pragma unroll
                 for (int r = 0; r < NT; ++r) {
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int row = r * 16 + 4 * q + fk;
-                        double kab = 0.0;
-                        if (row < k && rb < k)
-                            kab = (row == rb) ? diag64 : phi_arg64(pf64, g[h][r][q]);
+                        const double kab = (r >= ct) ? G[r * (r + 1) / 2 + ct][q]
+                                                     : tr[r * 256 + fr * 16 + 4 * q + fk];
                         const double cv = (fr < ell) ? (double)cb[row * ELLMAX + fr] : 0.0;
                         acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(kab, cv, acc64, 0, 0, 0);
                     }
                 }
-                R[ct] = acc64;
             }
+            R[ct] = acc64;
+            lds_sync();  // the transposes are read before the next tile's are written
         }
         lds_sync();  // the raw rows are dead; their space takes K64 C
         double *KC = (double *)(smem + L.off_r1);  // [64][ELLMAX]

@@ -204,13 +204,20 @@ __device__ __forceinline__ int select_pool(uint64_t *__restrict__ qpool, const i
     return base;
 }
 
+#ifndef FMG_SCREEN_TPB
+#define FMG_SCREEN_TPB 4
+#endif
+#ifndef FMG_SCREEN_WGS
+#define FMG_SCREEN_WGS 2
+#endif
+
 template <class Op, int KSTEPS, int CAP, bool PRUNE>
-__global__ __launch_bounds__(256, 2) void screen_kernel(ScreenArgs a) {
+__global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs a) {
     constexpr int RB = 4 * KSTEPS * Op::BPS;  // row bytes
     constexpr int CH = RB / 16;               // 16-byte chunks per row
     constexpr int SWZ = (CH % 8 == 0) ? 7 : 3;  // chunk XOR swizzle (bank spread)
     constexpr int LDI = CH / 4;               // LDS-DMA loads per wave per tile
-    constexpr int TPB = 4;                    // tiles per barrier period
+    constexpr int TPB = FMG_SCREEN_TPB;       // tiles per barrier period
     constexpr int SUB = CAP / 4;              // sub-pool per lane group
     constexpr int TRIG = SUB - 16 * TPB;      // select when a sub-pool exceeds this
     constexpr int PE = CAP / 64;
