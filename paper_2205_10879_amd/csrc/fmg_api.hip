@@ -253,6 +253,8 @@ void **model_array(fmg_model *M, int idx) {
     case MA_BOX: return (void **)&M->box;
     case MA_SC: return &M->sup_c;
     case MA_SR: return (void **)&M->sup_r;
+    case MA_GC: return &M->grp_c;
+    case MA_GR: return (void **)&M->grp_r;
     default: return (void **)&M->mu;
     }
 }
@@ -488,6 +490,8 @@ fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_
             sa.tile_r = M->tile_r;
             sa.sup_c = M->sup_c;
             sa.sup_r = M->sup_r;
+            sa.grp_c = M->grp_c;
+            sa.grp_r = M->grp_r;
             sa.nzq = nzq;
             sa.acc_coef = M->acc_coef;
             sa.nx_max = M->nx_max;
@@ -903,6 +907,9 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
             const size_t nsup = (size_t)(n_pad / SCREEN_SUPER_ROWS);
             MCHK(model_alloc(M, MA_SC, &M->sup_c, nsup * geom.row_bytes, "model super-tiles"));
             MCHK(model_alloc(M, MA_SR, (void **)&M->sup_r, nsup * 4, "model super-tiles"));
+            const size_t ngrp = (size_t)(n_pad / SCREEN_GROUP_ROWS);
+            MCHK(model_alloc(M, MA_GC, &M->grp_c, ngrp * geom.row_bytes, "model tile groups"));
+            MCHK(model_alloc(M, MA_GR, (void **)&M->grp_r, ngrp * 4, "model tile groups"));
             perm = M->perm;
             HCHK(tmp.alloc((void **)&ka, (size_t)n * 4), "scratch");
             HCHK(tmp.alloc((void **)&va, (size_t)n * 4), "scratch");
@@ -914,7 +921,8 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
                  "pivot order");
             HCHK(launch_cell_starts(M->keys, n, npiv, M->cell, s), "cell starts");
             HCHK(launch_prune_rows(geom, Xq, M->Xp, nzx, perm, n, n_pad, d, Xq2, M->Xpp, nzq,
-                                   M->tile_c, M->tile_r, M->sup_c, M->sup_r, s),
+                                   M->tile_c, M->tile_r, M->grp_c, M->grp_r, M->sup_c,
+                                   M->sup_r, s),
                  "pruning rows");
             MCHK(read_maxima());
             sa.Q = Xq2;
@@ -924,6 +932,8 @@ fmg_status fastmuygps_build(const void *X, const void *Y, int64_t n, int32_t d, 
             sa.tile_r = M->tile_r;
             sa.sup_c = M->sup_c;
             sa.sup_r = M->sup_r;
+            sa.grp_c = M->grp_c;
+            sa.grp_r = M->grp_r;
             sa.nzq = nzq;
             sa.acc_coef = M->acc_coef;
             sa.nx_max = M->nx_max;

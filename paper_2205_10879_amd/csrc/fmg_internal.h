@@ -17,7 +17,7 @@ enum { EV_START = 0, EV_PREP, EV_SCREEN, EV_RERANK, EV_FALLBACK, EV_LAST, EV_COU
 // Device arrays of a model, in the order they are moved between device and
 // host memory by model_offload / model_restore.
 enum { MA_X = 0, MA_N, MA_C, MA_XP, MA_MU, MA_Y, MA_PERM, MA_XPP, MA_TC, MA_TR, MA_CELL, MA_KEYS,
-       MA_BOX, MA_SC, MA_SR, MA_COUNT };
+       MA_BOX, MA_SC, MA_SR, MA_GC, MA_GR, MA_COUNT };
 
 }  // namespace fmg
 
@@ -53,6 +53,8 @@ struct fmg_model {
     float *box = nullptr;      // [128] the Morton code's box: low ends, then scales
     void *sup_c = nullptr;     // [n_pad / SCREEN_SUPER_ROWS, kp] super-tile centroid rows
     float *sup_r = nullptr;    // [n_pad / SCREEN_SUPER_ROWS] super-tile radii
+    void *grp_c = nullptr;     // [n_pad / SCREEN_GROUP_ROWS, kp] group centroid rows
+    float *grp_r = nullptr;    // [n_pad / SCREEN_GROUP_ROWS] group radii
     double e_max = 0.0, nx_max = 0.0, acc_coef = 0.0;
     int c_build = 0, c_query = 0;
     int64_t nonpd = 0, build_fb = 0;

@@ -24,6 +24,10 @@ constexpr int SCREEN_CMAX = 128;
 constexpr int SCREEN_SUPER = 256;
 constexpr int SCREEN_SUPER_ROWS = SCREEN_SUPER * SCREEN_TILE;
 constexpr int SCREEN_SUPER_MAX = 2048;
+// Between the two, groups of SCREEN_GROUP tiles (16 per super-tile), the
+// unit in which a pruned scan loads tiles.
+constexpr int SCREEN_GROUP = 16;
+constexpr int SCREEN_GROUP_ROWS = SCREEN_GROUP * SCREEN_TILE;
 
 // Row layout of the screening arrays: `kp` elements per row (bf16 or f32),
 // row bytes = kp * elem.  bf16: kp = 64 (2 MFMA k-steps of 32); f32: kp a
@@ -57,6 +61,8 @@ struct ScreenArgs {
     const float *tile_r; // [n_pad / SCREEN_TILE]
     const void *sup_c;   // [n_pad / SCREEN_SUPER_ROWS, kp] super-tile centroid rows
     const float *sup_r;  // [n_pad / SCREEN_SUPER_ROWS] super-tile radii
+    const void *grp_c;   // [n_pad / SCREEN_GROUP_ROWS, kp] group centroid rows
+    const float *grp_r;  // [n_pad / SCREEN_GROUP_ROWS] group radii
     const float *nzq;    // [m_pad] ||z~||^2 of the query rows
     double acc_coef, nx_max;
     // Optional start column of each workgroup (a multiple of SCREEN_TILE);
@@ -228,15 +234,16 @@ hipError_t prune_sort_bytes(int64_t n, size_t *bytes);
 hipError_t launch_prune_order(const float *X, int64_t n, int d, const float *mu, void *sort_tmp,
                               size_t sort_bytes, int32_t *label, float *box, uint32_t *ka,
                               uint32_t *keys, uint32_t *va, uint32_t *perm, hipStream_t s);
-// Also the super-tile balls: per SCREEN_SUPER tiles a centroid row (the mean
-// of the tiles' real centroids, in the row format) and a radius
-// max_t (||c_t - c|| + r_t) (FP64, rounded up); n_pad must be a multiple of
-// SCREEN_SUPER_ROWS.  Tiles and super-tiles with no real row get a negative
-// radius of -1e18, so every screen skips them.
+// Also the group and super-tile balls: per SCREEN_GROUP (SCREEN_SUPER) tiles a
+// centroid row (the mean of the tiles' real centroids, in the row format) and
+// a radius max_t (||c_t - c|| + r_t) (FP64, rounded up); n_pad must be a
+// multiple of SCREEN_SUPER_ROWS.  Balls with no real row get a negative radius
+// of -1e18, so every screen skips them.
 hipError_t launch_prune_rows(const ScreenGeom &g, const void *Qrows, const void *Prows,
                              const double *nz, const uint32_t *perm, int64_t n, int64_t n_pad,
                              int d, void *Qout, void *Pout, float *nzq, void *tile_c,
-                             float *tile_r, void *sup_c, float *sup_r, hipStream_t s);
+                             float *tile_r, void *grp_c, float *grp_r, void *sup_c, float *sup_r,
+                             hipStream_t s);
 // cell[j], j <= P: first position of pivot j in the sorted keys.
 hipError_t launch_cell_starts(const uint32_t *keys, int64_t n, int P, int32_t *cell,
                               hipStream_t s);

@@ -375,22 +375,22 @@ __global__ __launch_bounds__(64) void tile_bounds_f32_kernel(const float *__rest
     if (lane == 0) rad[tile] = (float)(sqrt(mx) * (1.0 + 1.0e-6)) * (1.0f + 1.0e-6f);
 }
 
-// One wave per super-tile of SCREEN_SUPER tiles: the centroid row of the
-// super-tile (the mean of its real tiles' centroids, rounded to the row
-// format: BF16 rows hold -2 c then three BF16 parts of ||c||^2, FP32 rows
-// -2 c then ||c||^2) and the radius max_t (||c_t - c|| + r_t) over its real
-// tiles (FP64, rounded up): by the triangle inequality every row of the
-// super-tile lies within it.  Coordinates are recovered exactly from the
+// One wave per ball of `fan` consecutive tiles (a group or a super-tile): the
+// centroid row of the ball (the mean of its real tiles' centroids, rounded to
+// the row format: BF16 rows hold -2 c then three BF16 parts of ||c||^2, FP32
+// rows -2 c then ||c||^2) and the radius max_t (||c_t - c|| + r_t) over its
+// real tiles (FP64, rounded up): by the triangle inequality every row of the
+// ball's tiles lies within it.  Coordinates are recovered exactly from the
 // rows' -2 x entries.
 template <bool BF16>
 __global__ __launch_bounds__(64) void super_bounds_kernel(const void *__restrict__ tile_c,
                                                           const float *__restrict__ tile_r,
-                                                          int d, int kp,
+                                                          int d, int kp, int fan,
                                                           void *__restrict__ sup_c,
                                                           float *__restrict__ sup_r) {
     __shared__ double ctr[64];
     const int lane = threadIdx.x;
-    const int64_t s0 = (int64_t)blockIdx.x * SCREEN_SUPER;
+    const int64_t s0 = (int64_t)blockIdx.x * fan;
     auto coord = [&](int64_t t, int c) -> double {
         if (BF16) return -0.5 * (double)bf16_to_f32(((const uint16_t *)tile_c)[t * kp + c]);
         return -0.5 * (double)((const float *)tile_c)[t * kp + c];
@@ -398,7 +398,7 @@ __global__ __launch_bounds__(64) void super_bounds_kernel(const void *__restrict
     // real tiles: radius not negative
     int cnt = 0;
     double sum = 0.0;
-    for (int t = 0; t < SCREEN_SUPER; ++t) {
+    for (int t = 0; t < fan; ++t) {
         if (!(tile_r[s0 + t] >= 0.0f)) continue;
         ++cnt;
         if (lane < d) sum += coord(s0 + t, lane);
@@ -417,7 +417,7 @@ __global__ __launch_bounds__(64) void super_bounds_kernel(const void *__restrict
     const double nc = wave_sum_f64(ct * ct);
     // radius: lane handles tiles lane, lane + 64, ...
     double mx = cnt > 0 ? 0.0 : -1.0e18;
-    for (int t = lane; t < SCREEN_SUPER; t += 64) {
+    for (int t = lane; t < fan; t += 64) {
         const float r = tile_r[s0 + t];
         if (!(r >= 0.0f)) continue;
         double e2 = 0.0;
@@ -672,7 +672,8 @@ hipError_t launch_prune_order(const float *X, int64_t n, int d, const float *mu,
 hipError_t launch_prune_rows(const ScreenGeom &g, const void *Qrows, const void *Prows,
                              const double *nz, const uint32_t *perm, int64_t n, int64_t n_pad,
                              int d, void *Qout, void *Pout, float *nzq, void *tile_c,
-                             float *tile_r, void *sup_c, float *sup_r, hipStream_t s) {
+                             float *tile_r, void *grp_c, float *grp_r, void *sup_c, float *sup_r,
+                             hipStream_t s) {
     if (g.row_bytes % 16 != 0 || n_pad % SCREEN_SUPER_ROWS != 0) return hipErrorInvalidValue;
     const int chunks = g.row_bytes / 16;
     const int64_t items = n_pad * chunks;
@@ -690,13 +691,18 @@ hipError_t launch_prune_rows(const ScreenGeom &g, const void *Qrows, const void 
         hipLaunchKernelGGL(tile_bounds_f32_kernel, dim3((unsigned)(n_pad / SCREEN_TILE)), dim3(64),
                            0, s, (const float *)Pout, n, d, g.kp, (float *)tile_c, tile_r);
     }
-    const unsigned nsup = (unsigned)(n_pad / SCREEN_SUPER_ROWS);
-    if (g.mode == SCREEN_BF16)
-        hipLaunchKernelGGL(super_bounds_kernel<true>, dim3(nsup), dim3(64), 0, s,
-                           (const void *)tile_c, (const float *)tile_r, d, g.kp, sup_c, sup_r);
-    else
-        hipLaunchKernelGGL(super_bounds_kernel<false>, dim3(nsup), dim3(64), 0, s,
-                           (const void *)tile_c, (const float *)tile_r, d, g.kp, sup_c, sup_r);
+    for (int level = 0; level < 2; ++level) {
+        const int fan = level == 0 ? SCREEN_GROUP : SCREEN_SUPER;
+        const unsigned balls = (unsigned)(n_pad / SCREEN_TILE / fan);
+        void *bc = level == 0 ? grp_c : sup_c;
+        float *br = level == 0 ? grp_r : sup_r;
+        if (g.mode == SCREEN_BF16)
+            hipLaunchKernelGGL(super_bounds_kernel<true>, dim3(balls), dim3(64), 0, s,
+                               (const void *)tile_c, (const float *)tile_r, d, g.kp, fan, bc, br);
+        else
+            hipLaunchKernelGGL(super_bounds_kernel<false>, dim3(balls), dim3(64), 0, s,
+                               (const void *)tile_c, (const float *)tile_r, d, g.kp, fan, bc, br);
+    }
     return hipGetLastError();
 }
 

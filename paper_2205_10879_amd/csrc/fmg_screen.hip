@@ -234,8 +234,10 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
     __shared__ uint32_t sup_keep[PRUNE ? SCREEN_SUPER_MAX / 32 : 1];
     __shared__ uint16_t sup_list[PRUNE ? SCREEN_SUPER_MAX : 1];
     // Pruned scans: per group of 16 tiles the tiles some wave needs (one bit
-    // each, OR over the waves), three buffers used in turn.
+    // each, OR over the waves), and per super-tile its groups some wave needs;
+    // three buffers of each, used in turn.
     __shared__ uint32_t grp_need[3];
+    __shared__ uint32_t sup_grp[3];
 
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
@@ -258,10 +260,13 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
         const int start = a.rot_tab ? (int)(a.rot_tab[blockIdx.x] % (ce - cb))
                                     : (int)(((int64_t)blockIdx.x * SCREEN_QPB) % (ce - cb));
         own_sup = start / SCREEN_SUPER_ROWS;
-        rot_t = (start % SCREEN_SUPER_ROWS) / TILE;
+        rot_t = ((start % SCREEN_SUPER_ROWS) / TILE) & ~(SCREEN_GROUP - 1);  // whole groups
         len = SCREEN_SUPER_ROWS;  // the first phase
         if (threadIdx.x < SCREEN_SUPER_MAX / 32) sup_keep[threadIdx.x] = 0u;
-        if (threadIdx.x < 3) grp_need[threadIdx.x] = 0u;
+        if (threadIdx.x < 3) {
+            grp_need[threadIdx.x] = 0u;
+            sup_grp[threadIdx.x] = 0u;
+        }
     }
     auto phys = [&](int v) -> int {
         if constexpr (!PRUNE) {
@@ -446,15 +451,56 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
         for (int t = 0; t < 4; ++t)
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) acc[t][mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < KSTEPS; ++s) {
-            typename Op::frag_t af[4];
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt) af[mt] = Op::load(cur + mt * 16 * RB + frag_off[s]);
+        if constexpr (std::is_same<Op, OpBF16>::value && KSTEPS == 2 && RB == 128) {
+            // The eight 16-byte fragments of the tile in one asm block that
+            // also waits for them.  Read through the compiler, every tile
+            // read would first wait for all vector memory operations in
+            // flight (the next period's LDS-DMA loads and this wave's pool
+            // appends), since the compiler cannot tell the DMA's LDS target
+            // from the ring being read.  The ring read here was filled before
+            // the last period's barrier, which waited for its loads.
+            const uint32_t base =
+                (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)cur;
+            uint4 f0, f1, f2, f3, f4, f5, f6, f7;
+            asm volatile(
+                "ds_read_b128 %0, %8\n\t"
+                "ds_read_b128 %1, %8 offset:2048\n\t"
+                "ds_read_b128 %2, %8 offset:4096\n\t"
+                "ds_read_b128 %3, %8 offset:6144\n\t"
+                "ds_read_b128 %4, %9\n\t"
+                "ds_read_b128 %5, %9 offset:2048\n\t"
+                "ds_read_b128 %6, %9 offset:4096\n\t"
+                "ds_read_b128 %7, %9 offset:6144\n\t"
+                "s_waitcnt lgkmcnt(0)"
+                : "=&v"(f0), "=&v"(f1), "=&v"(f2), "=&v"(f3), "=&v"(f4), "=&v"(f5), "=&v"(f6),
+                  "=&v"(f7)
+                : "v"(base + (uint32_t)frag_off[0]), "v"(base + (uint32_t)frag_off[1])
+                : "memory");
+            static_assert(16 * RB == 2048, "fragment offsets of the asm block");
+            const bf16x8 a0[4] = {__builtin_bit_cast(bf16x8, f0), __builtin_bit_cast(bf16x8, f1),
+                                  __builtin_bit_cast(bf16x8, f2), __builtin_bit_cast(bf16x8, f3)};
+            const bf16x8 a1[4] = {__builtin_bit_cast(bf16x8, f4), __builtin_bit_cast(bf16x8, f5),
+                                  __builtin_bit_cast(bf16x8, f6), __builtin_bit_cast(bf16x8, f7)};
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
-                for (int mt = 0; mt < 4; ++mt) acc[t][mt] = Op::mfma(af[mt], bq[t][s], acc[t][mt]);
+                for (int mt = 0; mt < 4; ++mt) acc[t][mt] = Op::mfma(a0[mt], bq[t][0], acc[t][mt]);
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) acc[t][mt] = Op::mfma(a1[mt], bq[t][1], acc[t][mt]);
+        } else {
+#pragma unroll
+            for (int s = 0; s < KSTEPS; ++s) {
+                typename Op::frag_t af[4];
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) af[mt] = Op::load(cur + mt * 16 * RB + frag_off[s]);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int mt = 0; mt < 4; ++mt)
+                        acc[t][mt] = Op::mfma(af[mt], bq[t][s], acc[t][mt]);
+            }
         }
 
         // Candidate selection.  For each query tile t a lane holds 16 values
@@ -462,37 +508,37 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
         // v_min3, no canonicalisation: the file is built without IEEE mode,
         // every screened value being finite) is tested against the query's
         // threshold, so a query tile whose candidates all fail costs one
-        // wave-wide branch.  Otherwise each candidate tile is tested the same
-        // way, and a passing lane compares its four values and appends to its
-        // own sub-pool.  The query's own index and padding candidates may be
-        // appended here; the selection drops them.
+        // wave-wide branch.  Otherwise all 16 comparisons are made at once,
+        // each into a wave mask of its own, and each mask that has a lane set
+        // becomes the execution mask of one append (a lane appends to its own
+        // sub-pool): the comparisons do not wait on one another, and the
+        // appends cost scalar branches only.  The query's own index and
+        // padding candidates may be appended here; the selection drops them.
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
+            const float th = thr[t];
             float m16 = acc[t][0][0];
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
                 for (int i = (mt == 0 ? 1 : 0); i < 4; ++i) m16 = fminf(m16, acc[t][mt][i]);
-            if (__ballot(m16 <= thr[t]) == 0) continue;
+            if (__ballot(m16 <= th) == 0) continue;
+            uint64_t B[16];
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                const f32x4 v = acc[t][mt];
-                const float mn = fminf(fminf(v[0], v[1]), fminf(v[2], v[3]));
-                const bool lane_pass = mn <= thr[t];
-                if (__ballot(lane_pass) != 0) {
-                    if (lane_pass) {
+            for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            if (v[i] <= thr[t]) {
-                                const uint32_t p = (uint32_t)(col + mt * 16 + g * 4 + i);
-                                mysub[(uint32_t)(t * 64 * SUB) + (uint32_t)cnt[t]] =
-                                    raw_entry(v[i], p);
-                                cnt[t] += 1;
-                            }
-                        }
+                for (int i = 0; i < 4; ++i) B[mt * 4 + i] = __ballot(acc[t][mt][i] <= th);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (__builtin_amdgcn_inverse_ballot_w64(B[mt * 4 + i])) {
+                        const uint32_t p = (uint32_t)(col + mt * 16 + g * 4 + i);
+                        mysub[(uint32_t)(t * 64 * SUB) + (uint32_t)cnt[t]] =
+                            raw_entry(acc[t][mt][i], p);
+                        cnt[t] += 1;
                     }
                 }
-            }
         }
     };
 
@@ -518,20 +564,50 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
         __syncthreads();
     };
 
-    // Pruned scans go a group of 16 tiles at a time: every wave computes its
-    // skip bits for the group, the workgroup ORs the tiles some wave needs,
-    // and only those are loaded; a group no wave needs costs one barrier.
-    // Within a group the periods run as in the full scan, the next period's
-    // needed tiles loading while the current one is screened.
-    int grp = 0;
+    // Pruned scans go a super-tile, then a group of 16 tiles at a time.  At a
+    // super-tile's start every wave tests its 16 group balls and the
+    // workgroup ORs the groups some wave needs (one barrier); a group no wave
+    // needs is passed over.  In a needed group every wave that needs it
+    // computes its skip bits for the group's tiles, the workgroup ORs the
+    // tiles some wave needs, and only those are loaded; a group whose tiles
+    // no wave needs costs one barrier.  Within a group the periods run as in
+    // the full scan, the next period's needed tiles loading while the current
+    // one is screened.  Super-tiles start at multiples of SCREEN_SUPER_ROWS
+    // and groups at multiples of SCREEN_GROUP_ROWS (virtual and physical
+    // positions alike), so the group balls line up with the scan.
+    int grp = 0;  // groups taken, for the grp_need buffers
+    int sgi = 0;  // super-tiles entered, for the sup_grp buffers
     auto run_groups = [&](int v_begin) {
-        for (int v0 = v_begin; v0 < len; v0 += 16 * TILE, ++grp) {
-            skip16 = prune_mask(v0);
+        uint32_t gneed = 0u, gmine = 0u;
+        for (int v0 = v_begin; v0 < len; v0 += SCREEN_GROUP_ROWS) {
+            const int jg = (v0 / SCREEN_GROUP_ROWS) & (SCREEN_GROUP - 1);
+            if (jg == 0) {
+                gmine = ~ball_mask(
+                            [&](int j) {
+                                return (const char *)a.grp_c +
+                                       (int64_t)(phys(v0 + j * SCREEN_GROUP_ROWS) /
+                                                 SCREEN_GROUP_ROWS) * RB;
+                            },
+                            [&](int j) {
+                                return a.grp_r[phys(v0 + j * SCREEN_GROUP_ROWS) /
+                                               SCREEN_GROUP_ROWS];
+                            }) &
+                        0xffffu;
+                const int sb = sgi % 3;
+                if (lane == 0 && gmine != 0u) atomicOr(&sup_grp[sb], gmine);
+                __syncthreads();
+                gneed = sup_grp[sb];
+                if (threadIdx.x == 0) sup_grp[(sgi + 2) % 3] = 0u;  // ordered by the next one's barrier
+                ++sgi;
+            }
+            if (((gneed >> jg) & 1u) == 0u) continue;
+            skip16 = ((gmine >> jg) & 1u) ? prune_mask(v0) : 0xffffu;
             const int gb = grp % 3;
             if (lane == 0 && (skip16 & 0xffffu) != 0xffffu) atomicOr(&grp_need[gb], ~skip16 & 0xffffu);
             __syncthreads();
             const uint32_t need = grp_need[gb];
             if (threadIdx.x == 0) grp_need[(grp + 2) % 3] = 0u;  // ordered by the next group's barrier
+            ++grp;
             if (need == 0u) continue;
             auto load_period = [&](int vp, char (*dst)[TILE * RB]) {
 #pragma unroll
@@ -661,7 +737,7 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
 // A pruned screen: one split over whole super-tiles, with every bound array.
 bool pruned_args_ok(const ScreenArgs &a) {
     return a.splits == 1 && a.col_chunk >= a.n_pad && a.tile_c && a.tile_r && a.sup_c &&
-           a.sup_r && a.nzq && a.n_pad % SCREEN_SUPER_ROWS == 0 &&
+           a.sup_r && a.grp_c && a.grp_r && a.nzq && a.n_pad % SCREEN_SUPER_ROWS == 0 &&
            a.n_pad / SCREEN_SUPER_ROWS <= SCREEN_SUPER_MAX;
 }
 
