@@ -233,11 +233,11 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
     // bit each), and their list in scan order.
     __shared__ uint32_t sup_keep[PRUNE ? SCREEN_SUPER_MAX / 32 : 1];
     __shared__ uint16_t sup_list[PRUNE ? SCREEN_SUPER_MAX : 1];
-    // Pruned scans: per group of 16 tiles the tiles some wave needs (one bit
-    // each, OR over the waves), and per super-tile its groups some wave needs;
-    // three buffers of each, used in turn.
-    __shared__ uint32_t grp_need[3];
-    __shared__ uint32_t sup_grp[3];
+    // Pruned scans: per group of a quad (four groups of 16 tiles) the tiles
+    // some wave needs (one bit each, OR over the waves; three buffers used in
+    // turn), and each wave's own skip bits.
+    __shared__ uint32_t need_q[PRUNE ? 3 : 1][4];
+    __shared__ uint32_t my_skip[PRUNE ? 4 : 1][4];
 
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
@@ -263,10 +263,7 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
         rot_t = ((start % SCREEN_SUPER_ROWS) / TILE) & ~(SCREEN_GROUP - 1);  // whole groups
         len = SCREEN_SUPER_ROWS;  // the first phase
         if (threadIdx.x < SCREEN_SUPER_MAX / 32) sup_keep[threadIdx.x] = 0u;
-        if (threadIdx.x < 3) {
-            grp_need[threadIdx.x] = 0u;
-            sup_grp[threadIdx.x] = 0u;
-        }
+        if (threadIdx.x < 12) need_q[threadIdx.x / 4][threadIdx.x % 4] = 0u;
     }
     auto phys = [&](int v) -> int {
         if constexpr (!PRUNE) {
@@ -338,6 +335,7 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
     // decreases: the kept keys, and the certificate's premise that every
     // non-candidate screened at or above T', are unchanged.
     float nzq[4], aq[4];
+    const float margin_nx = (float)(1.0e-6 * a.nx_max);
     uint32_t skip16 = 0;
     if constexpr (PRUNE) {
 #pragma unroll
@@ -348,52 +346,62 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
                             1.0e-6 * 1.02 * a.nx_max);
         }
     }
-    // Skip bits of 16 balls (centre rows `cen`, radii `radius`): ball_row(j)
-    // and ball_rad(j) give the centre row and radius of ball j < 16 (a
-    // radius of +inf for a ball past the range: never skipped).
-    auto ball_mask = [&](auto ball_row, auto ball_rad) -> uint32_t {
+    // Skip bits of 16 balls: ball_row(j) and ball_rad(j) give the centre row
+    // and radius of ball j < 16 (a radius of +inf for a ball past the range:
+    // never skipped).  The loads (ball_load) are apart from the test
+    // (ball_test), so that several sets of balls can have theirs in flight
+    // together.
+    struct Balls {
         typename Op::frag_t af[KSTEPS];
+        float rad[4];  // this lane's balls 4g + i
+    };
+    auto ball_load = [&](auto ball_row, auto ball_rad, Balls &b) {
         const char *crow = ball_row(r16);
 #pragma unroll
-        for (int s = 0; s < KSTEPS; ++s) af[s] = Op::load(crow + g * KSTEPS * Op::BPS + s * Op::BPS);
+        for (int s = 0; s < KSTEPS; ++s)
+            b.af[s] = Op::load(crow + g * KSTEPS * Op::BPS + s * Op::BPS);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) b.rad[i] = ball_rad(4 * g + i);
+    };
+    auto ball_test = [&](const Balls &b) -> uint32_t {
         f32x4 ac[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             ac[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int s = 0; s < KSTEPS; ++s) ac[t] = Op::mfma(af[s], bq[t][s], ac[t]);
+            for (int s = 0; s < KSTEPS; ++s) ac[t] = Op::mfma(b.af[s], bq[t][s], ac[t]);
         }
-        // this lane holds centroid rows 4g + i of the group
-        float rad[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) rad[i] = ball_rad(4 * g + i);
         uint32_t skip = 0xffffu;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int i = 0; i < 4; ++i) {
+            uint64_t all = ~0ull;  // lanes whose query (of any query tile) can skip ball 4g + i
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                bool pr;
-                if (thr[t] == -INFINITY) {
-                    pr = true;  // padding query
-                } else {
-                    const float L = ac[t][i] + nzq[t] - aq[t];
-                    const float dl = (L > 0.0f) ? sqrtf(L) - rad[i] : -1.0f;
-                    const float d2 = dl * dl;
-                    pr = dl > 0.0f &&
-                         d2 - nzq[t] - aq[t] - 1.0e-5f * (d2 + nzq[t]) - (float)(1.0e-6 * a.nx_max) >
-                             thr[t];
-                }
-                const uint64_t m = __ballot(pr);
-#pragma unroll
-                for (int gg = 0; gg < 4; ++gg)
-                    if (((m >> (16 * gg)) & 0xffffull) != 0xffffull) skip &= ~(1u << (4 * gg + i));
+            for (int t = 0; t < 4; ++t) {
+                // branch free; the square root is the hardware one (within
+                // 1 ulp), whose error the margins cover many times over.  A
+                // non-positive L gives dl <= 0: never skipped.
+                const float L = ac[t][i] + nzq[t] - aq[t];
+                const float dl = __builtin_amdgcn_sqrtf(fmaxf(L, 0.0f)) - b.rad[i];
+                const float d2 = dl * dl;
+                const bool pr = thr[t] == -INFINITY ||  // padding query
+                                (dl > 0.0f &&
+                                 d2 - nzq[t] - aq[t] - 1.0e-5f * (d2 + nzq[t]) - margin_nx > thr[t]);
+                all &= __ballot(pr);
             }
+#pragma unroll
+            for (int gg = 0; gg < 4; ++gg)
+                if (((all >> (16 * gg)) & 0xffffull) != 0xffffull) skip &= ~(1u << (4 * gg + i));
         }
         return skip;
     };
+    auto ball_mask = [&](auto ball_row, auto ball_rad) -> uint32_t {
+        Balls b;
+        ball_load(ball_row, ball_rad, b);
+        return ball_test(b);
+    };
     // The 16 tiles at virtual positions v0 + j * TILE.
-    auto prune_mask = [&](int v0) -> uint32_t {
-        return ball_mask(
+    auto prune_load = [&](int v0, Balls &b) {
+        ball_load(
             [&](int j) {
                 const int vr = v0 + j * TILE;
                 return (const char *)a.tile_c + (int64_t)(phys(vr < len ? vr : 0) / TILE) * RB;
@@ -401,7 +409,13 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
             [&](int j) {
                 const int vj = v0 + j * TILE;
                 return vj < len ? a.tile_r[phys(vj) / TILE] : INFINITY;
-            });
+            },
+            b);
+    };
+    auto prune_mask = [&](int v0) -> uint32_t {
+        Balls b;
+        prune_load(v0, b);
+        return ball_test(b);
     };
 
     // Counts of the four sub-pools of wave query (t, rl).
@@ -564,21 +578,21 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
         __syncthreads();
     };
 
-    // Pruned scans go a super-tile, then a group of 16 tiles at a time.  At a
-    // super-tile's start every wave tests its 16 group balls and the
-    // workgroup ORs the groups some wave needs (one barrier); a group no wave
-    // needs is passed over.  In a needed group every wave that needs it
-    // computes its skip bits for the group's tiles, the workgroup ORs the
-    // tiles some wave needs, and only those are loaded; a group whose tiles
-    // no wave needs costs one barrier.  Within a group the periods run as in
-    // the full scan, the next period's needed tiles loading while the current
-    // one is screened.  Super-tiles start at multiples of SCREEN_SUPER_ROWS
-    // and groups at multiples of SCREEN_GROUP_ROWS (virtual and physical
-    // positions alike), so the group balls line up with the scan.
-    int grp = 0;  // groups taken, for the grp_need buffers
-    int sgi = 0;  // super-tiles entered, for the sup_grp buffers
+    // Pruned scans go a super-tile, then a quad of four groups, then a group
+    // of 16 tiles at a time.  Super-tiles start at multiples of
+    // SCREEN_SUPER_ROWS and groups at multiples of SCREEN_GROUP_ROWS (virtual
+    // and physical positions alike), so the group balls line up with the
+    // scan.  At a super-tile's start every wave tests its 16 group balls.  At
+    // a quad's start every wave computes the skip bits of its needed groups'
+    // tiles, the four groups' centre rows and radii in flight together, and
+    // the workgroup ORs the tiles some wave needs per group (one barrier per
+    // quad); only those are loaded, and a group no wave needs costs nothing.
+    // Within a group the periods run as in the full scan, the next period's
+    // needed tiles loading while the current one is screened.
+    int qc = 0;  // quads entered, for the need_q buffers
     auto run_groups = [&](int v_begin) {
-        uint32_t gneed = 0u, gmine = 0u;
+        uint32_t gmine = 0u;
+        int qb = 0;
         for (int v0 = v_begin; v0 < len; v0 += SCREEN_GROUP_ROWS) {
             const int jg = (v0 / SCREEN_GROUP_ROWS) & (SCREEN_GROUP - 1);
             if (jg == 0) {
@@ -593,22 +607,30 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
                                                SCREEN_GROUP_ROWS];
                             }) &
                         0xffffu;
-                const int sb = sgi % 3;
-                if (lane == 0 && gmine != 0u) atomicOr(&sup_grp[sb], gmine);
-                __syncthreads();
-                gneed = sup_grp[sb];
-                if (threadIdx.x == 0) sup_grp[(sgi + 2) % 3] = 0u;  // ordered by the next one's barrier
-                ++sgi;
             }
-            if (((gneed >> jg) & 1u) == 0u) continue;
-            skip16 = ((gmine >> jg) & 1u) ? prune_mask(v0) : 0xffffu;
-            const int gb = grp % 3;
-            if (lane == 0 && (skip16 & 0xffffu) != 0xffffu) atomicOr(&grp_need[gb], ~skip16 & 0xffffu);
-            __syncthreads();
-            const uint32_t need = grp_need[gb];
-            if (threadIdx.x == 0) grp_need[(grp + 2) % 3] = 0u;  // ordered by the next group's barrier
-            ++grp;
+            if ((jg & 3) == 0) {
+                qb = qc % 3;
+                Balls b[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if ((gmine >> (jg + u)) & 1u) prune_load(v0 + u * SCREEN_GROUP_ROWS, b[u]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t sk = ((gmine >> (jg + u)) & 1u) ? ball_test(b[u]) : 0xffffu;
+                    if (lane == 0) {
+                        my_skip[wave][u] = sk;
+                        if (sk != 0xffffu) atomicOr(&need_q[qb][u], ~sk & 0xffffu);
+                    }
+                }
+                __syncthreads();
+                // the buffer of two quads ago: read before this barrier, next
+                // written after the next quad's barrier
+                if (threadIdx.x < 4) need_q[(qc + 2) % 3][threadIdx.x] = 0u;
+                ++qc;
+            }
+            const uint32_t need = need_q[qb][jg & 3];
             if (need == 0u) continue;
+            skip16 = my_skip[wave][jg & 3];
             auto load_period = [&](int vp, char (*dst)[TILE * RB]) {
 #pragma unroll
                 for (int j = 0; j < TPB; ++j) {
