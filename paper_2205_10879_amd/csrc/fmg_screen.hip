@@ -348,9 +348,9 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
     }
     // Skip bits of 16 balls: ball_row(j) and ball_rad(j) give the centre row
     // and radius of ball j < 16 (a radius of +inf for a ball past the range:
-    // never skipped).  The loads (ball_load) are apart from the test
-    // (ball_test), so that several sets of balls can have theirs in flight
-    // together.
+    // never skipped).  The test is branch free (bitwise logic on the
+    // comparisons, the hardware square root), which made it several times
+    // cheaper than with short-circuit conditions.
     struct Balls {
         typename Op::frag_t af[KSTEPS];
         float rad[4];  // this lane's balls 4g + i
@@ -372,6 +372,9 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
             for (int s = 0; s < KSTEPS; ++s) ac[t] = Op::mfma(b.af[s], bq[t][s], ac[t]);
         }
         uint32_t skip = 0xffffu;
+        bool pad[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) pad[t] = thr[t] == -INFINITY;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             uint64_t all = ~0ull;  // lanes whose query (of any query tile) can skip ball 4g + i
@@ -383,9 +386,9 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
                 const float L = ac[t][i] + nzq[t] - aq[t];
                 const float dl = __builtin_amdgcn_sqrtf(fmaxf(L, 0.0f)) - b.rad[i];
                 const float d2 = dl * dl;
-                const bool pr = thr[t] == -INFINITY ||  // padding query
-                                (dl > 0.0f &&
-                                 d2 - nzq[t] - aq[t] - 1.0e-5f * (d2 + nzq[t]) - margin_nx > thr[t]);
+                const bool pr = pad[t] |  // padding query
+                                ((dl > 0.0f) &
+                                 (d2 - nzq[t] - aq[t] - 1.0e-5f * (d2 + nzq[t]) - margin_nx > thr[t]));
                 all &= __ballot(pr);
             }
 #pragma unroll
@@ -584,9 +587,10 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
     // and physical positions alike), so the group balls line up with the
     // scan.  At a super-tile's start every wave tests its 16 group balls.  At
     // a quad's start every wave computes the skip bits of its needed groups'
-    // tiles, the four groups' centre rows and radii in flight together, and
-    // the workgroup ORs the tiles some wave needs per group (one barrier per
-    // quad); only those are loaded, and a group no wave needs costs nothing.
+    // tiles and the workgroup ORs the tiles some wave needs per group (one
+    // barrier per quad); only those are loaded, and a group no wave needs
+    // costs nothing.  (Loading the four groups' centre rows and radii
+    // together, ahead of their tests, spilled registers and was slower.)
     // Within a group the periods run as in the full scan, the next period's
     // needed tiles loading while the current one is screened.
     int qc = 0;  // quads entered, for the need_q buffers
@@ -610,13 +614,10 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
             }
             if ((jg & 3) == 0) {
                 qb = qc % 3;
-                Balls b[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if ((gmine >> (jg + u)) & 1u) prune_load(v0 + u * SCREEN_GROUP_ROWS, b[u]);
-#pragma unroll
+#pragma unroll 1
                 for (int u = 0; u < 4; ++u) {
-                    const uint32_t sk = ((gmine >> (jg + u)) & 1u) ? ball_test(b[u]) : 0xffffu;
+                    const uint32_t sk =
+                        ((gmine >> (jg + u)) & 1u) ? prune_mask(v0 + u * SCREEN_GROUP_ROWS) : 0xffffu;
                     if (lane == 0) {
                         my_skip[wave][u] = sk;
                         if (sk != 0xffffu) atomicOr(&need_q[qb][u], ~sk & 0xffffu);
