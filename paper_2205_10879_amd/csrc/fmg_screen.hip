@@ -107,6 +107,25 @@ __device__ __forceinline__ int wave_incl_scan(int v, int lane) {
     return v;
 }
 
+// The bin of a 256-bin LDS histogram that holds the need-th smallest item
+// (1 <= need <= total): *before = items in lower bins, *inbin = items in it.
+__device__ __forceinline__ int hist_find(const uint32_t *__restrict__ hist, int need, int lane,
+                                         int *before_out, int *inbin_out) {
+    const uint4 h = ((const uint4 *)hist)[lane];
+    const int own = (int)(h.x + h.y + h.z + h.w);
+    const int incl = wave_incl_scan(own, lane);
+    const int excl = incl - own;
+    const bool mine = excl < need && need <= incl;
+    int bin = 3, before = excl + (int)(h.x + h.y + h.z), inbin = (int)h.w;
+    if (excl + (int)(h.x + h.y + h.z) >= need) { bin = 2; before = excl + (int)(h.x + h.y); inbin = (int)h.z; }
+    if (excl + (int)(h.x + h.y) >= need) { bin = 1; before = excl + (int)h.x; inbin = (int)h.y; }
+    if (excl + (int)h.x >= need) { bin = 0; before = excl; inbin = (int)h.x; }
+    const int L = __ffsll((long long)__ballot(mine)) - 1;
+    *before_out = __builtin_amdgcn_readlane(before, L);
+    *inbin_out = __builtin_amdgcn_readlane(inbin, L);
+    return L * 4 + __builtin_amdgcn_readlane(bin, L);
+}
+
 // Radix selection (8-bit digits, most significant first) of the c-th
 // smallest of the wave's 64*PE keys (~0 marks an empty slot).  Returns a bound
 // B such that exactly the c smallest keys satisfy key <= B, or ~0 when fewer
@@ -130,19 +149,8 @@ __device__ __forceinline__ uint64_t radix_kth(const uint64_t (&key)[PE], int c,
             if (in) atomicAdd(&hist[(uint32_t)(key[e] >> shift) & 255u], 1u);
         }
         wave_lds_sync();
-        const uint4 h = ((const uint4 *)hist)[lane];
-        const int own = (int)(h.x + h.y + h.z + h.w);
-        const int incl = wave_incl_scan(own, lane);
-        const int excl = incl - own;
-        const bool mine = excl < need && need <= incl;
-        int bin = 3, before = excl + (int)(h.x + h.y + h.z), inbin = (int)h.w;
-        if (excl + (int)(h.x + h.y + h.z) >= need) { bin = 2; before = excl + (int)(h.x + h.y); inbin = (int)h.z; }
-        if (excl + (int)(h.x + h.y) >= need) { bin = 1; before = excl + (int)h.x; inbin = (int)h.y; }
-        if (excl + (int)h.x >= need) { bin = 0; before = excl; inbin = (int)h.x; }
-        const int L = __ffsll((long long)__ballot(mine)) - 1;
-        const int digit = L * 4 + __builtin_amdgcn_readlane(bin, L);
-        const int cb = __builtin_amdgcn_readlane(before, L);
-        const int cin = __builtin_amdgcn_readlane(inbin, L);
+        int cb, cin;
+        const int digit = hist_find(hist, need, lane, &cb, &cin);
         prefix |= (uint64_t)digit << shift;
         need -= cb;
         wave_lds_sync();
@@ -151,7 +159,56 @@ __device__ __forceinline__ uint64_t radix_kth(const uint64_t (&key)[PE], int c,
     return prefix;
 }
 
-// Keep the c smallest entries of one query's pool (four sub-pools of SUB
+// A bound for the selections during the scan, in one histogram pass: the
+// keys' value parts (key >> 32) are binned in 256 bins of 2^sh values from
+// the smallest one (sh the least shift that puts the largest one in bin 255),
+// and the bound takes every key up to the end of the bin that holds the c-th
+// smallest.  At least c keys (and so the c smallest) satisfy key <= bound; a
+// few more may, which only keeps the threshold a little higher until the next
+// selection (the final selection is exact).  Should more than c + 32 keys
+// fall at or below it (values crowded into one bin), the exact radix
+// selection decides instead.  ~0 when at most c keys are present.
+template <int PE>
+__device__ __forceinline__ uint64_t bin_bound(const uint64_t (&key)[PE], int c,
+                                              uint32_t *__restrict__ hist, int lane) {
+    int valid = 0;
+    uint32_t lo = 0xffffffffu, hi = 0u;
+#pragma unroll
+    for (int e = 0; e < PE; ++e) {
+        const bool v = key[e] != ~0ull;
+        valid += __popcll(__ballot(v));
+        const uint32_t u = (uint32_t)(key[e] >> 32);
+        if (v) {
+            lo = u < lo ? u : lo;
+            hi = u > hi ? u : hi;
+        }
+    }
+    if (valid <= c) return ~0ull;
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        const uint32_t ol = (uint32_t)__shfl_xor((int)lo, m), oh = (uint32_t)__shfl_xor((int)hi, m);
+        lo = ol < lo ? ol : lo;
+        hi = oh > hi ? oh : hi;
+    }
+    const uint32_t span = hi - lo;
+    const int bits = span == 0u ? 0 : 32 - __clz((int)span);
+    const int sh = bits > 8 ? bits - 8 : 0;
+    ((uint4 *)hist)[lane] = uint4{0u, 0u, 0u, 0u};
+    wave_lds_sync();
+#pragma unroll
+    for (int e = 0; e < PE; ++e)
+        if (key[e] != ~0ull) atomicAdd(&hist[((uint32_t)(key[e] >> 32) - lo) >> sh], 1u);
+    wave_lds_sync();
+    int before, inbin;
+    const int b = hist_find(hist, c, lane, &before, &inbin);
+    wave_lds_sync();
+    if (before + inbin > c + 32) return radix_kth<PE>(key, c, hist, lane);
+    const uint64_t top = (uint64_t)lo + ((uint64_t)(b + 1) << sh) - 1ull;
+    return ((top < 0xffffffffull ? top : 0xffffffffull) << 32) | 0xffffffffull;
+}
+
+// Keep the c smallest entries (final == true; during the scan at least the c
+// smallest, see bin_bound) of one query's pool (four sub-pools of SUB
 // entries, counts cg[0..3]).  Entries of the query's own index (leave-one-out)
 // and of padding candidates (index >= n) are dropped here: the screen appends
 // without checking them.  The kept entries go back to the sub-pools round
@@ -181,7 +238,7 @@ __device__ __forceinline__ int select_pool(uint64_t *__restrict__ qpool, const i
             if (p != self && p < n) key[e] = raw_to_key(r);
         }
     }
-    const uint64_t bound = radix_kth<PE>(key, c, hist, lane);
+    const uint64_t bound = final ? radix_kth<PE>(key, c, hist, lane) : bin_bound<PE>(key, c, hist, lane);
     const uint64_t lt = (1ull << lane) - 1ull;
     int base = 0;
     uint64_t mx = 0;
