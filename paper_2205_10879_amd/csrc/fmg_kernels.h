@@ -15,8 +15,13 @@ constexpr int SCREEN_TILE = 64;
 // Queries per screen workgroup (4 waves x 64 queries).
 constexpr int SCREEN_QPB = 256;
 // Pool entries per query in the screen (candidate keys awaiting selection),
-// and the largest number of candidates kept per query and split.
+// and the largest number of candidates kept per query and split.  Screens
+// keeping at most SCREEN_CAP_SMALL_C candidates use pools of SCREEN_CAP_SMALL
+// entries (selections come more often, each over fewer entries); pool
+// buffers are sized for SCREEN_CAP.
 constexpr int SCREEN_CAP = 512;
+constexpr int SCREEN_CAP_SMALL = 256;
+constexpr int SCREEN_CAP_SMALL_C = 112;
 constexpr int SCREEN_CMAX = 128;
 // Pruned screens group tiles into super-tiles of SCREEN_SUPER tiles (a
 // pruned model pads its candidate rows to whole super-tiles) and keep at

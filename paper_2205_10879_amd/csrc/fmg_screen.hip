@@ -276,7 +276,7 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
     constexpr int LDI = CH / 4;               // LDS-DMA loads per wave per tile
     constexpr int TPB = FMG_SCREEN_TPB;       // tiles per barrier period
     constexpr int SUB = CAP / 4;              // sub-pool per lane group
-    constexpr int TRIG = SUB - 16 * TPB;      // select when a sub-pool exceeds this
+    constexpr int TRIG = SUB - 16;            // select when a sub-pool exceeds this (after a tile)
     constexpr int PE = CAP / 64;
     static_assert(CH % 4 == 0, "tile load split");
     // Candidate tiles: 64 rows x RB bytes, unpadded; 16-byte chunk c of row r
@@ -629,10 +629,11 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
         }
 #pragma unroll 1
         for (int j = 0; j < TPB; ++j)
-            if (v + j * TILE < len)
+            if (v + j * TILE < len) {
                 screen_tile(phys(v + j * TILE), cur[j], ((v >> 6) + j) & 15);
-        if (__ballot(cnt[0] > TRIG || cnt[1] > TRIG || cnt[2] > TRIG || cnt[3] > TRIG) != 0)
-            flush_full();
+                if (__ballot(cnt[0] > TRIG || cnt[1] > TRIG || cnt[2] > TRIG || cnt[3] > TRIG) != 0)
+                    flush_full();
+            }
         // the next period's tiles must have landed in LDS before any wave reads them
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
@@ -707,10 +708,11 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
                 if (p + 1 < 16 / TPB) load_period(vp + TPB * TILE, nxt);
 #pragma unroll 1
                 for (int j = 0; j < TPB; ++j)
-                    if (vp + j * TILE < len)
+                    if (vp + j * TILE < len) {
                         screen_tile(phys(vp + j * TILE), cur[j], ((vp >> 6) + j) & 15);
-                if (__ballot(cnt[0] > TRIG || cnt[1] > TRIG || cnt[2] > TRIG || cnt[3] > TRIG) != 0)
-                    flush_full();
+                        if (__ballot(cnt[0] > TRIG || cnt[1] > TRIG || cnt[2] > TRIG || cnt[3] > TRIG) != 0)
+                            flush_full();
+                    }
                 asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
                 __syncthreads();
             }
@@ -821,19 +823,18 @@ bool pruned_args_ok(const ScreenArgs &a) {
            a.n_pad / SCREEN_SUPER_ROWS <= SCREEN_SUPER_MAX;
 }
 
-hipError_t launch_screen(const ScreenGeom &g, const ScreenArgs &a, hipStream_t s) {
+template <int CAP>
+hipError_t launch_screen_cap(const ScreenGeom &g, const ScreenArgs &a, hipStream_t s) {
     dim3 grid((unsigned)(a.m_pad / SCREEN_QPB), (unsigned)a.splits);
-    if (a.c < 1 || a.c > SCREEN_CMAX) return hipErrorInvalidValue;
 #define FMG_SCREEN_LAUNCH(OP, KS) \
-    hipLaunchKernelGGL((screen_kernel<OP, KS, SCREEN_CAP, false>), grid, dim3(256), 0, s, a)
+    hipLaunchKernelGGL((screen_kernel<OP, KS, CAP, false>), grid, dim3(256), 0, s, a)
 #define FMG_SCREEN_LAUNCH_PRUNED(OP, KS) \
-    hipLaunchKernelGGL((screen_kernel<OP, KS, SCREEN_CAP, true>), grid, dim3(256), 0, s, a)
+    hipLaunchKernelGGL((screen_kernel<OP, KS, CAP, true>), grid, dim3(256), 0, s, a)
     if (g.mode == SCREEN_BF16) {
         if (g.ksteps != 2) return hipErrorInvalidValue;
         if (a.prune) {
             if (!pruned_args_ok(a)) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((screen_kernel<OpBF16, 2, SCREEN_CAP, true>), grid, dim3(256), 0, s,
-                               a);
+            FMG_SCREEN_LAUNCH_PRUNED(OpBF16, 2);
         } else {
             FMG_SCREEN_LAUNCH(OpBF16, 2);
         }
@@ -858,6 +859,12 @@ hipError_t launch_screen(const ScreenGeom &g, const ScreenArgs &a, hipStream_t s
 #undef FMG_SCREEN_LAUNCH
 #undef FMG_SCREEN_LAUNCH_PRUNED
     return hipGetLastError();
+}
+
+hipError_t launch_screen(const ScreenGeom &g, const ScreenArgs &a, hipStream_t s) {
+    if (a.c < 1 || a.c > SCREEN_CMAX) return hipErrorInvalidValue;
+    return a.c <= SCREEN_CAP_SMALL_C ? launch_screen_cap<SCREEN_CAP_SMALL>(g, a, s)
+                                     : launch_screen_cap<SCREEN_CAP>(g, a, s);
 }
 
 }  // namespace fmg
