@@ -148,7 +148,7 @@ def main():
     screen_ms = avg("build_screen_ms")
     flops = 2.0 * args.n * args.n * w.X.shape[1]
     achieved_tflops = flops / (screen_ms / 1000.0) / 1e12
-    roofline = {"bound": "mfma", "kernel": "screen_kernel<OpBF16,2,512,true> (build, pruned)",
+    roofline = {"bound": "mfma", "kernel": "screen_kernel<OpBF16,2,256,true> (build, pruned)",
                 "achieved": round(achieved_tflops, 2), "peak": PEAK_BF16_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_BF16_TFLOPS, 4),
                 "traffic": screen_traffic(args.n), "avg_launch_ms": round(screen_ms, 3),
