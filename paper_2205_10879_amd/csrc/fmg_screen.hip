@@ -56,6 +56,23 @@ struct OpF32 {
 
 constexpr int TILE = SCREEN_TILE;
 
+// Four 16-byte LDS reads at addr, addr + OFF, addr + 2 OFF, addr + 3 OFF,
+// waited for inside the asm block (so no result is used, and no register is
+// reused, before its read has landed).
+template <int OFF>
+__device__ __forceinline__ void lds_read4(uint32_t addr, uint4 &r0, uint4 &r1, uint4 &r2,
+                                          uint4 &r3) {
+    asm volatile(
+        "ds_read_b128 %0, %4\n\t"
+        "ds_read_b128 %1, %4 offset:%5\n\t"
+        "ds_read_b128 %2, %4 offset:%6\n\t"
+        "ds_read_b128 %3, %4 offset:%7\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(r0), "=&v"(r1), "=&v"(r2), "=&v"(r3)
+        : "v"(addr), "i"(OFF), "i"(2 * OFF), "i"(3 * OFF)
+        : "memory");
+}
+
 // Pool entries hold the raw pair (index << 32 | float bits of S'); selection
 // works on keys (orderable value << 32 | index), which order by (S', index).
 __device__ __forceinline__ uint64_t raw_entry(float v, uint32_t p) {
@@ -286,15 +303,6 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
     __shared__ __align__(16) char ringB[TPB][TILE * RB];
     __shared__ __align__(16) uint32_t hist_all[4][256];
     __shared__ __align__(16) uint64_t stage_all[4][SCREEN_CMAX];
-    // Pruned scans: super-tiles some wave of the workgroup cannot skip (one
-    // bit each), and their list in scan order.
-    __shared__ uint32_t sup_keep[PRUNE ? SCREEN_SUPER_MAX / 32 : 1];
-    __shared__ uint16_t sup_list[PRUNE ? SCREEN_SUPER_MAX : 1];
-    // Pruned scans: per group of a quad (four groups of 16 tiles) the tiles
-    // some wave needs (one bit each, OR over the waves; three buffers used in
-    // turn), and each wave's own skip bits.
-    __shared__ uint32_t need_q[PRUNE ? 3 : 1][4];
-    __shared__ uint32_t my_skip[PRUNE ? 4 : 1][4];
 
     const int lane = lane_id();
     const int wave = threadIdx.x >> 6;
@@ -303,35 +311,21 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
     const int split = blockIdx.y;
     const int cb = split * (int)a.col_chunk;
     const int ce = (cb + a.col_chunk < a.n_pad) ? cb + (int)a.col_chunk : (int)a.n_pad;
-    // Columns are visited at virtual positions v = 0, TILE, ... < len.
-    // Without pruning: in order.  With pruning (one split, n_pad a multiple
-    // of SCREEN_SUPER_ROWS) in two phases: first this workgroup's own
-    // super-tile, starting at its own rows (the self-join's rows and columns
-    // share one order; a prediction's start column comes from rot_tab) and
-    // wrapping within the super-tile; then, in order after it, the other
-    // super-tiles that some wave cannot skip with its thresholds at the end
-    // of the first phase (sup_list).
-    int len = ce - cb;
-    int own_sup = 0, rot_t = 0;
+    // Without pruning the workgroup visits the columns of its range in order,
+    // every wave screening every tile.  With pruning (one split, n_pad a
+    // multiple of SCREEN_SUPER_ROWS) every wave scans on its own, in two
+    // phases: first the workgroup's own super-tile, starting at its own group
+    // (the self-join's rows and columns share one order; a prediction's start
+    // column comes from rot_tab) and wrapping within the super-tile; then the
+    // other super-tiles in order after it, wrapping.
+    const int len = ce - cb;
+    int own_sup = 0, rot_g = 0;
     if constexpr (PRUNE) {
         const int start = a.rot_tab ? (int)(a.rot_tab[blockIdx.x] % (ce - cb))
                                     : (int)(((int64_t)blockIdx.x * SCREEN_QPB) % (ce - cb));
         own_sup = start / SCREEN_SUPER_ROWS;
-        rot_t = ((start % SCREEN_SUPER_ROWS) / TILE) & ~(SCREEN_GROUP - 1);  // whole groups
-        len = SCREEN_SUPER_ROWS;  // the first phase
-        if (threadIdx.x < SCREEN_SUPER_MAX / 32) sup_keep[threadIdx.x] = 0u;
-        if (threadIdx.x < 12) need_q[threadIdx.x / 4][threadIdx.x % 4] = 0u;
+        rot_g = (start % SCREEN_SUPER_ROWS) / SCREEN_GROUP_ROWS;
     }
-    auto phys = [&](int v) -> int {
-        if constexpr (!PRUNE) {
-            return cb + v;
-        } else {
-            const int t = v / TILE;
-            if (t < SCREEN_SUPER) return (own_sup * SCREEN_SUPER + ((rot_t + t) & (SCREEN_SUPER - 1))) * TILE;
-            return ((int)sup_list[(t - SCREEN_SUPER) / SCREEN_SUPER] * SCREEN_SUPER +
-                    (t & (SCREEN_SUPER - 1))) * TILE;
-        }
-    };
     const int n_real = (int)a.n, m_real = (int)a.m;
     const char *__restrict__ Pb = (const char *)a.P;
     uint32_t *hist = hist_all[wave];
@@ -358,21 +352,24 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
         cnt[t] = 0;
     }
 
-    // Tile loads go straight from global memory to LDS (global_load_lds):
-    // wave w fills slots [w*LDI*64, (w+1)*LDI*64), lane l of load j writes slot
-    // (w*LDI + j)*64 + l, i.e. row slot/CH, chunk position slot%CH.
-    auto load_tile = [&](int col0, char *dst) {
+    // Tile loads go straight from global memory to LDS (global_load_lds).
+    // Loads j0 .. j0 + nj - 1 of a tile's CH (lane l of load j writes slot
+    // j*64 + l, i.e. row slot/CH, chunk position slot%CH): a full scan's waves
+    // share each tile (wave w issues loads w*LDI ..), a pruned scan's wave
+    // loads its own tiles whole.
+    auto load_tile_part = [&](int col0, char *dst, int j0, int nj) __attribute__((always_inline)) {
 #pragma unroll
-        for (int j = 0; j < LDI; ++j) {
-            const int slot = (wave * LDI + j) * 64 + lane;
+        for (int j = j0; j < j0 + nj; ++j) {
+            const int slot = j * 64 + lane;
             const int r = slot / CH, pc = slot % CH;
             const int c = pc ^ (r & SWZ);
             const char *src = Pb + (size_t)(col0 + r) * RB + c * 16;
             __builtin_amdgcn_global_load_lds(
-                (const void *)src,
-                (__attribute__((address_space(3))) void *)(dst + (wave * LDI + j) * 1024), 16, 0, 0);
+                (const void *)src, (__attribute__((address_space(3))) void *)(dst + j * 1024), 16, 0,
+                0);
         }
     };
+    auto load_tile = [&](int col0, char *dst) { load_tile_part(col0, dst, wave * LDI, LDI); };
     // This lane's fragment offsets inside a tile (row r16 of each 16-row block).
     int frag_off[KSTEPS];
 #pragma unroll
@@ -393,7 +390,6 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
     // non-candidate screened at or above T', are unchanged.
     float nzq[4], aq[4];
     const float margin_nx = (float)(1.0e-6 * a.nx_max);
-    uint32_t skip16 = 0;
     if constexpr (PRUNE) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -412,7 +408,7 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
         typename Op::frag_t af[KSTEPS];
         float rad[4];  // this lane's balls 4g + i
     };
-    auto ball_load = [&](auto ball_row, auto ball_rad, Balls &b) {
+    auto ball_load = [&](auto ball_row, auto ball_rad, Balls &b) __attribute__((always_inline)) {
         const char *crow = ball_row(r16);
 #pragma unroll
         for (int s = 0; s < KSTEPS; ++s)
@@ -420,7 +416,7 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
 #pragma unroll
         for (int i = 0; i < 4; ++i) b.rad[i] = ball_rad(4 * g + i);
     };
-    auto ball_test = [&](const Balls &b) -> uint32_t {
+    auto ball_test = [&](const Balls &b) __attribute__((always_inline)) -> uint32_t  {
         f32x4 ac[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -454,28 +450,20 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
         }
         return skip;
     };
-    auto ball_mask = [&](auto ball_row, auto ball_rad) -> uint32_t {
+    auto ball_mask = [&](auto ball_row, auto ball_rad) __attribute__((always_inline)) -> uint32_t  {
         Balls b;
         ball_load(ball_row, ball_rad, b);
         return ball_test(b);
     };
-    // The 16 tiles at virtual positions v0 + j * TILE.
-    auto prune_load = [&](int v0, Balls &b) {
-        ball_load(
-            [&](int j) {
-                const int vr = v0 + j * TILE;
-                return (const char *)a.tile_c + (int64_t)(phys(vr < len ? vr : 0) / TILE) * RB;
-            },
-            [&](int j) {
-                const int vj = v0 + j * TILE;
-                return vj < len ? a.tile_r[phys(vj) / TILE] : INFINITY;
-            },
-            b);
+    // Skip bits of the 16 tiles t0 .. t0 + 15, of the 16 groups g0 .. g0 + 15
+    // (a super-tile's), and of the 16 super-tiles s(0) .. s(15).
+    auto tile_mask = [&](int t0) __attribute__((always_inline)) -> uint32_t  {
+        return ball_mask([&](int j) { return (const char *)a.tile_c + (int64_t)(t0 + j) * RB; },
+                         [&](int j) { return a.tile_r[t0 + j]; });
     };
-    auto prune_mask = [&](int v0) -> uint32_t {
-        Balls b;
-        prune_load(v0, b);
-        return ball_test(b);
+    auto group_mask = [&](int g0) __attribute__((always_inline)) -> uint32_t  {
+        return ball_mask([&](int j) { return (const char *)a.grp_c + (int64_t)(g0 + j) * RB; },
+                         [&](int j) { return a.grp_r[g0 + j]; });
     };
 
     // Counts of the four sub-pools of wave query (t, rl).
@@ -486,7 +474,7 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
     };
 
     // Select in every query of the wave with a sub-pool above the trigger.
-    auto flush_full = [&]() {
+    auto flush_full = [&]() __attribute__((always_inline)) {
         for (int t = 0; t < 4; ++t) {
             const int ct = t == 0 ? cnt[0] : t == 1 ? cnt[1] : t == 2 ? cnt[2] : cnt[3];
             const uint64_t m = __ballot(ct > TRIG);
@@ -516,10 +504,7 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
     };
 
     // MFMA screen of one tile and candidate selection.
-    auto screen_tile = [&](int col, const char *cur, int j16) {
-        if constexpr (PRUNE) {
-            if ((skip16 >> j16) & 1u) return;
-        }
+    auto screen_tile = [&](int col, const char *cur) __attribute__((always_inline)) {
         f32x4 acc[4][4];
 #pragma unroll
         for (int t = 0; t < 4; ++t)
@@ -564,17 +549,32 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
 #pragma unroll
                 for (int mt = 0; mt < 4; ++mt) acc[t][mt] = Op::mfma(a1[mt], bq[t][1], acc[t][mt]);
         } else {
+            // FP32 rows: k-steps 4q .. 4q + 3 of candidate block mt are one
+            // 16-byte chunk (frag_off[4q]); the four blocks' chunks of each q
+            // are read in one asm block, for the same reason as above.
+            static_assert(KSTEPS % 4 == 0, "whole 16-byte chunks per lane");
+            const uint32_t base =
+                (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)cur;
+            float af[4][KSTEPS];
 #pragma unroll
-            for (int s = 0; s < KSTEPS; ++s) {
-                typename Op::frag_t af[4];
+            for (int q = 0; q < KSTEPS / 4; ++q) {
+                uint4 f[4];
+                lds_read4<16 * RB>(base + (uint32_t)frag_off[4 * q], f[0], f[1], f[2], f[3]);
 #pragma unroll
-                for (int mt = 0; mt < 4; ++mt) af[mt] = Op::load(cur + mt * 16 * RB + frag_off[s]);
+                for (int mt = 0; mt < 4; ++mt) {
+                    af[mt][4 * q] = __uint_as_float(f[mt].x);
+                    af[mt][4 * q + 1] = __uint_as_float(f[mt].y);
+                    af[mt][4 * q + 2] = __uint_as_float(f[mt].z);
+                    af[mt][4 * q + 3] = __uint_as_float(f[mt].w);
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < KSTEPS; ++s)
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
 #pragma unroll
                     for (int mt = 0; mt < 4; ++mt)
-                        acc[t][mt] = Op::mfma(af[mt], bq[t][s], acc[t][mt]);
-            }
+                        acc[t][mt] = Op::mfma(af[mt][s], bq[t][s], acc[t][mt]);
         }
 
         // Candidate selection.  For each query tile t a lane holds 16 values
@@ -623,14 +623,11 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
     auto period = [&](int v, char (*cur)[TILE * RB], char (*nxt)[TILE * RB]) {
 #pragma unroll
         for (int j = 0; j < TPB; ++j)
-            if (v + (TPB + j) * TILE < len) load_tile(phys(v + (TPB + j) * TILE), nxt[j]);
-        if constexpr (PRUNE) {
-            if ((v & (16 * TILE - 1)) == 0) skip16 = prune_mask(v);
-        }
+            if (v + (TPB + j) * TILE < len) load_tile(cb + v + (TPB + j) * TILE, nxt[j]);
 #pragma unroll 1
         for (int j = 0; j < TPB; ++j)
             if (v + j * TILE < len) {
-                screen_tile(phys(v + j * TILE), cur[j], ((v >> 6) + j) & 15);
+                screen_tile(cb + v + j * TILE, cur[j]);
                 if (__ballot(cnt[0] > TRIG || cnt[1] > TRIG || cnt[2] > TRIG || cnt[3] > TRIG) != 0)
                     flush_full();
             }
@@ -639,89 +636,10 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
         __syncthreads();
     };
 
-    // Pruned scans go a super-tile, then a quad of four groups, then a group
-    // of 16 tiles at a time.  Super-tiles start at multiples of
-    // SCREEN_SUPER_ROWS and groups at multiples of SCREEN_GROUP_ROWS (virtual
-    // and physical positions alike), so the group balls line up with the
-    // scan.  At a super-tile's start every wave tests its 16 group balls.  At
-    // a quad's start every wave computes the skip bits of its needed groups'
-    // tiles and the workgroup ORs the tiles some wave needs per group (one
-    // barrier per quad); only those are loaded, and a group no wave needs
-    // costs nothing.  (Loading the four groups' centre rows and radii
-    // together, ahead of their tests, spilled registers and was slower.)
-    // Within a group the periods run as in the full scan, the next period's
-    // needed tiles loading while the current one is screened.
-    int qc = 0;  // quads entered, for the need_q buffers
-    auto run_groups = [&](int v_begin) {
-        uint32_t gmine = 0u;
-        int qb = 0;
-        for (int v0 = v_begin; v0 < len; v0 += SCREEN_GROUP_ROWS) {
-            const int jg = (v0 / SCREEN_GROUP_ROWS) & (SCREEN_GROUP - 1);
-            if (jg == 0) {
-                gmine = ~ball_mask(
-                            [&](int j) {
-                                return (const char *)a.grp_c +
-                                       (int64_t)(phys(v0 + j * SCREEN_GROUP_ROWS) /
-                                                 SCREEN_GROUP_ROWS) * RB;
-                            },
-                            [&](int j) {
-                                return a.grp_r[phys(v0 + j * SCREEN_GROUP_ROWS) /
-                                               SCREEN_GROUP_ROWS];
-                            }) &
-                        0xffffu;
-            }
-            if ((jg & 3) == 0) {
-                qb = qc % 3;
-#pragma unroll 1
-                for (int u = 0; u < 4; ++u) {
-                    const uint32_t sk =
-                        ((gmine >> (jg + u)) & 1u) ? prune_mask(v0 + u * SCREEN_GROUP_ROWS) : 0xffffu;
-                    if (lane == 0) {
-                        my_skip[wave][u] = sk;
-                        if (sk != 0xffffu) atomicOr(&need_q[qb][u], ~sk & 0xffffu);
-                    }
-                }
-                __syncthreads();
-                // the buffer of two quads ago: read before this barrier, next
-                // written after the next quad's barrier
-                if (threadIdx.x < 4) need_q[(qc + 2) % 3][threadIdx.x] = 0u;
-                ++qc;
-            }
-            const uint32_t need = need_q[qb][jg & 3];
-            if (need == 0u) continue;
-            skip16 = my_skip[wave][jg & 3];
-            auto load_period = [&](int vp, char (*dst)[TILE * RB]) {
-#pragma unroll
-                for (int j = 0; j < TPB; ++j) {
-                    const int t = ((vp - v0) >> 6) + j;
-                    if (vp + j * TILE < len && ((need >> t) & 1u)) load_tile(phys(vp + j * TILE), dst[j]);
-                }
-            };
-            load_period(v0, ringA);
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-            __syncthreads();
-#pragma unroll 1
-            for (int p = 0; p < 16 / TPB; ++p) {
-                const int vp = v0 + p * TPB * TILE;
-                char(*cur)[TILE * RB] = (p & 1) ? ringB : ringA;
-                char(*nxt)[TILE * RB] = (p & 1) ? ringA : ringB;
-                if (p + 1 < 16 / TPB) load_period(vp + TPB * TILE, nxt);
-#pragma unroll 1
-                for (int j = 0; j < TPB; ++j)
-                    if (vp + j * TILE < len) {
-                        screen_tile(phys(vp + j * TILE), cur[j], ((vp >> 6) + j) & 15);
-                        if (__ballot(cnt[0] > TRIG || cnt[1] > TRIG || cnt[2] > TRIG || cnt[3] > TRIG) != 0)
-                            flush_full();
-                    }
-                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-                __syncthreads();
-            }
-        }
-    };
     if constexpr (!PRUNE) {
 #pragma unroll
         for (int j = 0; j < TPB; ++j)
-            if (j * TILE < len) load_tile(phys(j * TILE), ringA[j]);
+            if (j * TILE < len) load_tile(cb + j * TILE, ringA[j]);
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         for (int v = 0; v < len; v += 2 * TPB * TILE) {
@@ -729,58 +647,76 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
             if (v + TPB * TILE < len) period(v + TPB * TILE, ringB, ringA);
         }
     } else {
-        __syncthreads();  // the LDS words above are cleared
-        run_groups(0);
-        // Second phase: every wave marks the super-tiles it cannot skip with
-        // its current thresholds (which only fall, so a super-tile skipped
-        // now holds no candidate for any later threshold either); the kept
-        // ones after the own super-tile, in order and wrapping, are scanned.
+        // Pruned scan, every wave on its own: no workgroup barrier, so a wave
+        // busy with a selection holds up no other.  The wave goes a super-tile,
+        // then a group of 16 tiles, at a time: at a super-tile it tests the 16
+        // group balls, at a needed group the 16 tile balls (thresholds as they
+        // stand then), and it loads and screens only the tiles it needs,
+        // through two LDS slots of its own: a tile's load is issued before
+        // the previous tile is screened.  In the second phase the super-tile
+        // balls are tested 16 at a time ahead of the scan; thresholds only
+        // fall, so a ball skipped with a threshold holds no candidate for any
+        // later one either.
+        static_assert(TPB == 4, "a wave's two slots are ringA[wave] and ringB[wave]");
+        int pend = -1, ps = 0;  // the tile in flight (not yet screened) and its slot
+        auto screen_pending = [&]() __attribute__((always_inline)) {
+            screen_tile(pend * TILE, ps ? ringB[wave] : ringA[wave]);
+            if (__ballot(cnt[0] > TRIG || cnt[1] > TRIG || cnt[2] > TRIG || cnt[3] > TRIG) != 0)
+                flush_full();
+        };
+        auto visit = [&](int tile) __attribute__((always_inline)) {
+            if (pend >= 0) {
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // the pending tile has landed
+                load_tile_part(tile * TILE, ps ? ringA[wave] : ringB[wave], 0, CH);
+                screen_pending();
+                ps ^= 1;
+            } else {
+                load_tile_part(tile * TILE, ps ? ringB[wave] : ringA[wave], 0, CH);
+            }
+            pend = tile;
+        };
+        auto scan_group = [&](int gidx) __attribute__((always_inline)) {
+            uint32_t need = ~tile_mask(gidx * SCREEN_GROUP) & 0xffffu;
+            while (need != 0u) {
+                const int j = __ffs(need) - 1;
+                need &= need - 1u;
+                visit(gidx * SCREEN_GROUP + j);
+            }
+        };
+        // first phase: the own super-tile from the own group, wrapping
+#pragma unroll 1
+        for (int jj = 0; jj < SCREEN_GROUP; ++jj)
+            scan_group(own_sup * SCREEN_GROUP + ((rot_g + jj) & (SCREEN_GROUP - 1)));
+        // second phase: the other super-tiles, in order after the own one
         const int nsup = (int)((ce - cb) / SCREEN_SUPER_ROWS);
-        for (int s0 = 0; s0 < nsup; s0 += 16) {
-            const uint32_t skip = ball_mask(
-                [&](int j) {
-                    const int sj = s0 + j < nsup ? s0 + j : s0;
-                    return (const char *)a.sup_c + (int64_t)sj * RB;
+#pragma unroll 1
+        for (int q0 = 1; q0 < nsup; q0 += 16) {
+            auto sidx = [&](int j) {
+                const int sj = own_sup + q0 + j;
+                return sj < nsup ? sj : sj - nsup;
+            };
+            uint32_t sneed =
+                ~ball_mask([&](int j) {
+                    return (const char *)a.sup_c + (int64_t)(q0 + j < nsup ? sidx(j) : own_sup) * RB;
                 },
-                [&](int j) { return s0 + j < nsup ? a.sup_r[s0 + j] : INFINITY; });
-            const uint32_t keep = ~skip & 0xffffu;
-            if (lane == 0 && keep) atomicOr(&sup_keep[s0 / 32], keep << (s0 & 31));
-        }
-        __syncthreads();
-        if (wave == 0) {
-            // list: own + 1, ..., nsup - 1, then 0, ..., own - 1 (lane w
-            // counts word w; two exclusive scans place the indices)
-            int total = 0;
-            for (int part = 0; part < 2; ++part) {
-                for (int w0 = 0; w0 < SCREEN_SUPER_MAX / 32; w0 += 64) {
-                    const int w = w0 + lane;
-                    uint32_t bits = 0u;
-                    if (w * 32 < nsup) {
-                        bits = sup_keep[w];
-                        for (int b = 0; b < 32; ++b) {
-                            const int sidx = w * 32 + b;
-                            const bool in = sidx < nsup && sidx != own_sup &&
-                                            (part == 0 ? sidx > own_sup : sidx < own_sup);
-                            if (!in) bits &= ~(1u << b);
-                        }
-                    }
-                    const int cnt = __popc(bits);
-                    const int incl = wave_incl_scan(cnt, lane);
-                    int pos = total + incl - cnt;
-                    while (bits) {
-                        const int b = __ffs(bits) - 1;
-                        bits &= bits - 1;
-                        sup_list[pos++] = (uint16_t)(w * 32 + b);
-                    }
-                    total += __builtin_amdgcn_readlane(incl, 63);
+                           [&](int j) { return q0 + j < nsup ? a.sup_r[sidx(j)] : -1.0e18f; }) &
+                0xffffu;
+            while (sneed != 0u) {
+                const int j = __ffs(sneed) - 1;
+                sneed &= sneed - 1u;
+                const int sup = sidx(j);
+                uint32_t gneed = ~group_mask(sup * SCREEN_GROUP) & 0xffffu;
+                while (gneed != 0u) {
+                    const int jg = __ffs(gneed) - 1;
+                    gneed &= gneed - 1u;
+                    scan_group(sup * SCREEN_GROUP + jg);
                 }
             }
-            if (lane == 0) sup_keep[0] = (uint32_t)total;  // the count, for every wave
         }
-        __syncthreads();
-        const int kept = (int)sup_keep[0];
-        len = SCREEN_SUPER_ROWS * (1 + kept);
-        run_groups(SCREEN_SUPER_ROWS);
+        if (pend >= 0) {
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            screen_pending();
+        }
     }
 
     // Final selection, sort and output of every real query of this wave.
