@@ -306,6 +306,106 @@ __device__ __forceinline__ void chol_steps(float (&K)[KMAX], float (&y)[ELLMAX],
     }
 }
 
+// Blocked solves on FP32 MFMA (the mixed path).  The right-hand sides are
+// held in the 16x16x4 output layout: per 16-row block J a lane holds rows
+// 16 J + 4 (l / 16) + q (q < 4) of column l % 16 (columns past ell are zero).
+// A product M W of a 16x16 block M and such a block W takes four k-steps, the
+// k-index of step q on lane l being 4 (l / 16) + q, so that the B operand of
+// step q is the lane's own element q and the A operand is
+// M[l % 16][4 (l / 16) + q].  The unit diagonal blocks of U are replaced in
+// LDS by their inverses (same packed places, unit diagonal implicit), so
+// that a block solve is one product:
+//   U w = r:      w_J = inv(U_JJ) (r_J - sum_{I<J} U_JI w_I),   J ascending;
+//   U^T x = v:    x_J = inv(U_JJ)^T (v_J - sum_{I>J} U_IJ^T x_I), J descending.
+// Entries of rows at or past k are zero (their right-hand sides are zero).
+
+// Entry (row, col) of U, or of an inverted diagonal block when both lie in
+// one block (unit diagonal), from the packed strictly lower part.
+__device__ __forceinline__ float u_entry(const float *__restrict__ U, int k, int row, int col) {
+    if (row >= k || col > row) return 0.0f;
+    if (col == row) return 1.0f;
+    return U[row * (row - 1) / 2 + col];
+}
+
+template <int NT>
+__device__ __forceinline__ void mfma_forward(const float *__restrict__ U, int k, int fr, int fk,
+                                             f32x4 (&r)[NT]) {
+#pragma unroll
+    for (int J = 0; J < NT; ++J) {
+        f32x4 acc = r[J];
+#pragma unroll
+        for (int I = 0; I < J; ++I)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                    -u_entry(U, k, 16 * J + fr, 16 * I + 4 * fk + q), r[I][q], acc, 0, 0, 0);
+        f32x4 w = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            w = __builtin_amdgcn_mfma_f32_16x16x4f32(u_entry(U, k, 16 * J + fr, 16 * J + 4 * fk + q),
+                                                     acc[q], w, 0, 0, 0);
+        r[J] = w;
+    }
+}
+
+template <int NT>
+__device__ __forceinline__ void mfma_backward(const float *__restrict__ U, int k, int fr, int fk,
+                                              f32x4 (&r)[NT]) {
+#pragma unroll
+    for (int J = NT - 1; J >= 0; --J) {
+        f32x4 acc = r[J];
+#pragma unroll
+        for (int I = J + 1; I < NT; ++I)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                    -u_entry(U, k, 16 * I + 4 * fk + q, 16 * J + fr), r[I][q], acc, 0, 0, 0);
+        f32x4 x = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            x = __builtin_amdgcn_mfma_f32_16x16x4f32(u_entry(U, k, 16 * J + 4 * fk + q, 16 * J + fr),
+                                                     acc[q], x, 0, 0, 0);
+        r[J] = x;
+    }
+}
+
+// The inverses of U's unit lower diagonal blocks, in place: lane a = 16 J + r
+// holds row r of block J and forward-substitutes the identity, row m of its
+// block coming from lane 16 J + m by a DPP row broadcast (row_newbcast).
+template <int M>
+__device__ __forceinline__ float bcast16(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                 0x150 + M, 0xf, 0xf, false));
+}
+template <int M>
+__device__ __forceinline__ void inv_step(float (&X)[16], const float (&um)[16]) {
+#pragma unroll
+    for (int c = 0; c <= M; ++c) X[c] = fmaf(-um[M], bcast16<M>(X[c]), X[c]);
+}
+template <int M>
+__device__ __forceinline__ void inv_steps(float (&X)[16], const float (&um)[16]) {
+    if constexpr (M < 15) {
+        inv_step<M>(X, um);
+        inv_steps<M + 1>(X, um);
+    }
+}
+__device__ __forceinline__ void invert_diag_blocks(float *__restrict__ U, int k, int a) {
+    const int J = a >> 4, r = a & 15;
+    const int arow = a * (a - 1) / 2;
+    float um[16], X[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        um[m] = (m < r && a < k) ? U[arow + 16 * J + m] : 0.0f;
+        X[m] = (m == r) ? 1.0f : 0.0f;
+    }
+    inv_steps<0>(X, um);
+    lds_sync();  // every lane has read its block row before any is overwritten
+#pragma unroll
+    for (int c = 0; c < 15; ++c)
+        if (c < r && a < k) U[arow + 16 * J + c] = X[c];
+    lds_sync();
+}
+
 template <int KMAX, int ELLMAX, bool REFINE>
 __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
     extern __shared__ __align__(16) char smem[];
@@ -439,9 +539,34 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
     // 3. v = D^{-1} w, then U^T x = v.
 #pragma unroll
     for (int c = 0; c < ELLMAX; ++c) y[c] *= dinv;
-    solve_unit_backward<ELLMAX>(U, k, ell, a, y);
+    if constexpr (!REFINE) {
+        solve_unit_backward<ELLMAX>(U, k, ell, a, y);
+        if (a < k) {
+            float *__restrict__ C = (float *)P.C + (i * k + a) * ell;
+#pragma unroll
+            for (int c = 0; c < ELLMAX; ++c)
+                if (c < ell) C[c] = bad ? NAN : y[c];
+        }
+        if (a == 0) P.status[i] = bad ? 1 : 0;
+    } else {
+        // Mixed: the solves go through FP32 MFMA in 16-row blocks (see
+        // mfma_forward / mfma_backward), with the diagonal blocks of U
+        // inverted in place first; v moves to the MFMA layout through LDS.
+        const int fr = a & 15, fk = a >> 4;
+        invert_diag_blocks(U, k, a);
+        float *vb = (float *)(smem + L.off_r1);  // [64][16] v, rows past k zero (the Gram is dead)
+        float *dv = nrm;                          // [64] D^{-1} (the norms are dead)
+#pragma unroll
+        for (int c = 0; c < 16; ++c) vb[a * 16 + c] = (c < ELLMAX && a < k) ? y[c] : 0.0f;
+        dv[a] = a < k ? dinv : 0.0f;
+        lds_sync();
+        f32x4 Xs[NT];
+#pragma unroll
+        for (int J = 0; J < NT; ++J)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Xs[J][q] = vb[(16 * J + 4 * fk + q) * 16 + fr];
+        mfma_backward<NT>(U, k, fr, fk, Xs);
 
-    if constexpr (REFINE) {
         // 4. One refinement step, r = Y_N - (K64 + sigma^2 I) C, in FP64 on
         // FP64 MFMA.  The centred rows are exact in FP64 (a difference of two
         // FP32 values); their Gram matrix gives D_ab = |c_a|^2 + |c_b|^2 -
@@ -451,13 +576,17 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
         // (K being symmetric) is exactly the A operand of the product for
         // the transposed tile, so K never leaves registers.
         const int ld = L.xs_ld, d4 = (d + 3) & ~3;
+        float *cb = bc;  // [64][ELLMAX] current coefficients, zero past k / ell
+        if (fr < ELLMAX) {
+#pragma unroll
+            for (int J = 0; J < NT; ++J)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) cb[(16 * J + 4 * fk + q) * ELLMAX + fr] = Xs[J][q];
+        }
+        lds_sync();  // v is read: its space takes the raw rows
         float *xr = (float *)(smem + L.off_r1);
         float *xc = xr + k * ld;
-        lds_sync();  // the Gram staging area is dead
         nrm64[a] = stage_rows_raw(X, d, k, xi, p, xr, ld, xc, a);
-        float *cb = bc;  // [64][ELLMAX] current coefficients, zero past k / ell
-#pragma unroll
-        for (int c = 0; c < ELLMAX; ++c) cb[a * ELLMAX + c] = (a < k && c < ell) ? y[c] : 0.0f;
         lds_sync();
         const double diag64 = P.amp + P.noise;
         const PhiForm<double> pf64 = phi_form<double>(P.kc, P.inv_rho, P.amp);
@@ -536,35 +665,50 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
             R[ct] = acc64;
             lds_sync();  // the transposes are read before the next tile's are written
         }
-        lds_sync();  // the raw rows are dead; their space takes K64 C
+        // K64 C moves through LDS from the FP64 output layout (rows
+        // 16 ct + 4 q + l / 16) to the FP32 one of the solves (rows
+        // 16 J + 4 (l / 16) + q); the residual takes the neighbour of a row
+        // from that row's lane.
+        lds_sync();  // the transposes are dead; their space takes K64 C
         double *KC = (double *)(smem + L.off_r1);  // [64][ELLMAX]
-        if (fr < ell) {
+        if (fr < ELLMAX) {
 #pragma unroll
             for (int ct = 0; ct < NT; ++ct)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) KC[(ct * 16 + 4 * q + fk) * ELLMAX + fr] = R[ct][q];
         }
         lds_sync();
-        float dl[ELLMAX];
+        f32x4 Rs[NT];
 #pragma unroll
-        for (int c = 0; c < ELLMAX; ++c)
-            dl[c] = (a < k && c < ell) ? (float)((double)Y[p * ell + c] - KC[a * ELLMAX + c])
-                                       : 0.0f;
-        solve_unit_forward<ELLMAX>(U, k, ell, a, dl);
+        for (int J = 0; J < NT; ++J)
 #pragma unroll
-        for (int c = 0; c < ELLMAX; ++c) dl[c] *= dinv;
-        solve_unit_backward<ELLMAX>(U, k, ell, a, dl);
+            for (int q = 0; q < 4; ++q) {
+                const int row = 16 * J + 4 * fk + q;
+                const int prow = __shfl((int)p, row);
+                const bool in = row < k && fr < ell;
+                Rs[J][q] = in ? (float)((double)Y[(int64_t)prow * ell + fr] - KC[row * ELLMAX + fr])
+                              : 0.0f;
+            }
+        mfma_forward<NT>(U, k, fr, fk, Rs);
 #pragma unroll
-        for (int c = 0; c < ELLMAX; ++c) y[c] += dl[c];
+        for (int J = 0; J < NT; ++J)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Rs[J][q] *= dv[16 * J + 4 * fk + q];
+        mfma_backward<NT>(U, k, fr, fk, Rs);
+        if (fr < ell) {
+#pragma unroll
+            for (int J = 0; J < NT; ++J)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = 16 * J + 4 * fk + q;
+                    if (row < k) {
+                        const float cnew = cb[row * ELLMAX + fr] + Rs[J][q];
+                        ((float *)P.C)[(i * k + row) * ell + fr] = bad ? NAN : cnew;
+                    }
+                }
+        }
+        if (a == 0) P.status[i] = bad ? 1 : 0;
     }
-
-    if (a < k) {
-        float *__restrict__ C = (float *)P.C + (i * k + a) * ell;
-#pragma unroll
-        for (int c = 0; c < ELLMAX; ++c)
-            if (c < ell) C[c] = bad ? NAN : y[c];
-    }
-    if (a == 0) P.status[i] = bad ? 1 : 0;
 }
 
 template <int KMAX, int ELLMAX, bool REFINE>

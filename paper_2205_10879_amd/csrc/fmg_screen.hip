@@ -416,7 +416,7 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
 #pragma unroll
         for (int i = 0; i < 4; ++i) b.rad[i] = ball_rad(4 * g + i);
     };
-    auto ball_test = [&](const Balls &b) __attribute__((always_inline)) -> uint32_t  {
+    auto ball_test = [&](const Balls &b) __attribute__((always_inline)) -> uint32_t {
         f32x4 ac[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
@@ -450,18 +450,18 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
         }
         return skip;
     };
-    auto ball_mask = [&](auto ball_row, auto ball_rad) __attribute__((always_inline)) -> uint32_t  {
+    auto ball_mask = [&](auto ball_row, auto ball_rad) __attribute__((always_inline)) -> uint32_t {
         Balls b;
         ball_load(ball_row, ball_rad, b);
         return ball_test(b);
     };
     // Skip bits of the 16 tiles t0 .. t0 + 15, of the 16 groups g0 .. g0 + 15
     // (a super-tile's), and of the 16 super-tiles s(0) .. s(15).
-    auto tile_mask = [&](int t0) __attribute__((always_inline)) -> uint32_t  {
+    auto tile_mask = [&](int t0) __attribute__((always_inline)) -> uint32_t {
         return ball_mask([&](int j) { return (const char *)a.tile_c + (int64_t)(t0 + j) * RB; },
                          [&](int j) { return a.tile_r[t0 + j]; });
     };
-    auto group_mask = [&](int g0) __attribute__((always_inline)) -> uint32_t  {
+    auto group_mask = [&](int g0) __attribute__((always_inline)) -> uint32_t {
         return ball_mask([&](int j) { return (const char *)a.grp_c + (int64_t)(g0 + j) * RB; },
                          [&](int j) { return a.grp_r[g0 + j]; });
     };
