@@ -220,7 +220,8 @@ __device__ __forceinline__ void solve_unit_backward(const float *__restrict__ U,
     }
 }
 
-// Four Cholesky steps j .. j + 3 at once (register window of W columns).
+// Four Cholesky steps j .. j + 3 at once (register window of W columns);
+// the first NY right-hand sides in y take the forward solve along.
 // The panel, columns j .. j + 3 held in K[0..3], is factored with values
 // read across lanes (the entry of row j + t2 in column j + t comes from lane
 // j + t2); every lane then publishes its four panel entries in LDS, and the
@@ -228,7 +229,7 @@ __device__ __forceinline__ void solve_unit_backward(const float *__restrict__ U,
 // entry sees exactly the operations of four single steps, with one LDS
 // round trip instead of four.  bc holds two buffers of 64 float4, used
 // alternately.
-template <int KMAX, int ELLMAX, int W>
+template <int KMAX, int ELLMAX, int NY, int W>
 __device__ __forceinline__ void chol_block4(float (&K)[KMAX], float (&y)[ELLMAX], int j, int k,
                                             int a, float *__restrict__ U,
                                             float *__restrict__ bc, float &dinv, bool &bad) {
@@ -247,7 +248,7 @@ __device__ __forceinline__ void chol_block4(float (&K)[KMAX], float (&y)[ELLMAX]
         if (a == j + t) dinv = rp;
         if (below) U[arow + j + t] = u[t];
 #pragma unroll
-        for (int c = 0; c < ELLMAX; ++c) y[c] = fmaf(-u[t], readlane_f32(y[c], j + t), y[c]);
+        for (int c = 0; c < NY; ++c) y[c] = fmaf(-u[t], readlane_f32(y[c], j + t), y[c]);
 #pragma unroll
         for (int t2 = t + 1; t2 < 4; ++t2)
             K[t2] = fmaf(-u[t], readlane_f32(K[t], j + t2), K[t2]);
@@ -272,14 +273,14 @@ __device__ __forceinline__ void chol_block4(float (&K)[KMAX], float (&y)[ELLMAX]
 
 // Cholesky steps j in [j0, j1) with a register window of W columns: blocks
 // of four steps, then single steps.
-template <int KMAX, int ELLMAX, int W>
+template <int KMAX, int ELLMAX, int NY, int W>
 __device__ __forceinline__ void chol_steps(float (&K)[KMAX], float (&y)[ELLMAX], int j0, int j1,
                                            int k, int ell, int a, float *__restrict__ U,
                                            float *__restrict__ bc, float &dinv, bool &bad) {
     const int arow = a * (a - 1) / 2;
     int j = j0;
     if (j + 4 <= j1) {
-        for (; j + 4 <= j1; j += 4) chol_block4<KMAX, ELLMAX, W>(K, y, j, k, a, U, bc, dinv, bad);
+        for (; j + 4 <= j1; j += 4) chol_block4<KMAX, ELLMAX, NY, W>(K, y, j, k, a, U, bc, dinv, bad);
         lds_sync();  // the last block's readers are done before bc is written again
     }
     for (; j < j1; ++j) {
@@ -294,7 +295,7 @@ __device__ __forceinline__ void chol_steps(float (&K)[KMAX], float (&y)[ELLMAX],
         if (a == j) dinv = rp;
         if (below) U[arow + j] = u;
 #pragma unroll
-        for (int c = 0; c < ELLMAX; ++c) y[c] = fmaf(-u, readlane_f32(y[c], j), y[c]);
+        for (int c = 0; c < NY; ++c) y[c] = fmaf(-u, readlane_f32(y[c], j), y[c]);
         // Entry b of the broadcast is column j of the trailing matrix at row
         // j + 1 + b; the positions past the last row are zero.
         bc[(a - j - 1) & 63] = (a > j) ? K[0] : 0.0f;
@@ -319,31 +320,49 @@ __device__ __forceinline__ void chol_steps(float (&K)[KMAX], float (&y)[ELLMAX],
 //   U^T x = v:    x_J = inv(U_JJ)^T (v_J - sum_{I>J} U_IJ^T x_I), J descending.
 // Entries of rows at or past k are zero (their right-hand sides are zero).
 
-// Entry (row, col) of U, or of an inverted diagonal block when both lie in
-// one block (unit diagonal), from the packed strictly lower part.
-__device__ __forceinline__ float u_entry(const float *__restrict__ U, int k, int row, int col) {
-    if (row >= k || col > row) return 0.0f;
-    if (col == row) return 1.0f;
-    return U[row * (row - 1) / 2 + col];
-}
-
+// The A operands of each 16x16 block product are read first, four at a time
+// (branch free: addresses clamped to a valid entry and the value selected),
+// so that the reads are in flight together and the four MFMAs follow
+// without a wait each.
 template <int NT>
 __device__ __forceinline__ void mfma_forward(const float *__restrict__ U, int k, int fr, int fk,
                                              f32x4 (&r)[NT]) {
+    // opaque copies: the addresses are formed afresh in every solve instead
+    // of being shared (and kept live) across the kernel
+    asm volatile("" : "+v"(fr), "+v"(fk));
 #pragma unroll
     for (int J = 0; J < NT; ++J) {
+        __builtin_amdgcn_sched_barrier(0);  // one block's reads at a time (register pressure)
+        // row 16 J + fr of U: entries (row, 16 I + 4 fk + q), I < J, then
+        // the inverted diagonal block's (row, 16 J + 4 fk + q)
+        const int row = 16 * J + fr;
+        const bool rv = row < k;
+        const int rb = row * (row - 1) / 2 + 4 * fk;
         f32x4 acc = r[J];
 #pragma unroll
-        for (int I = 0; I < J; ++I)
+        for (int I = 0; I < J; ++I) {
+            float aop[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float v = U[rv ? rb + 16 * I + q : 0];
+                aop[q] = rv ? -v : 0.0f;
+            }
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                    -u_entry(U, k, 16 * J + fr, 16 * I + 4 * fk + q), r[I][q], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[q], r[I][q], acc, 0, 0, 0);
+        }
+        float aop[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = 4 * fk + q;  // column within the block
+            const bool lower = rv && c < fr;
+            const float v = U[lower ? rb + 16 * J + q : 0];
+            aop[q] = lower ? v : ((rv && c == fr) ? 1.0f : 0.0f);
+        }
         f32x4 w = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            w = __builtin_amdgcn_mfma_f32_16x16x4f32(u_entry(U, k, 16 * J + fr, 16 * J + 4 * fk + q),
-                                                     acc[q], w, 0, 0, 0);
+            w = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[q], acc[q], w, 0, 0, 0);
         r[J] = w;
     }
 }
@@ -351,20 +370,40 @@ __device__ __forceinline__ void mfma_forward(const float *__restrict__ U, int k,
 template <int NT>
 __device__ __forceinline__ void mfma_backward(const float *__restrict__ U, int k, int fr, int fk,
                                               f32x4 (&r)[NT]) {
+    asm volatile("" : "+v"(fr), "+v"(fk));  // as in mfma_forward
 #pragma unroll
     for (int J = NT - 1; J >= 0; --J) {
+        __builtin_amdgcn_sched_barrier(0);  // one block's reads at a time (register pressure)
+        // column 16 J + fr of U: entries (16 I + 4 fk + q, col), I > J, then
+        // the inverted diagonal block's (16 J + 4 fk + q, col)
         f32x4 acc = r[J];
 #pragma unroll
-        for (int I = J + 1; I < NT; ++I)
+        for (int I = J + 1; I < NT; ++I) {
+            float aop[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = 16 * I + 4 * fk + q;
+                const bool rv = row < k;
+                const float v = U[rv ? row * (row - 1) / 2 + 16 * J + fr : 0];
+                aop[q] = rv ? -v : 0.0f;
+            }
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                    -u_entry(U, k, 16 * I + 4 * fk + q, 16 * J + fr), r[I][q], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[q], r[I][q], acc, 0, 0, 0);
+        }
+        float aop[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int c = 4 * fk + q;  // row within the block
+            const int row = 16 * J + c;
+            const bool lower = row < k && fr < c;
+            const float v = U[lower ? row * (row - 1) / 2 + 16 * J + fr : 0];
+            aop[q] = lower ? v : ((row < k && c == fr) ? 1.0f : 0.0f);
+        }
         f32x4 x = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            x = __builtin_amdgcn_mfma_f32_16x16x4f32(u_entry(U, k, 16 * J + 4 * fk + q, 16 * J + fr),
-                                                     acc[q], x, 0, 0, 0);
+            x = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[q], acc[q], x, 0, 0, 0);
         r[J] = x;
     }
 }
@@ -407,7 +446,7 @@ __device__ __forceinline__ void invert_diag_blocks(float *__restrict__ U, int k,
 }
 
 template <int KMAX, int ELLMAX, bool REFINE>
-__global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void precompute32_kernel(PrecomputeArgs P) {
     extern __shared__ __align__(16) char smem[];
     if ((int64_t)blockIdx.x >= P.n) return;
     const int64_t i = P.order ? (int64_t)P.order[blockIdx.x] : (int64_t)blockIdx.x;
@@ -512,34 +551,36 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
         K[b] = (a < k) ? v : ((a == b) ? 1.0f : 0.0f);
     }
 
-    // 2. K = U D U^T with U w = y folded in; the window narrows by 16 columns
-    // whenever the trailing matrix fits a narrower one.
+    // 2. K = U D U^T with U w = y folded in (plain FP32; the mixed path
+    // solves on MFMA afterwards); the window narrows by 16 columns whenever
+    // the trailing matrix fits a narrower one.
+    constexpr int NY = REFINE ? 0 : ELLMAX;
     bool bad = false;
     float dinv = 0.0f;
     {
         int j = 0;
         if constexpr (KMAX > 48) {
             const int e = k - 48 > 0 ? k - 48 : 0;
-            chol_steps<KMAX, ELLMAX, 64>(K, y, j, e, k, ell, a, U, bc, dinv, bad);
+            chol_steps<KMAX, ELLMAX, NY, 64>(K, y, j, e, k, ell, a, U, bc, dinv, bad);
             j = e;
         }
         if constexpr (KMAX > 32) {
             const int e = k - 32 > j ? k - 32 : j;
-            chol_steps<KMAX, ELLMAX, 48>(K, y, j, e, k, ell, a, U, bc, dinv, bad);
+            chol_steps<KMAX, ELLMAX, NY, 48>(K, y, j, e, k, ell, a, U, bc, dinv, bad);
             j = e;
         }
         {
             const int e = k - 16 > j ? k - 16 : j;
-            chol_steps<KMAX, ELLMAX, 32>(K, y, j, e, k, ell, a, U, bc, dinv, bad);
+            chol_steps<KMAX, ELLMAX, NY, 32>(K, y, j, e, k, ell, a, U, bc, dinv, bad);
             j = e;
         }
-        chol_steps<KMAX, ELLMAX, 16>(K, y, j, k, k, ell, a, U, bc, dinv, bad);
+        chol_steps<KMAX, ELLMAX, NY, 16>(K, y, j, k, k, ell, a, U, bc, dinv, bad);
     }
 
     // 3. v = D^{-1} w, then U^T x = v.
-#pragma unroll
-    for (int c = 0; c < ELLMAX; ++c) y[c] *= dinv;
     if constexpr (!REFINE) {
+#pragma unroll
+        for (int c = 0; c < ELLMAX; ++c) y[c] *= dinv;
         solve_unit_backward<ELLMAX>(U, k, ell, a, y);
         if (a < k) {
             float *__restrict__ C = (float *)P.C + (i * k + a) * ell;
@@ -551,20 +592,27 @@ __global__ __launch_bounds__(64) void precompute32_kernel(PrecomputeArgs P) {
     } else {
         // Mixed: the solves go through FP32 MFMA in 16-row blocks (see
         // mfma_forward / mfma_backward), with the diagonal blocks of U
-        // inverted in place first; v moves to the MFMA layout through LDS.
+        // inverted in place first.
         const int fr = a & 15, fk = a >> 4;
         invert_diag_blocks(U, k, a);
-        float *vb = (float *)(smem + L.off_r1);  // [64][16] v, rows past k zero (the Gram is dead)
-        float *dv = nrm;                          // [64] D^{-1} (the norms are dead)
-#pragma unroll
-        for (int c = 0; c < 16; ++c) vb[a * 16 + c] = (c < ELLMAX && a < k) ? y[c] : 0.0f;
+        float *dv = nrm;  // [64] D^{-1} (the norms are dead)
         dv[a] = a < k ? dinv : 0.0f;
-        lds_sync();
+        // Y in the MFMA layout, the neighbour of a row taken from its lane
         f32x4 Xs[NT];
 #pragma unroll
         for (int J = 0; J < NT; ++J)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) Xs[J][q] = vb[(16 * J + 4 * fk + q) * 16 + fr];
+            for (int q = 0; q < 4; ++q) {
+                const int row = 16 * J + 4 * fk + q;
+                const int prow = __shfl((int)p, row);
+                Xs[J][q] = (row < k && fr < ell) ? Y[(int64_t)prow * ell + fr] : 0.0f;
+            }
+        lds_sync();
+        mfma_forward<NT>(U, k, fr, fk, Xs);
+#pragma unroll
+        for (int J = 0; J < NT; ++J)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Xs[J][q] *= dv[16 * J + 4 * fk + q];
         mfma_backward<NT>(U, k, fr, fk, Xs);
 
         // 4. One refinement step, r = Y_N - (K64 + sigma^2 I) C, in FP64 on
