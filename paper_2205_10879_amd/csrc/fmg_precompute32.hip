@@ -42,10 +42,16 @@ __device__ __forceinline__ void lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Row stride (floats) of the staged coordinates: d rounded up to the MFMA
-// k-step of 4, plus one (odd, so that lanes reading different rows spread
-// over the LDS banks).
-__host__ __device__ __forceinline__ int xs_stride(int d) { return ((d + 3) / 4) * 4 + 1; }
+// Rows are staged a chunk of coordinates at a time (the Gram products
+// accumulate in registers across chunks, so LDS holds one chunk): d rounded
+// up to the MFMA k-step of 4 when that is at most 24, else chunks of 20.
+// The row stride is the chunk plus one (odd, so that lanes reading different
+// rows spread over the LDS banks).
+__host__ __device__ __forceinline__ int stage_chunk(int d) {
+    const int d4 = (d + 3) & ~3;
+    return d4 <= 24 ? d4 : 20;
+}
+__host__ __device__ __forceinline__ int xs_stride(int d) { return stage_chunk(d) + 1; }
 
 // LDS layout (bytes), one wavefront per block.
 struct PcLayout {
@@ -70,10 +76,11 @@ __host__ __device__ __forceinline__ PcLayout pc_layout(int k, int d, int kmax, i
     PcLayout L;
     L.xs_ld = xs_stride(d);
     L.g_ld = kmax + 4;
-    // The refinement's raw rows and centre reuse the staging space; K64 C
-    // reuses theirs once the product is done.
-    const int r64 = refine ? imax3(k * L.xs_ld * 4 + 64 * 4, 64 * ellmax * 8, 0) : 0;
-    const int r1 = imax3(k * L.xs_ld * 4, 32 * L.g_ld * 4, r64);
+    // One region serves in turn: a chunk of the staged rows, the Gram
+    // matrix's transpose 16 columns at a time, a chunk of the refinement's
+    // raw rows and centre, one transposed FP64 tile, the residual.
+    const int r64 = refine ? imax3(k * L.xs_ld * 4 + 32 * 4, 256 * 8, 64 * ellmax * 4) : 0;
+    const int r1 = imax3(k * L.xs_ld * 4, 16 * L.g_ld * 4, r64);
     L.off_r1 = 0;
     L.off_l = (r1 + 15) & ~15;
     L.off_bc = (L.off_l + (k * (k - 1) / 2) * 4 + 15) & ~15;
@@ -84,19 +91,20 @@ __host__ __device__ __forceinline__ PcLayout pc_layout(int k, int d, int kmax, i
     return L;
 }
 
-// Stage rows N(i)_b (b < k) centred on x_i (difference in FP64, rounded to
-// FP32) into xs[b][0..d), zero padded to a multiple of 4; lane b loads row b,
-// four coordinates per load when rows are 16-byte aligned.  xi is the centre
-// (the training point itself, or a query for per-query solves).
+// Stage coordinates c0 .. c0 + cw - 1 (cw a multiple of 4) of rows N(i)_b
+// (b < k) centred on x_i (difference in FP64, rounded to FP32) into
+// xs[b][0..cw), zero past d; lane b loads row b, four coordinates per load
+// when rows are 16-byte aligned.  xi is the centre (the training point
+// itself, or a query for per-query solves).
 __device__ __forceinline__ void stage_rows(const float *__restrict__ X, int d, int k,
                                            const float *__restrict__ xi, int64_t p,
-                                           float *__restrict__ xs, int ld, int a) {
+                                           float *__restrict__ xs, int ld, int a, int c0,
+                                           int cw) {
     const float *__restrict__ xp = X + p * d;
     if (a >= k) return;
-    float *row = xs + a * ld;
+    float *row = xs + a * ld - c0;
     if ((d & 3) == 0 && (((uintptr_t)X | (uintptr_t)xi) & 15) == 0) {
-#pragma unroll 4
-        for (int c = 0; c < d; c += 4) {
+        for (int c = c0; c < c0 + cw; c += 4) {
             const float4 u = *(const float4 *)(xp + c);
             const float4 v = *(const float4 *)(xi + c);
             row[c] = (float)((double)u.x - (double)v.x);
@@ -105,29 +113,27 @@ __device__ __forceinline__ void stage_rows(const float *__restrict__ X, int d, i
             row[c + 3] = (float)((double)u.w - (double)v.w);
         }
     } else {
-#pragma unroll 4
-        for (int c = 0; c < d; ++c) row[c] = (float)((double)xp[c] - (double)xi[c]);
-        for (int c = d; c < ((d + 3) & ~3); ++c) row[c] = 0.0f;
+        for (int c = c0; c < c0 + cw; ++c)
+            row[c] = c < d ? (float)((double)xp[c] - (double)xi[c]) : 0.0f;
     }
 }
 
-// The refinement's rows: the raw FP32 coordinates of rows N(i)_b staged in
-// xr[b][0..d) (zero padded to a multiple of 4) and the centre in xc[0..64)
-// (zero past d), so that every FP64 MFMA operand is formed as the exact
-// difference (double) x_b - (double) x_i when it is loaded.  Returns
-// |x_a - x_i|^2 in FP64 for lane a's row.
-__device__ __forceinline__ double stage_rows_raw(const float *__restrict__ X, int d, int k,
-                                                 const float *__restrict__ xi, int64_t p,
-                                                 float *__restrict__ xr, int ld,
-                                                 float *__restrict__ xc, int a) {
-    xc[a] = a < d ? xi[a] : 0.0f;
+// The refinement's rows: coordinates c0 .. c0 + cw - 1 of rows N(i)_b, raw
+// FP32, staged in xr[b][0..cw) (zero past d) and of the centre in xc[0..cw),
+// so that every FP64 MFMA operand is formed as the exact difference
+// (double) x_b - (double) x_i when it is loaded.  Adds the chunk's part of
+// |x_a - x_i|^2 (FP64, coordinates in order) to n64 for lane a's row.
+__device__ __forceinline__ void stage_rows_raw(const float *__restrict__ X, int d, int k,
+                                               const float *__restrict__ xi, int64_t p,
+                                               float *__restrict__ xr, int ld,
+                                               float *__restrict__ xc, int a, int c0, int cw,
+                                               double &n64) {
+    if (a < cw) xc[a] = c0 + a < d ? xi[c0 + a] : 0.0f;
     const float *__restrict__ xp = X + p * d;
-    double n64 = 0.0;
-    if (a >= k) return n64;
-    float *row = xr + a * ld;
+    if (a >= k) return;
+    float *row = xr + a * ld - c0;
     if ((d & 3) == 0 && (((uintptr_t)X | (uintptr_t)xi) & 15) == 0) {
-#pragma unroll 4
-        for (int c = 0; c < d; c += 4) {
+        for (int c = c0; c < c0 + cw; c += 4) {
             const float4 u = *(const float4 *)(xp + c);
             const float4 v = *(const float4 *)(xi + c);
             const double e0 = (double)u.x - (double)v.x, e1 = (double)u.y - (double)v.y;
@@ -142,15 +148,16 @@ __device__ __forceinline__ double stage_rows_raw(const float *__restrict__ X, in
             n64 = fma(e3, e3, n64);
         }
     } else {
-#pragma unroll 4
-        for (int c = 0; c < d; ++c) {
-            const double e = (double)xp[c] - (double)xi[c];
-            row[c] = xp[c];
-            n64 = fma(e, e, n64);
+        for (int c = c0; c < c0 + cw; ++c) {
+            if (c < d) {
+                const double e = (double)xp[c] - (double)xi[c];
+                row[c] = xp[c];
+                n64 = fma(e, e, n64);
+            } else {
+                row[c] = 0.0f;
+            }
         }
-        for (int c = d; c < ((d + 3) & ~3); ++c) row[c] = 0.0f;
     }
-    return n64;
 }
 
 // exp(x) for x <= 0 in FP64: additive range reduction x = n ln2 + r,
@@ -468,9 +475,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void pr
 #pragma unroll
     for (int c = 0; c < ELLMAX; ++c) y[c] = (a < k && c < ell) ? Y[p * ell + c] : 0.0f;
 
-    // 1. Gram matrix of the centred rows on FP32 MFMA.
-    stage_rows(X, d, k, xi, p, xs, L.xs_ld, a);
-    lds_sync();
+    // 1. Gram matrix of the centred rows on FP32 MFMA, a chunk of
+    // coordinates at a time.
     constexpr int NT = KMAX / 16;
     f32x4 acc[NT][NT];
 #pragma unroll
@@ -478,21 +484,28 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void pr
 #pragma unroll
         for (int c = 0; c < NT; ++c) acc[r][c] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int fr = a & 15, fk = a >> 4;
-    for (int s = 0; s < d; s += 4) {
-        float f[NT];
+    const int d4 = (d + 3) & ~3, cwmax = stage_chunk(d);
+    for (int c0 = 0; c0 < d4; c0 += cwmax) {
+        const int cw = d4 - c0 < cwmax ? d4 - c0 : cwmax;
+        lds_sync();  // the previous chunk's readers are done
+        stage_rows(X, d, k, xi, p, xs, L.xs_ld, a, c0, cw);
+        lds_sync();
+        for (int s = 0; s < cw; s += 4) {
+            float f[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const int row = t * 16 + fr;
-            f[t] = (row < k) ? xs[row * L.xs_ld + s + fk] : 0.0f;
+            for (int t = 0; t < NT; ++t) {
+                const int row = t * 16 + fr;
+                f[t] = (row < k) ? xs[row * L.xs_ld + s + fk] : 0.0f;
+            }
+            // tiles on and below the diagonal only: G is symmetric
+#pragma unroll
+            for (int r = 0; r < NT; ++r)
+#pragma unroll
+                for (int c = 0; c <= r; ++c)
+                    acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(f[r], f[c], acc[r][c], 0, 0, 0);
         }
-        // tiles on and below the diagonal only: G is symmetric
-#pragma unroll
-        for (int r = 0; r < NT; ++r)
-#pragma unroll
-            for (int c = 0; c <= r; ++c)
-                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(f[r], f[c], acc[r][c], 0, 0, 0);
     }
-    // Transpose through LDS, 32 columns at a time: tile (r, c), lane l holds
+    // Transpose through LDS, 16 columns at a time: tile (r, c), lane l holds
     // rows r*16 + 4*(l/16) + 0..3 of column c*16 + l%16; lane a then reads
     // column a, which is its row.  A tile above the diagonal is the transpose
     // of tile (c, r): its lane l holds column c*16 + 4*(l/16) + 0..3 at row
@@ -500,12 +513,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void pr
     // exactly symmetric).
     float K[KMAX];
 #pragma unroll
-    for (int h = 0; h < NT; h += 2) {
-        lds_sync();  // previous readers (fragments or the other half) are done
+    for (int h = 0; h < NT; ++h) {
+        lds_sync();  // previous readers (fragments or the previous columns) are done
 #pragma unroll
         for (int r = 0; r < NT; ++r)
 #pragma unroll
-            for (int c = h; c < h + 2 && c < NT; ++c) {
+            for (int c = h; c < h + 1; ++c) {
                 if (r >= c) {
                     *(f32x4 *)(G + ((c - h) * 16 + fr) * L.g_ld + r * 16 + 4 * fk) = acc[r][c];
                 } else {
@@ -515,7 +528,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void pr
                 }
             }
         lds_sync();
-        const bool mine = a >= h * 16 && a < (h + 2) * 16 && a < KMAX;
+        const bool mine = a >= h * 16 && a < (h + 1) * 16 && a < KMAX;
         const float *col = G + (a - h * 16) * L.g_ld;
 #pragma unroll
         for (int b = 0; b < KMAX; b += 4) {
@@ -623,7 +636,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void pr
         // lane l holds entries (4g + l/16, l%16), g = 0..3, of a tile, which
         // (K being symmetric) is exactly the A operand of the product for
         // the transposed tile, so K never leaves registers.
-        const int ld = L.xs_ld, d4 = (d + 3) & ~3;
+        const int ld = L.xs_ld;
         float *cb = bc;  // [64][ELLMAX] current coefficients, zero past k / ell
         if (fr < ELLMAX) {
 #pragma unroll
@@ -631,11 +644,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void pr
 #pragma unroll
                 for (int q = 0; q < 4; ++q) cb[(16 * J + 4 * fk + q) * ELLMAX + fr] = Xs[J][q];
         }
-        lds_sync();  // v is read: its space takes the raw rows
         float *xr = (float *)(smem + L.off_r1);
         float *xc = xr + k * ld;
-        nrm64[a] = stage_rows_raw(X, d, k, xi, p, xr, ld, xc, a);
-        lds_sync();
         const double diag64 = P.amp + P.noise;
         const PhiForm<double> pf64 = phi_form<double>(P.kc, P.inv_rho, P.amp);
         // The Gram matrix is symmetric: only its tiles on and below the
@@ -649,22 +659,31 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void pr
         f64x4 G[NL];  // tile (r, c), r >= c, at r (r + 1) / 2 + c
 #pragma unroll
         for (int t = 0; t < NL; ++t) G[t] = f64x4{0.0, 0.0, 0.0, 0.0};
-        for (int s = 0; s < d4; s += 4) {
-            double f[NT];
-            const double cc = (double)xc[s + fk];
+        double n64 = 0.0;  // |x_a - x_i|^2 in FP64, summed over the chunks in order
+        for (int c0 = 0; c0 < d4; c0 += cwmax) {
+            const int cw = d4 - c0 < cwmax ? d4 - c0 : cwmax;
+            lds_sync();  // the previous chunk's readers are done
+            stage_rows_raw(X, d, k, xi, p, xr, ld, xc, a, c0, cw, n64);
+            lds_sync();
+            for (int s = 0; s < cw; s += 4) {
+                double f[NT];
+                const double cc = (double)xc[s + fk];
 #pragma unroll
-            for (int r = 0; r < NT; ++r) {
-                const int row = r * 16 + fr;
-                f[r] = (row < k) ? (double)xr[row * ld + s + fk] - cc : 0.0;
+                for (int r = 0; r < NT; ++r) {
+                    const int row = r * 16 + fr;
+                    f[r] = (row < k) ? (double)xr[row * ld + s + fk] - cc : 0.0;
+                }
+#pragma unroll
+                for (int r = 0; r < NT; ++r)
+#pragma unroll
+                    for (int c = 0; c <= r; ++c)
+                        if (r * 16 < k)
+                            G[r * (r + 1) / 2 + c] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                f[r], f[c], G[r * (r + 1) / 2 + c], 0, 0, 0);
             }
-#pragma unroll
-            for (int r = 0; r < NT; ++r)
-#pragma unroll
-                for (int c = 0; c <= r; ++c)
-                    if (r * 16 < k)
-                        G[r * (r + 1) / 2 + c] =
-                            __builtin_amdgcn_mfma_f64_16x16x4f64(f[r], f[c], G[r * (r + 1) / 2 + c], 0, 0, 0);
         }
+        nrm64[a] = n64;
+        lds_sync();
         // kernel values of the lower tiles, in place: lane l holds entries
         // (r * 16 + 4 q + l / 16, c * 16 + l % 16)
 #pragma unroll
@@ -685,58 +704,59 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void pr
                     T[q] = kab;
                 }
             }
-        lds_sync();  // the raw rows are dead: their space holds the transposes
-        double *tr = (double *)(smem + L.off_r1);  // [NT - 1][16 x 16]
+        double *tr = (double *)(smem + L.off_r1);  // one transposed tile [16 x 16]
         f64x4 R[NT];
 #pragma unroll
         for (int ct = 0; ct < NT; ++ct) {
-            // tiles (r, ct), r < ct: the transposes of the lower tiles (ct, r)
-#pragma unroll
-            for (int r = 0; r < ct; ++r)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) tr[r * 256 + (4 * q + fk) * 16 + fr] = G[ct * (ct + 1) / 2 + r][q];
-            lds_sync();
             f64x4 acc64 = f64x4{0.0, 0.0, 0.0, 0.0};
-            if (ct * 16 < k) {
 #pragma unroll
-                for (int r = 0; r < NT; ++r) {
+            for (int r = 0; r < NT; ++r) {
+                // tile (r, ct) with r < ct: the transpose of the lower tile
+                // (ct, r), through LDS one tile at a time
+                if (r < ct) {
+                    lds_sync();  // the raw rows, or the previous transpose, are read
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) tr[(4 * q + fk) * 16 + fr] = G[ct * (ct + 1) / 2 + r][q];
+                    lds_sync();
+                }
+                if (ct * 16 < k) {
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int row = r * 16 + 4 * q + fk;
-                        const double kab = (r >= ct) ? G[r * (r + 1) / 2 + ct][q]
-                                                     : tr[r * 256 + fr * 16 + 4 * q + fk];
+                        const double kab =
+                            (r >= ct) ? G[r * (r + 1) / 2 + ct][q] : tr[fr * 16 + 4 * q + fk];
                         const double cv = (fr < ell) ? (double)cb[row * ELLMAX + fr] : 0.0;
                         acc64 = __builtin_amdgcn_mfma_f64_16x16x4f64(kab, cv, acc64, 0, 0, 0);
                     }
                 }
             }
             R[ct] = acc64;
-            lds_sync();  // the transposes are read before the next tile's are written
         }
-        // K64 C moves through LDS from the FP64 output layout (rows
-        // 16 ct + 4 q + l / 16) to the FP32 one of the solves (rows
-        // 16 J + 4 (l / 16) + q); the residual takes the neighbour of a row
-        // from that row's lane.
-        lds_sync();  // the transposes are dead; their space takes K64 C
-        double *KC = (double *)(smem + L.off_r1);  // [64][ELLMAX]
-        if (fr < ELLMAX) {
+        // The residual, in FP64 and rounded to FP32, in the FP64 output
+        // layout (rows 16 ct + 4 q + l / 16; the neighbour of a row taken from
+        // that row's lane), moves through LDS to the FP32 layout of the
+        // solves (rows 16 J + 4 (l / 16) + q).
+        lds_sync();  // the last transpose is read; its space takes the residual
+        float *res = (float *)(smem + L.off_r1);  // [64][ELLMAX]
 #pragma unroll
-            for (int ct = 0; ct < NT; ++ct)
+        for (int ct = 0; ct < NT; ++ct)
 #pragma unroll
-                for (int q = 0; q < 4; ++q) KC[(ct * 16 + 4 * q + fk) * ELLMAX + fr] = R[ct][q];
-        }
+            for (int q = 0; q < 4; ++q) {
+                const int row = ct * 16 + 4 * q + fk;
+                const int prow = __shfl((int)p, row);
+                if (fr < ELLMAX)
+                    res[row * ELLMAX + fr] =
+                        (row < k && fr < ell)
+                            ? (float)((double)Y[(int64_t)prow * ell + fr] - R[ct][q])
+                            : 0.0f;
+            }
         lds_sync();
         f32x4 Rs[NT];
 #pragma unroll
         for (int J = 0; J < NT; ++J)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int row = 16 * J + 4 * fk + q;
-                const int prow = __shfl((int)p, row);
-                const bool in = row < k && fr < ell;
-                Rs[J][q] = in ? (float)((double)Y[(int64_t)prow * ell + fr] - KC[row * ELLMAX + fr])
-                              : 0.0f;
-            }
+            for (int q = 0; q < 4; ++q)
+                Rs[J][q] = fr < ELLMAX ? res[(16 * J + 4 * fk + q) * ELLMAX + fr] : 0.0f;
         mfma_forward<NT>(U, k, fr, fk, Rs);
 #pragma unroll
         for (int J = 0; J < NT; ++J)
