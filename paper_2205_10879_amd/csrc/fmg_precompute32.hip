@@ -356,7 +356,8 @@ __device__ __forceinline__ void mfma_forward(const float *__restrict__ U, int k,
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[q], r[I][q], acc, 0, 0, 0);
+                if (16 * I + q < k)  // else every k-index of the step is a zero row
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[q], r[I][q], acc, 0, 0, 0);
         }
         float aop[4];
 #pragma unroll
@@ -369,7 +370,7 @@ __device__ __forceinline__ void mfma_forward(const float *__restrict__ U, int k,
         f32x4 w = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            w = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[q], acc[q], w, 0, 0, 0);
+            if (16 * J + q < k) w = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[q], acc[q], w, 0, 0, 0);
         r[J] = w;
     }
 }
@@ -396,7 +397,8 @@ __device__ __forceinline__ void mfma_backward(const float *__restrict__ U, int k
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[q], r[I][q], acc, 0, 0, 0);
+                if (16 * I + q < k)  // else every k-index of the step is a zero row
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[q], r[I][q], acc, 0, 0, 0);
         }
         float aop[4];
 #pragma unroll
@@ -410,7 +412,7 @@ __device__ __forceinline__ void mfma_backward(const float *__restrict__ U, int k
         f32x4 x = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-            x = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[q], acc[q], x, 0, 0, 0);
+            if (16 * J + q < k) x = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[q], acc[q], x, 0, 0, 0);
         r[J] = x;
     }
 }
@@ -722,6 +724,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void pr
                 if (ct * 16 < k) {
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
+                        // k-step (r, q) covers rows r*16 + 4q .. + 3 of C:
+                        // past k they are zero (uniform skip)
+                        if (r * 16 + 4 * q >= k) continue;
                         const int row = r * 16 + 4 * q + fk;
                         const double kab =
                             (r >= ct) ? G[r * (r + 1) / 2 + ct][q] : tr[fr * 16 + 4 * q + fk];
