@@ -21,11 +21,12 @@
  *   - no call throws; every call returns an fmg_status and, on failure,
  *     leaves a message for fastmuygps_last_error() (thread-local);
  *   - indices are int32, so n <= 2^31 - 1;
- *   - device scratch of a call (candidate pools, orders, staging) comes from
- *     a stream-ordered memory pool of the device that the library creates on
- *     first use; freed scratch stays cached there, up to 16 GiB per device,
- *     until the process ends (larger peaks return to the device at the next
- *     synchronisation, and a failed allocation trims the cache and retries);
+ *   - device scratch of a call (candidate pools, orders, staging) is kept by
+ *     the library when the call ends (up to 16 GiB per device), tagged with
+ *     the call's stream and an event recorded there, and reused by a later
+ *     call that asks for the same size (at once on the same stream, once the
+ *     event has completed on another); a failed allocation returns the
+ *     kept blocks to the device and retries;
  *   - the device arrays of a freed model are kept by the library (up to
  *     16 GiB per device) for later builds of the same sizes; an allocation
  *     that fails returns them to the device first, and
