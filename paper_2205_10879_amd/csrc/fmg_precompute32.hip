@@ -160,6 +160,23 @@ __device__ __forceinline__ void stage_rows_raw(const float *__restrict__ X, int 
     }
 }
 
+// exp(x) for x <= 0 in FP32: x log2(e) = n + f with n an integer and
+// |f| <= 1/2 + 2^-24, the product carried in two parts (its rounded value
+// and, from FMAs, its rounding error plus the tail of log2(e)), so that f is
+// accurate to a few units of 2^-48; then 2^f from the hardware base-2
+// exponential (about 1 ulp on that range) scaled by 2^n.  Results below the
+// smallest normal float may round differently from a correctly rounded exp;
+// the kernel values they stand for are negligible next to the diagonal.
+__device__ __forceinline__ float exp_nonpos32(float x) {
+    const float kL2e = 1.44269502f;          // log2(e) rounded to FP32
+    const float kL2eLo = 1.92596299e-8f;     // log2(e) - kL2e
+    const float th = x * kL2e;
+    const float tl = fmaf(x, kL2eLo, fmaf(x, kL2e, -th));
+    const float n = rintf(th);
+    const float f = (th - n) + tl;
+    return ldexpf(__builtin_amdgcn_exp2f(f), (int)n);
+}
+
 // exp(x) for x <= 0 in FP64: additive range reduction x = n ln2 + r,
 // |r| <= ln2/2 (Cody and Waite, with the product n ln2 taken in two FMAs),
 // then the Taylor series of exp(r) to degree 12 (truncation below 1e-15
@@ -193,7 +210,7 @@ __device__ __forceinline__ double exp_nonpos64(double x) {
 // exp_nonpos64 for the refinement residual.
 __device__ __forceinline__ float phi_arg32(const PhiForm<float> &f, float t) {
     const float s = f.scale * t;
-    return f.amp * fmaf(fmaf(f.c2, s, f.c1), s, 1.0f) * expf(-s);
+    return f.amp * fmaf(fmaf(f.c2, s, f.c1), s, 1.0f) * exp_nonpos32(-s);
 }
 
 __device__ __forceinline__ double phi_arg64(const PhiForm<double> &f, double t) {
@@ -227,6 +244,22 @@ __device__ __forceinline__ void solve_unit_backward(const float *__restrict__ U,
     }
 }
 
+// A pivot is usable when it is positive and finite: its bits, as an
+// unsigned integer, lie in [1, 0x7f7fffff] (a test on the scalar unit, the
+// pivot being uniform).
+__device__ __forceinline__ bool pivot_ok(float piv) {
+    return __builtin_bit_cast(uint32_t, piv) - 1u < 0x7f7fffffu;
+}
+
+// 1/p for a usable pivot: the hardware reciprocal (about 1 ulp) refined by
+// one Newton step whose residual 1 - p r comes from an FMA, which leaves it
+// within an ulp of the quotient (the division sequence that correct
+// rounding takes is seven times as long and runs once per step).
+__device__ __forceinline__ float recip_pivot(float p) {
+    const float r = __builtin_amdgcn_rcpf(p);
+    return fmaf(fmaf(-p, r, 1.0f), r, r);
+}
+
 // Four Cholesky steps j .. j + 3 at once (register window of W columns);
 // the first NY right-hand sides in y take the forward solve along.
 // The panel, columns j .. j + 3 held in K[0..3], is factored with values
@@ -245,11 +278,11 @@ __device__ __forceinline__ void chol_block4(float (&K)[KMAX], float (&y)[ELLMAX]
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         float piv = readlane_f32(K[t], j + t);
-        if (!(piv > 0.0f) || !isfinite(piv)) {
+        if (!pivot_ok(piv)) {
             bad = true;
             piv = 1.0f;
         }
-        const float rp = 1.0f / piv;
+        const float rp = recip_pivot(piv);
         const bool below = a > j + t && a < k;
         u[t] = below ? K[t] * rp : 0.0f;
         if (a == j + t) dinv = rp;
@@ -292,11 +325,11 @@ __device__ __forceinline__ void chol_steps(float (&K)[KMAX], float (&y)[ELLMAX],
     }
     for (; j < j1; ++j) {
         float piv = readlane_f32(K[0], j);
-        if (!(piv > 0.0f) || !isfinite(piv)) {
+        if (!pivot_ok(piv)) {
             bad = true;
             piv = 1.0f;
         }
-        const float rp = 1.0f / piv;
+        const float rp = recip_pivot(piv);
         const bool below = a > j && a < k;
         const float u = below ? K[0] * rp : 0.0f;
         if (a == j) dinv = rp;
@@ -697,6 +730,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void pr
                 const double ncol = nrm64[col];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
+                    if (r * 16 + 4 * q >= k) {  // rows past k (uniform skip)
+                        T[q] = 0.0;
+                        continue;
+                    }
                     const int row = r * 16 + 4 * q + fk;
                     double D = nrm64[row] + ncol - 2.0 * T[q];
                     D = D > 0.0 ? D : 0.0;
