@@ -384,6 +384,16 @@ const char *fastmuygps_version(void);
  * FMG_E_INVALID_ARG (n < 0, null pointers), FMG_E_DEVICE. */
 fmg_status fastmuygps_debug_exp_nonpos(const double *x, double *y, int64_t n, void *stream);
 
+/* Diagnostic, for tests of the arithmetic: y[i] = exp(x[i]) for x[i] <= 0,
+ * evaluated on the device by the FP32 exponential of the FP32 kernel values
+ * (x log2(e) = n + f carried in two parts, 2^f from the hardware base-2
+ * exponential, scaling by 2^n).  Results that are normal floats are within
+ * about two units in the last place; below the smallest normal float they
+ * are within that float of exp(x).  x and y are device pointers [n].
+ * Asynchronous on `stream`.  Errors: FMG_E_INVALID_ARG (n < 0, null
+ * pointers), FMG_E_DEVICE. */
+fmg_status fastmuygps_debug_exp_nonpos32(const float *x, float *y, int64_t n, void *stream);
+
 /* Return the device memory the library keeps cached on the current device
  * (the arrays of freed models and the freed scratch of earlier calls) to the
  * device.  Synchronises the device first; no call may be running on it.

@@ -50,7 +50,7 @@ EXPORTS = ("fastmuygps_build", "fastmuygps_predict", "fastmuygps_info", "fastmuy
            "fastmuygps_server_stats", "fastmuygps_server_reset_stats",
            "fastmuygps_server_destroy", "fastmuygps_release_cached",
            "fastmuygps_predict_noalloc", "fastmuygps_noalloc_scratch_bytes",
-           "fastmuygps_debug_exp_nonpos")
+           "fastmuygps_debug_exp_nonpos", "fastmuygps_debug_exp_nonpos32")
 
 # Largest batch of one fastmuygps_predict_noalloc call (FMG_NOALLOC_MAX_M).
 NOALLOC_MAX_M = 4096
@@ -112,6 +112,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fastmuygps_predict.restype = ctypes.c_int
     lib.fastmuygps_debug_exp_nonpos.argtypes = [P, P, ctypes.c_int64, P]
     lib.fastmuygps_debug_exp_nonpos.restype = ctypes.c_int
+    lib.fastmuygps_debug_exp_nonpos32.argtypes = [P, P, ctypes.c_int64, P]
+    lib.fastmuygps_debug_exp_nonpos32.restype = ctypes.c_int
     lib.fastmuygps_predict_noalloc.argtypes = [P, P, ctypes.c_int64, P, P, P]
     lib.fastmuygps_predict_noalloc.restype = ctypes.c_int
     lib.fastmuygps_noalloc_scratch_bytes.argtypes = []

@@ -703,6 +703,15 @@ fmg_status fastmuygps_debug_exp_nonpos(const double *x, double *y, int64_t n, vo
     return FMG_OK;
 }
 
+fmg_status fastmuygps_debug_exp_nonpos32(const float *x, float *y, int64_t n, void *stream) {
+    g_err.clear();
+    if (n < 0) return fail(FMG_E_INVALID_ARG, "n = %lld < 0", (long long)n);
+    if (n == 0) return FMG_OK;
+    if (!x || !y) return fail(FMG_E_INVALID_ARG, "x and y must not be null");
+    HIPCHK(launch_exp_nonpos32(x, y, n, (hipStream_t)stream), "exp kernel");
+    return FMG_OK;
+}
+
 fmg_status fastmuygps_release_cached(void) {
     g_err.clear();
     int dev = 0;

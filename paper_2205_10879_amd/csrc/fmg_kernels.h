@@ -268,6 +268,7 @@ hipError_t launch_prune_queries(const float *X, int64_t n, const float *Z, int64
 // y[i] = the FP64 exponential of x[i] <= 0 that the refinement's residual
 // evaluates kernel values with (fmg_precompute32.hip).
 hipError_t launch_exp_nonpos64(const double *x, double *y, int64_t n, hipStream_t s);
+hipError_t launch_exp_nonpos32(const float *x, float *y, int64_t n, hipStream_t s);
 
 // *dst += *src
 hipError_t launch_accum(const int32_t *src, unsigned long long *dst, hipStream_t s);

@@ -168,6 +168,9 @@ __device__ __forceinline__ void stage_rows_raw(const float *__restrict__ X, int 
 // smallest normal float may round differently from a correctly rounded exp;
 // the kernel values they stand for are negligible next to the diagonal.
 __device__ __forceinline__ float exp_nonpos32(float x) {
+    // th must be the rounded product: contracting it into th - n would count
+    // its rounding error twice (once there, once in tl)
+#pragma clang fp contract(off)
     const float kL2e = 1.44269502f;          // log2(e) rounded to FP32
     const float kL2eLo = 1.92596299e-8f;     // log2(e) - kL2e
     const float th = x * kL2e;
@@ -854,11 +857,24 @@ __global__ __launch_bounds__(256) void exp_nonpos64_kernel(const double *__restr
     if (i < n) y[i] = exp_nonpos64(x[i]);
 }
 
+__global__ __launch_bounds__(256) void exp_nonpos32_kernel(const float *__restrict__ x,
+                                                           float *__restrict__ y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) y[i] = exp_nonpos32(x[i]);
+}
+
 }  // namespace
 
 hipError_t launch_exp_nonpos64(const double *x, double *y, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(exp_nonpos64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       x, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_exp_nonpos32(const float *x, float *y, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(exp_nonpos32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                        x, y, n);
     return hipGetLastError();
 }
