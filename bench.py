@@ -55,6 +55,11 @@ def main():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the cfg-1 and cfg-2 build and predict lines")
     ap.add_argument("--serve-qps", type=float, default=2.0e6, help="offered queries per second")
+    ap.add_argument("--serve-qps-equal", type=float, default=5.0e5,
+                    help="offered load of the equal-load served runs (both precisions at a "
+                         "rate the plain FP32 path sustains)")
+    ap.add_argument("--serve-seconds-equal", type=float, default=8.0,
+                    help="length of each equal-load served run; 0 skips them")
     ap.add_argument("--no-muygps", action="store_true",
                     help="skip the MuyGPs prediction beside FastMuyGPs")
     ap.add_argument("--no-borehole", action="store_true",
@@ -252,6 +257,23 @@ def main():
             log("served %s: %s" % (prec, result["served"][prec]))
         for prec in result["served"]:
             result["p99_ms_served_" + prec] = result["served"][prec]["p99_ms"]
+
+    # The same comparison at an offered load that both paths sustain, so that
+    # the p99 latencies compare service times rather than a growing backlog.
+    if args.serve_seconds_equal > 0:
+        eq = {"offered_qps": args.serve_qps_equal}
+        for prec in ("mixed", "fp32"):
+            log("equal-load served run (%s): %.0f queries/s offered, %.1f s" % (
+                prec, args.serve_qps_equal, args.serve_seconds_equal))
+            model = fmg.fastmuygps_build(X, Y, w.k, w.kernel, w.nu, w.rho, w.noise,
+                                         precision=prec, stream=stream)
+            eq[prec] = serve_run(fmg, synth, np, torch, model, args.serve_qps_equal,
+                                 args.serve_seconds_equal)
+            model.free()
+            log("equal-load served %s: %s" % (prec, eq[prec]))
+        result["served_equal_load"] = eq
+        for prec in ("mixed", "fp32"):
+            result["p99_ms_equal_load_" + prec] = eq[prec]["p99_ms"]
 
     # Several resident models admitted by HBM budget (multi-model serving).
     cfg5_sample = None
