@@ -72,7 +72,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs the FastMuyGPs path on one GPU only; "
+        print("bench.py: the FastMuyGPs path runs on one GPU only; "
               "--gpus %d is not supported (sharding is described in the design notes)"
               % max(args.gpus, world), file=sys.stderr)
         sys.exit(2)

@@ -50,7 +50,7 @@ typedef enum {
                               positive definite; their C rows are NaN (count in fmg_info) */
     FMG_E_DEVICE = 4,      /* a HIP runtime call failed */
     FMG_E_BUSY = 5,        /* server admission: request queued, not yet admitted */
-    FMG_E_UNSUPPORTED = 6  /* valid request outside what this build implements (e.g. d too
+    FMG_E_UNSUPPORTED = 6  /* valid request outside what the library implements (e.g. d too
                               large for the chosen precision) */
 } fmg_status;
 
