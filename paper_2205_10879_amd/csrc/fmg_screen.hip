@@ -370,13 +370,21 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
         }
     };
     auto load_tile = [&](int col0, char *dst) { load_tile_part(col0, dst, wave * LDI, LDI); };
-    // This lane's fragment offsets inside a tile (row r16 of each 16-row block).
-    int frag_off[KSTEPS];
+    // A lane's fragment offsets inside a tile (row l % 16 of each 16-row
+    // block).  The tile reads form them afresh from a lane index that the
+    // compiler cannot see through: kept live across the scan they were
+    // spilled, and their reload from scratch, coming after the next tile's
+    // LDS-DMA load was issued, made every tile wait for that load.
+    auto frag_offsets = [&](int (&off)[KSTEPS]) __attribute__((always_inline)) {
+        int ln = lane_id();
+        asm volatile("" : "+v"(ln));
+        const int r = ln & 15, gg = ln >> 4;
 #pragma unroll
-    for (int s = 0; s < KSTEPS; ++s) {
-        const int byte = g * KSTEPS * Op::BPS + s * Op::BPS;
-        frag_off[s] = r16 * RB + (((byte >> 4) ^ (r16 & SWZ)) << 4) + (byte & 15);
-    }
+        for (int s = 0; s < KSTEPS; ++s) {
+            const int byte = gg * KSTEPS * Op::BPS + s * Op::BPS;
+            off[s] = r * RB + (((byte >> 4) ^ (r & SWZ)) << 4) + (byte & 15);
+        }
+    };
 
     // Tile pruning.  Every 16 tiles the wave screens their centroid rows
     // (8 MFMAs) and marks a tile skipped when for all of its 64 queries
@@ -520,6 +528,8 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
             // the last period's barrier, which waited for its loads.
             const uint32_t base =
                 (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)cur;
+            int frag_off[KSTEPS];
+            frag_offsets(frag_off);
             uint4 f0, f1, f2, f3, f4, f5, f6, f7;
             asm volatile(
                 "ds_read_b128 %0, %8\n\t"
@@ -555,6 +565,8 @@ __global__ __launch_bounds__(256, FMG_SCREEN_WGS) void screen_kernel(ScreenArgs 
             static_assert(KSTEPS % 4 == 0, "whole 16-byte chunks per lane");
             const uint32_t base =
                 (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) char *)cur;
+            int frag_off[KSTEPS];
+            frag_offsets(frag_off);
             float af[4][KSTEPS];
 #pragma unroll
             for (int q = 0; q < KSTEPS / 4; ++q) {
