@@ -101,7 +101,15 @@ hipError_t scratch_take(void **p, size_t bytes, hipStream_t s) {
         std::lock_guard<std::mutex> lock(c.mu);
         auto range = c.blocks.equal_range(bytes);
         for (auto it = range.first; it != range.second; ++it) {
-            if (it->second.stream == s || hipEventQuery(it->second.ev) == hipSuccess) {
+            bool ready = it->second.stream == s;
+            if (!ready) {
+                const hipError_t q = hipEventQuery(it->second.ev);
+                ready = q == hipSuccess;
+                // "not ready" is an answer, not a failure: keep it from being
+                // reported by the next launch check's hipGetLastError
+                if (q == hipErrorNotReady) (void)hipGetLastError();
+            }
+            if (ready) {
                 *p = it->second.p;
                 c.spare.push_back(it->second.ev);
                 c.bytes -= bytes;
