@@ -50,8 +50,10 @@ typedef enum {
                               positive definite; their C rows are NaN (count in fmg_info) */
     FMG_E_DEVICE = 4,      /* a HIP runtime call failed */
     FMG_E_BUSY = 5,        /* server admission: request queued, not yet admitted */
-    FMG_E_UNSUPPORTED = 6  /* valid request outside what the library implements (e.g. d too
+    FMG_E_UNSUPPORTED = 6, /* valid request outside what the library implements (e.g. d too
                               large for the chosen precision) */
+    FMG_E_IO = 7           /* a model file could not be opened, read or written, or is not
+                              a complete model file of this library's format */
 } fmg_status;
 
 /* Arithmetic of the path.
@@ -367,6 +369,24 @@ void fastmuygps_server_destroy(fmg_server *server);
 
 /* Release the model and all its device memory.  NULL is a no-op. */
 void fastmuygps_free(fmg_model *model);
+
+/* Checkpoint of a built model (the output of Algorithm 2's training loop:
+ * neighbour lists and coefficient rows, with the training rows, responses
+ * and screening structures that prediction reads).
+ * fastmuygps_save writes the model to the file `path` (created or
+ * truncated), after synchronising the device: an 8-byte tag "FMGMODEL", a
+ * format number (1), the model's parameters at their native widths and byte
+ * order, then its arrays.  The model is unchanged.
+ * fastmuygps_load reads such a file onto the current device and returns a
+ * new model in *out (owned by the caller, released with fastmuygps_free),
+ * whose predictions are bitwise identical to those of the saved model; its
+ * prediction fallback count starts at 0.  The file is read with the byte
+ * order of the machine that wrote it.
+ * Errors: FMG_E_INVALID_ARG (null pointers), FMG_E_IO (the file cannot be
+ * opened, read or written; a wrong tag or format; a malformed header; a
+ * truncated file or bytes past its end), FMG_E_OOM, FMG_E_DEVICE. */
+fmg_status fastmuygps_save(const fmg_model *model, const char *path);
+fmg_status fastmuygps_load(const char *path, fmg_model **out);
 
 /* Message of the last failed call on this thread ("" if none).  The string
  * is owned by the library and valid until the next call on this thread. */

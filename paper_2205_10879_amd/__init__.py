@@ -25,6 +25,7 @@ FMG_E_NOT_PD = 3
 FMG_E_DEVICE = 4
 FMG_E_BUSY = 5
 FMG_E_UNSUPPORTED = 6
+FMG_E_IO = 7
 
 PREC_FP64 = 0
 PREC_FP32 = 1
@@ -50,7 +51,8 @@ EXPORTS = ("fastmuygps_build", "fastmuygps_predict", "fastmuygps_info", "fastmuy
            "fastmuygps_server_stats", "fastmuygps_server_reset_stats",
            "fastmuygps_server_destroy", "fastmuygps_release_cached",
            "fastmuygps_predict_noalloc", "fastmuygps_noalloc_scratch_bytes",
-           "fastmuygps_debug_exp_nonpos", "fastmuygps_debug_exp_nonpos32")
+           "fastmuygps_debug_exp_nonpos", "fastmuygps_debug_exp_nonpos32",
+           "fastmuygps_save", "fastmuygps_load")
 
 # Largest batch of one fastmuygps_predict_noalloc call (FMG_NOALLOC_MAX_M).
 NOALLOC_MAX_M = 4096
@@ -114,6 +116,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.fastmuygps_debug_exp_nonpos.restype = ctypes.c_int
     lib.fastmuygps_debug_exp_nonpos32.argtypes = [P, P, ctypes.c_int64, P]
     lib.fastmuygps_debug_exp_nonpos32.restype = ctypes.c_int
+    lib.fastmuygps_save.argtypes = [P, ctypes.c_char_p]
+    lib.fastmuygps_save.restype = ctypes.c_int
+    lib.fastmuygps_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_void_p)]
+    lib.fastmuygps_load.restype = ctypes.c_int
     lib.fastmuygps_predict_noalloc.argtypes = [P, P, ctypes.c_int64, P, P, P]
     lib.fastmuygps_predict_noalloc.restype = ctypes.c_int
     lib.fastmuygps_noalloc_scratch_bytes.argtypes = []
@@ -366,6 +372,10 @@ class Model:
         _check(lib().fastmuygps_info(self.handle, ctypes.byref(inf)))
         return {name: getattr(inf, name) for name, _ in FmgInfo._fields_}
 
+    def save(self, path: str) -> None:
+        """fastmuygps_save: write the model to a file (synchronises the device)."""
+        _check(lib().fastmuygps_save(self.handle, os.fsencode(path)))
+
     def neighbors(self, stream=None) -> torch.Tensor:
         out = torch.empty((self.n, self.k), dtype=torch.int32, device="cuda")
         _check(lib().fastmuygps_neighbors(self.handle, ctypes.c_void_p(out.data_ptr()),
@@ -420,6 +430,20 @@ def fastmuygps_build(X: torch.Tensor, Y: torch.Tensor, k: int, kernel: str = "ma
                                _stream_handle(stream), ctypes.byref(h))
     _check(st, allow=(FMG_E_NOT_PD,) if allow_not_pd else ())
     return Model(h, dtype, d, ell, int(k), n, st)
+
+
+def fastmuygps_load(path: str) -> Model:
+    """fastmuygps_load: a model saved by Model.save, on the current device."""
+    h = ctypes.c_void_p()
+    _check(lib().fastmuygps_load(os.fsencode(path), ctypes.byref(h)))
+    inf = FmgInfo()
+    st = lib().fastmuygps_info(h, ctypes.byref(inf))
+    if st != FMG_OK:
+        lib().fastmuygps_free(h)
+        _check(st)
+    dtype = torch.float64 if inf.precision == PREC_FP64 else torch.float32
+    return Model(h, dtype, inf.d, inf.ell, inf.k, inf.n,
+                 FMG_E_NOT_PD if inf.nonpd_rows > 0 else FMG_OK)
 
 
 def fastmuygps_predict(model: Model, Z: torch.Tensor, out=None, nn_out=None, stream=None):

@@ -640,6 +640,83 @@ fmg_status predict_run(fmg_model *M, const void *Z, int64_t m, void *out, int32_
     return FMG_OK;
 }
 
+// Model files (fastmuygps_save / fastmuygps_load): an 8-byte tag, the
+// format number, the model's parameters field by field at their native
+// widths and byte order, the byte count of every array (0 where the model
+// has none), then the arrays present, in array order.
+constexpr char MODEL_TAG[8] = {'F', 'M', 'G', 'M', 'O', 'D', 'E', 'L'};
+constexpr uint32_t MODEL_FORMAT = 1;
+
+struct FileW {
+    FILE *f;
+    bool ok = true;
+    template <class T>
+    void field(T &v) {
+        if (ok && fwrite(&v, sizeof v, 1, f) != 1) ok = false;
+    }
+    template <class T>
+    void put(const T &v) {
+        T c = v;
+        field(c);
+    }
+    void bytes(const void *p, size_t n) {
+        if (ok && n && fwrite(p, 1, n, f) != n) ok = false;
+    }
+};
+
+struct FileR {
+    FILE *f;
+    bool ok = true;
+    template <class T>
+    void field(T &v) {
+        if (ok && fread(&v, sizeof v, 1, f) != 1) ok = false;
+    }
+    template <class T>
+    void get(T &v) {
+        field(v);
+    }
+    void bytes(void *p, size_t n) {
+        if (ok && n && fread(p, 1, n, f) != n) ok = false;
+    }
+};
+
+// The parameters a prediction needs, in file order (io: FileW or FileR).
+template <class IO>
+void model_fields(fmg_model *M, IO &io) {
+    io.field(M->n);
+    io.field(M->d);
+    io.field(M->ell);
+    io.field(M->k);
+    io.field(M->hyper.kernel);
+    io.field(M->hyper.nu);
+    io.field(M->hyper.length_scale);
+    io.field(M->hyper.noise_var);
+    io.field(M->hyper.amplitude);
+    io.field(M->prec);
+    io.field(M->flags);
+    io.field(M->kc);
+    io.field(M->inv_rho);
+    io.field(M->amp);
+    int32_t self = M->self_inc ? 1 : 0;
+    io.field(self);
+    M->self_inc = self != 0;
+    io.field(M->geom.mode);
+    io.field(M->geom.kp);
+    io.field(M->geom.ksteps);
+    io.field(M->geom.row_bytes);
+    io.field(M->n_pad);
+    io.field(M->e_max);
+    io.field(M->nx_max);
+    io.field(M->acc_coef);
+    io.field(M->c_build);
+    io.field(M->c_query);
+    io.field(M->nonpd);
+    io.field(M->build_fb);
+    int32_t arrays = MA_COUNT;
+    io.field(arrays);
+    if (arrays != MA_COUNT) io.ok = false;
+}
+
 fmg_status model_offload(fmg_model *M, bool idle) {
     if (!M->resident) return FMG_OK;
     if (!idle) HIPCHK(hipDeviceSynchronize(), "sync");
@@ -1490,6 +1567,115 @@ fmg_status fastmuygps_info(const fmg_model *model, fmg_info *info) {
     unsigned long long v = 0;
     HIPCHK(hipMemcpy(&v, model->pred_fb, 8, hipMemcpyDeviceToHost), "copy counter");
     info->predict_fallback_rows = (int64_t)v;
+    return FMG_OK;
+}
+
+fmg_status fastmuygps_save(const fmg_model *model, const char *path) {
+    g_err.clear();
+    if (!model || !path) return fail(FMG_E_INVALID_ARG, "null argument");
+    fmg_model *M = const_cast<fmg_model *>(model);
+    HIPCHK(hipDeviceSynchronize(), "sync");
+    FILE *f = fopen(path, "wb");
+    if (!f) return fail(FMG_E_IO, "cannot open %s for writing", path);
+    FileW w{f};
+    w.bytes(MODEL_TAG, sizeof MODEL_TAG);
+    w.put(MODEL_FORMAT);
+    model_fields(M, w);
+    uint64_t sizes[MA_COUNT];
+    for (int a = 0; a < MA_COUNT; ++a) {
+        const bool present = *model_array(M, a) != nullptr || M->host[a] != nullptr;
+        sizes[a] = present ? (uint64_t)M->arr_bytes[a] : 0;
+        w.put(sizes[a]);
+    }
+    std::vector<char> buf;
+    for (int a = 0; a < MA_COUNT && w.ok; ++a) {
+        if (sizes[a] == 0) continue;
+        const void *src = M->host[a];
+        if (!src) {
+            buf.resize(sizes[a]);
+            const hipError_t e =
+                hipMemcpy(buf.data(), *model_array(M, a), sizes[a], hipMemcpyDeviceToHost);
+            if (e != hipSuccess) {
+                fclose(f);
+                return hip_fail(e, "copy to host");
+            }
+            src = buf.data();
+        }
+        w.bytes(src, sizes[a]);
+    }
+    const bool closed = fclose(f) == 0;
+    if (!w.ok || !closed) return fail(FMG_E_IO, "writing %s failed", path);
+    return FMG_OK;
+}
+
+fmg_status fastmuygps_load(const char *path, fmg_model **out) {
+    g_err.clear();
+    if (!path || !out) return fail(FMG_E_INVALID_ARG, "null argument");
+    *out = nullptr;
+    FILE *f = fopen(path, "rb");
+    if (!f) return fail(FMG_E_IO, "cannot open %s", path);
+    FileR r{f};
+    char tag[sizeof MODEL_TAG];
+    uint32_t format = 0;
+    r.bytes(tag, sizeof tag);
+    r.get(format);
+    if (!r.ok || memcmp(tag, MODEL_TAG, sizeof tag) != 0 || format != MODEL_FORMAT) {
+        fclose(f);
+        return fail(FMG_E_IO, "%s is not a model file of format %u", path, MODEL_FORMAT);
+    }
+    fmg_model *M = new fmg_model();
+    auto bad = [&](fmg_status st) {
+        fclose(f);
+        free_model(M);
+        return st;
+    };
+    (void)hipGetDevice(&M->device);
+    model_fields(M, r);
+    uint64_t sizes[MA_COUNT];
+    for (int a = 0; a < MA_COUNT; ++a) r.get(sizes[a]);
+    const bool shape_ok = M->n >= 1 && M->d >= 1 && M->ell >= 1 && M->ell <= 16 && M->k >= 1 &&
+                          M->k <= 256 && M->k <= M->n && M->n_pad >= 0 &&
+                          (M->prec == FMG_PREC_FP64 || M->prec == FMG_PREC_FP32 ||
+                           M->prec == FMG_PREC_MIXED) &&
+                          kernel_code(M->hyper) == M->kc && sizes[MA_X] > 0 &&
+                          sizes[MA_N] >= (uint64_t)M->n * M->k * 4 && sizes[MA_C] > 0;
+    bool sizes_ok = true;
+    for (int a = 0; a < MA_COUNT; ++a) sizes_ok = sizes_ok && sizes[a] <= (1ull << 40);
+    if (!r.ok || !shape_ok || !sizes_ok) {
+        fail(FMG_E_IO, "%s: malformed model header", path);
+        return bad(FMG_E_IO);
+    }
+    std::vector<char> buf;
+    for (int a = 0; a < MA_COUNT; ++a) {
+        if (sizes[a] == 0) continue;
+        buf.resize(sizes[a]);
+        r.bytes(buf.data(), sizes[a]);
+        if (!r.ok) {
+            fail(FMG_E_IO, "%s is truncated", path);
+            return bad(FMG_E_IO);
+        }
+        void **p = model_array(M, a);
+        const fmg_status st = model_alloc(M, a, p, sizes[a], "model array");
+        if (st != FMG_OK) return bad(st);
+        const hipError_t e = hipMemcpy(*p, buf.data(), sizes[a], hipMemcpyHostToDevice);
+        if (e != hipSuccess) return bad(hip_fail(e, "copy to device"));
+    }
+    if (fgetc(f) != EOF) {
+        fail(FMG_E_IO, "%s has bytes past the last array", path);
+        return bad(FMG_E_IO);
+    }
+    fclose(f);
+    const fmg_status st = model_alloc(M, -1, (void **)&M->pred_fb, 8, "counters");
+    if (st != FMG_OK) {
+        free_model(M);
+        return st;
+    }
+    const hipError_t e = hipMemset(M->pred_fb, 0, 8);
+    if (e != hipSuccess) {
+        free_model(M);
+        return hip_fail(e, "hipMemset");
+    }
+    *out = M;
     return FMG_OK;
 }
 

@@ -182,3 +182,21 @@ def test_noalloc_limit_matches_the_header():
     import paper_2205_10879_amd as fmg
     text = open(HEADER).read()
     assert int(re.search(r"#define FMG_NOALLOC_MAX_M (\d+)", text).group(1)) == fmg.NOALLOC_MAX_M
+
+
+def test_model_files_are_checked_before_any_device_work(lib, tmp_path):
+    import paper_2205_10879_amd as fmg
+    h = ctypes.c_void_p()
+    assert lib.fastmuygps_load(None, ctypes.byref(h)) == fmg.FMG_E_INVALID_ARG
+    assert lib.fastmuygps_save(None, b"/dev/null") == fmg.FMG_E_INVALID_ARG
+    missing = str(tmp_path / "no_such_model.fmg").encode()
+    assert lib.fastmuygps_load(missing, ctypes.byref(h)) == fmg.FMG_E_IO
+    assert not h.value
+    other = tmp_path / "not_a_model.fmg"
+    other.write_bytes(b"NOTMODEL" + bytes(64))
+    assert lib.fastmuygps_load(str(other).encode(), ctypes.byref(h)) == fmg.FMG_E_IO
+    assert b"not a model file" in lib.fastmuygps_last_error()
+    newer = tmp_path / "newer_format.fmg"
+    newer.write_bytes(b"FMGMODEL" + (2).to_bytes(4, "little") + bytes(64))
+    assert lib.fastmuygps_load(str(newer).encode(), ctypes.byref(h)) == fmg.FMG_E_IO
+    assert not h.value
