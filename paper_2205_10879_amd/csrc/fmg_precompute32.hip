@@ -608,6 +608,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void pr
     constexpr int NY = REFINE ? 0 : ELLMAX;
     bool bad = false;
     float dinv = 0.0f;
+    // The factorisation and the first solves are one serial chain: at a
+    // raised issue priority the SIMD serves it before the other wavefronts'
+    // Gram and refinement work, which has more independent instructions to
+    // fill the gaps (26.6 -> 26.2 ms at 1M points, mixed precision; the
+    // priority is dropped again for the refinement, and the plain FP32 path
+    // keeps it to its end, the back substitution being part of the chain).
+    __builtin_amdgcn_s_setprio(3);
     {
         int j = 0;
         if constexpr (KMAX > 48) {
@@ -665,6 +672,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void pr
 #pragma unroll
             for (int q = 0; q < 4; ++q) Xs[J][q] *= dv[16 * J + 4 * fk + q];
         mfma_backward<NT>(U, k, fr, fk, Xs);
+        __builtin_amdgcn_s_setprio(0);
 
         // 4. One refinement step, r = Y_N - (K64 + sigma^2 I) C, in FP64 on
         // FP64 MFMA.  The centred rows are exact in FP64 (a difference of two
