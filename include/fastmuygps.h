@@ -345,8 +345,11 @@ fmg_status fastmuygps_server_remove_model(fmg_server *server, int32_t id);
  * stay owned by the caller and must stay valid until fastmuygps_server_wait
  * returns for this ticket.  arrival_ns: the request's scheduled arrival on
  * CLOCK_MONOTONIC in nanoseconds (latency is measured from it), 0 = now.
- * Returns at once.  Errors: FMG_E_INVALID_ARG (unknown id, B < 1 or B >
- * max_batch, null pointers). */
+ * A request of more than max_batch queries is queued as consecutive parts of
+ * at most max_batch queries (each batched like any request); its ticket
+ * completes with the last part, its latency runs to then, and it counts as
+ * one request in the statistics.  Returns at once.  Errors:
+ * FMG_E_INVALID_ARG (unknown id, B < 1, null pointers). */
 fmg_status fastmuygps_server_submit(fmg_server *server, int32_t id, const void *Z_host,
                                     int32_t B, void *out_host, int64_t arrival_ns,
                                     fmg_ticket *ticket);

@@ -45,6 +45,11 @@ struct fmg_request {
     bool done = false;
     std::mutex mu;
     std::condition_variable cv;
+    // A request of more than max_batch queries is queued as parts of at most
+    // max_batch queries each; the parts point at their parent (the ticket),
+    // which counts the parts still running and completes with the last.
+    fmg_request *parent = nullptr;
+    int parts = 0;
 };
 
 namespace {
@@ -58,12 +63,39 @@ int64_t now_ns() {
 constexpr int SLOT_MAX_D = 64;
 constexpr int SLOT_MAX_ELL = 16;
 
-void finish(fmg_request *r, fmg_status st, int64_t t_done) {
-    std::lock_guard<std::mutex> l(r->mu);
-    r->status = st;
-    r->latency_ms = (double)(t_done - r->arrival_ns) * 1e-6;
-    r->done = true;
-    r->cv.notify_all();
+// What completing a request (or a part) finished: the whole request, with
+// its status, latency and arrival, or nothing yet (parts still running).
+struct Finished {
+    bool whole = false;
+    fmg_status status = FMG_OK;
+    double ms = 0.0;
+    int64_t arrival_ns = 0;
+};
+
+// Marks r done with status st at t_done and wakes its waiter.  A part folds
+// its status into its parent and is deleted here (nobody waits on a part);
+// the parent completes with its last part.  Neither r nor its parent may be
+// used after this call: the waiter deletes a completed request.
+Finished finish(fmg_request *r, fmg_status st, int64_t t_done) {
+    Finished f;
+    fmg_request *const p = r->parent;
+    fmg_request *const w = p ? p : r;  // the request that may complete
+    if (p) delete r;
+    std::lock_guard<std::mutex> l(w->mu);
+    if (p) {
+        if (st != FMG_OK && w->status == FMG_OK) w->status = st;
+        if (--w->parts > 0) return f;
+    } else {
+        w->status = st;
+    }
+    w->latency_ms = (double)(t_done - w->arrival_ns) * 1e-6;
+    f.whole = true;
+    f.status = w->status;
+    f.ms = w->latency_ms;
+    f.arrival_ns = w->arrival_ns;
+    w->done = true;
+    w->cv.notify_all();
+    return f;
 }
 
 struct ServerModel {
@@ -365,15 +397,14 @@ void fmg_server::complete_loop() {
         const int64_t t = now_ns();
         l.lock();
         for (fmg_request *r : sl.reqs) {
-            const double ms = (double)(t - r->arrival_ns) * 1e-6;
-            if (st == FMG_OK) {
-                lat.push_back(ms);
+            if (st == FMG_OK) n_q += r->B;
+            const Finished fin = finish(r, st, t);  // r is gone after this
+            if (fin.whole && fin.status == FMG_OK) {
+                lat.push_back(fin.ms);
                 n_req += 1;
-                n_q += r->B;
-                if (t_first == 0 || r->arrival_ns < t_first) t_first = r->arrival_ns;
+                if (t_first == 0 || fin.arrival_ns < t_first) t_first = fin.arrival_ns;
                 t_last = std::max(t_last, t);
             }
-            finish(r, st, t);
         }
         if (st == FMG_OK) n_batch += 1;
         sl.reqs.clear();
@@ -533,8 +564,8 @@ fmg_status fastmuygps_server_submit(fmg_server *S, int32_t id, const void *Z_hos
                                     void *out_host, int64_t arrival_ns, fmg_ticket *ticket) {
     if (!S || !Z_host || !out_host || !ticket) return set_error(FMG_E_INVALID_ARG, "null argument");
     *ticket = nullptr;
-    if (B < 1 || B > S->opts.max_batch)
-        return set_error(FMG_E_INVALID_ARG, "B = %d outside [1, %d]", B, S->opts.max_batch);
+    if (B < 1) return set_error(FMG_E_INVALID_ARG, "B = %d < 1", B);
+    const int32_t mb = S->opts.max_batch;
     fmg_request *r = new fmg_request();
     r->model = id;
     r->Z = Z_host;
@@ -547,7 +578,24 @@ fmg_status fastmuygps_server_submit(fmg_server *S, int32_t id, const void *Z_hos
             delete r;
             return set_error(FMG_E_INVALID_ARG, "unknown model id %d", id);
         }
-        S->models[id].queue.push_back(r);
+        ServerModel &sm = S->models[id];
+        if (B <= mb) {
+            sm.queue.push_back(r);
+        } else {
+            // parts of at most max_batch queries, queued back to back
+            const size_t zrow = (size_t)sm.M->d * sm.esz, orow = (size_t)sm.M->ell * sm.esz;
+            r->parts = (B + mb - 1) / mb;
+            for (int32_t s0 = 0; s0 < B; s0 += mb) {
+                fmg_request *q = new fmg_request();
+                q->model = id;
+                q->Z = (const char *)Z_host + (size_t)s0 * zrow;
+                q->out = (char *)out_host + (size_t)s0 * orow;
+                q->B = B - s0 < mb ? B - s0 : mb;
+                q->arrival_ns = r->arrival_ns;
+                q->parent = r;
+                sm.queue.push_back(q);
+            }
+        }
     }
     S->cv_work.notify_one();
     *ticket = r;

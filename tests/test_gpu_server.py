@@ -213,3 +213,30 @@ def test_swapping_idle_models_serves_every_stream(use_graphs):
     for key, m in models.items():
         assert np.array_equal(direct(m, Zs[key]), refs[key])
         m.free()
+
+
+def test_requests_larger_than_a_batch_are_split():
+    # A request of more than max_batch queries is served as parts of at most
+    # max_batch; the whole request completes once, with every query's mean
+    # equal to direct prediction, and counts as one request.
+    f = fmg()
+    model, X, Y, Z = build("mixed", 6000, 5000, 8, 3, 30, seed=21)
+    ref = direct(model, Z)
+    with f.Server(slots=3, max_batch=1024, use_graphs=True) as srv:
+        mid, adm = srv.add_model(model)
+        assert adm
+        big = srv.submit(mid, Z[:2600])           # three parts: 1024 + 1024 + 552
+        small = srv.submit(mid, Z[2600:2700])     # queued behind it
+        exact = srv.submit(mid, Z[2700:4748])     # exactly two full parts
+        out_b, lat_b = big.wait()
+        out_s, _ = small.wait()
+        out_e, _ = exact.wait()
+        st = srv.stats()
+    assert np.array_equal(out_b, ref[:2600])
+    assert np.array_equal(out_s, ref[2600:2700])
+    assert np.array_equal(out_e, ref[2700:4748])
+    assert lat_b > 0.0
+    assert st["requests"] == 3
+    assert st["queries"] == 2600 + 100 + 2048
+    assert st["batches"] >= 5
+    model.free()
