@@ -1640,9 +1640,26 @@ fmg_status fastmuygps_load(const char *path, fmg_model **out) {
                           kernel_code(M->hyper) == M->kc && sizes[MA_X] > 0 &&
                           sizes[MA_N] >= (uint64_t)M->n * M->k * 4 && sizes[MA_C] > 0;
     bool sizes_ok = true;
-    for (int a = 0; a < MA_COUNT; ++a) sizes_ok = sizes_ok && sizes[a] <= (1ull << 40);
+    uint64_t body = 0;
+    for (int a = 0; a < MA_COUNT; ++a) {
+        sizes_ok = sizes_ok && sizes[a] <= (1ull << 40);
+        body += sizes[a];
+    }
     if (!r.ok || !shape_ok || !sizes_ok) {
         fail(FMG_E_IO, "%s: malformed model header", path);
+        return bad(FMG_E_IO);
+    }
+    // the arrays must fill the rest of the file exactly (checked before any
+    // allocation, so that a damaged header cannot ask for absurd sizes)
+    const long here = ftell(f);
+    if (here < 0 || fseek(f, 0, SEEK_END) != 0) {
+        fail(FMG_E_IO, "%s: cannot seek", path);
+        return bad(FMG_E_IO);
+    }
+    const long end = ftell(f);
+    if (end < here || (uint64_t)(end - here) != body || fseek(f, here, SEEK_SET) != 0) {
+        fail(FMG_E_IO, "%s holds %lld bytes of arrays where its header names %llu", path,
+             (long long)(end - here), (unsigned long long)body);
         return bad(FMG_E_IO);
     }
     std::vector<char> buf;
