@@ -150,7 +150,12 @@ void scratch_give(void *p, size_t bytes, hipStream_t s) {
         (void)hipFree(p);
         return;
     }
-    (void)hipEventRecord(ev, s);
+    if (hipEventRecord(ev, s) != hipSuccess) {
+        // an event never recorded reads as complete: wait for the stream
+        // instead, so that no other stream takes the block too early
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(s);
+    }
     // over the limit: cached blocks go back to the device, smallest first
     while (!c.blocks.empty() && c.bytes + bytes > SCRATCH_KEEP) {
         auto it = c.blocks.begin();
