@@ -314,14 +314,77 @@ __device__ __forceinline__ void chol_block4(float (&K)[KMAX], float (&y)[ELLMAX]
     for (int b = W - 4; b < W; ++b) K[b] = 0.0f;
 }
 
+// Eight Cholesky steps j .. j + 7 at once, as chol_block4 with a panel of
+// eight columns (K[0..7]): each entry sees exactly the operations of eight
+// single steps in step order, with one LDS round trip and one register shift
+// per eight steps.  bc holds one buffer of 64 rows of two float4 (the space
+// of chol_block4's two buffers), so it is written only after the previous
+// block's readers are done.
+template <int KMAX, int ELLMAX, int NY, int W>
+__device__ __forceinline__ void chol_block8(float (&K)[KMAX], float (&y)[ELLMAX], int j, int k,
+                                            int a, float *__restrict__ U,
+                                            float *__restrict__ bc, float &dinv, bool &bad) {
+    const int arow = a * (a - 1) / 2;
+    float u[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        float piv = readlane_f32(K[t], j + t);
+        if (!pivot_ok(piv)) {
+            bad = true;
+            piv = 1.0f;
+        }
+        const float rp = recip_pivot(piv);
+        const bool below = a > j + t && a < k;
+        u[t] = below ? K[t] * rp : 0.0f;
+        if (a == j + t) dinv = rp;
+        if (below) U[arow + j + t] = u[t];
+#pragma unroll
+        for (int c = 0; c < NY; ++c) y[c] = fmaf(-u[t], readlane_f32(y[c], j + t), y[c]);
+#pragma unroll
+        for (int t2 = t + 1; t2 < 8; ++t2)
+            K[t2] = fmaf(-u[t], readlane_f32(K[t], j + t2), K[t2]);
+    }
+    // Entry b of the buffer (two float4): the panel row of lane j + 8 + b;
+    // positions past the last row are zero.
+    float4 *buf = (float4 *)bc;
+    const int slot = 2 * ((a - j - 8) & 63);
+    const bool pub = a >= j + 8;
+    lds_sync();  // the previous block's readers are done
+    buf[slot] = pub ? make_float4(K[0], K[1], K[2], K[3]) : make_float4(0.f, 0.f, 0.f, 0.f);
+    buf[slot + 1] = pub ? make_float4(K[4], K[5], K[6], K[7]) : make_float4(0.f, 0.f, 0.f, 0.f);
+    lds_sync();
+#pragma unroll
+    for (int b = 8; b < W; ++b) {
+        const float4 v0 = buf[2 * (b - 8)];
+        const float4 v1 = buf[2 * (b - 8) + 1];
+        float x = fmaf(-u[0], v0.x, K[b]);
+        x = fmaf(-u[1], v0.y, x);
+        x = fmaf(-u[2], v0.z, x);
+        x = fmaf(-u[3], v0.w, x);
+        x = fmaf(-u[4], v1.x, x);
+        x = fmaf(-u[5], v1.y, x);
+        x = fmaf(-u[6], v1.z, x);
+        K[b - 8] = fmaf(-u[7], v1.w, x);
+    }
+#pragma unroll
+    for (int b = W - 8; b < W; ++b) K[b] = 0.0f;
+}
+
 // Cholesky steps j in [j0, j1) with a register window of W columns: blocks
-// of four steps, then single steps.
+// of eight steps, then of four, then single steps.
 template <int KMAX, int ELLMAX, int NY, int W>
 __device__ __forceinline__ void chol_steps(float (&K)[KMAX], float (&y)[ELLMAX], int j0, int j1,
                                            int k, int ell, int a, float *__restrict__ U,
                                            float *__restrict__ bc, float &dinv, bool &bad) {
     const int arow = a * (a - 1) / 2;
     int j = j0;
+    if constexpr (W >= 16) {
+        if (j + 8 <= j1) {
+            for (; j + 8 <= j1; j += 8)
+                chol_block8<KMAX, ELLMAX, NY, W>(K, y, j, k, a, U, bc, dinv, bad);
+            lds_sync();  // the last block's readers are done before bc is written again
+        }
+    }
     if (j + 4 <= j1) {
         for (; j + 4 <= j1; j += 4) chol_block4<KMAX, ELLMAX, NY, W>(K, y, j, k, a, U, bc, dinv, bad);
         lds_sync();  // the last block's readers are done before bc is written again
